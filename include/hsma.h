@@ -1,0 +1,140 @@
+/*
+ * hsma.h -- C ABI of the MI355X (gfx950) HSMA hot path.
+ *
+ * Harmonic surface mapping (HSMA) Coulomb solver for N point charges in a
+ * box that is either fully periodic (HSMA3D, Eq. 3 of the paper) or periodic
+ * in x and y with two planar dielectric interfaces at the z faces of the box
+ * (HSMA2D, Eq. 4).  One call computes, for one configuration:
+ *   the electrostatic energy E = 1/2 sum_i q_i Phi_i,
+ *   the potential Phi_i at every particle (own self term excluded, all of its
+ *     periodic / dielectric images included),
+ *   the force F_i = q_i E_i with E_i = -grad Phi at r_i.
+ * The method (Sec. 2.2): the charges and images inside an auxiliary region
+ * are summed directly; the rest is a harmonic series of degree <= p whose
+ * coefficients are fitted by least squares at check points (Eqs. 5-6), then
+ * mapped to charges and dipoles on a sphere of radius R = lambda * half box
+ * diagonal (integrated with a lattice "Fibonacci" rule) and summed at the
+ * particles.  Units: Coulomb constant coulomb_k (1 by default), eps_c = 1.
+ *
+ * Conventions
+ *  - Every buffer belongs to the caller.  Host entry points copy inputs in
+ *    and results out and keep no caller pointer after they return.  Device
+ *    entry points read and write the caller's device buffers asynchronously
+ *    on the given stream; they must stay valid until that work completes.
+ *  - Layouts: positions are n x 3 row-major (x0 y0 z0 x1 ...), FP64;
+ *    charges n FP64; potential n FP64; force n x 3 FP64; energy 1 FP64.
+ *    Any output pointer may be NULL (that output is skipped).
+ *  - A plan is not thread-safe; distinct plans are independent.  No C++
+ *    exception crosses this interface.  On error the call returns a negative
+ *    hsma_status and hsma_last_error() describes it.
+ */
+#ifndef HSMA_H
+#define HSMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSMA_OK = 0,
+  HSMA_ERR_INVALID_ARG = -1,   /* NULL pointer, bad size or parameter          */
+  HSMA_ERR_NOT_NEUTRAL = -2,   /* |sum q| > 1e-12 sum |q|: A_0^0 undetermined  */
+  HSMA_ERR_OUT_OF_DOMAIN = -3, /* slab: a particle z not strictly inside; or a
+                                  non-finite coordinate / charge               */
+  HSMA_ERR_GEOMETRY = -4,      /* sphere radius outside its admissible range   */
+  HSMA_ERR_RANK = -5,          /* fewer fitting rows than unknowns, or the
+                                  fitting matrix is rank deficient             */
+  HSMA_ERR_NO_DEVICE = -6,     /* no usable gfx950 device                      */
+  HSMA_ERR_OOM = -7,           /* device allocation failed / over budget       */
+  HSMA_ERR_DEVICE = -8,        /* a HIP runtime call failed                    */
+  HSMA_ERR_BUSY = -9,          /* server queue full                            */
+  HSMA_ERR_CANCELLED = -10     /* server shut down before the request ran      */
+} hsma_status;
+
+enum { HSMA_GEOM_3D = 0, HSMA_GEOM_2D = 1 };
+enum { HSMA_FP64 = 0, HSMA_FP32C = 1 };
+
+/* Method parameters (cf. the kspace_style arguments of Sec. 3.2).          */
+typedef struct hsma_params {
+  int geometry;        /* HSMA_GEOM_3D or HSMA_GEOM_2D                          */
+  int precision;       /* HSMA_FP64: all sums in FP64.  HSMA_FP32C: pair and
+                          surface sums in FP32 with compensated accumulation;
+                          FP64 in the least-squares solve, the energy reduction
+                          and the close-pair coordinate correction            */
+  double lambda;       /* R = lambda * |L| / 2 (sphere radius over half the
+                          box diagonal); 3D: |L|/2 < R < 1.5 min L;
+                          2D: |L|/2 < R < min(1.5 Lx, 1.5 Ly, (M+1/2) Lz)     */
+  int p;               /* harmonic degree; (p+1)^2 - 1 unknowns (A_0^0 = 0)  */
+  int K;               /* 3D: check-point pairs on opposite faces (2K rows);
+                          2D: x/y face pairs                                  */
+  int F;               /* points on the sphere                                */
+  int Fw;              /* lattice generator of the surface rule (0 = auto)   */
+  int surface_rule;    /* 0: periodised rank-1 (Fibonacci) lattice;
+                          1: Gauss-Legendre x trapezoid (F = 2 n^2)          */
+  int M;               /* 2D: image layers above and below                    */
+  double gamma_up;     /* 2D: (eps_c - eps_up)/(eps_c + eps_up), |gamma| < 1  */
+  double gamma_low;    /* 2D: (eps_c - eps_low)/(eps_c + eps_low)             */
+  int nz;              /* 2D: interface grid points per dimension (DtN rows)  */
+  double coulomb_k;    /* prefactor of q_i q_j / r (default 1)                */
+} hsma_params;
+
+typedef struct hsma_plan hsma_plan;
+
+/* Fills *p with defaults: 3D, FP32C, lambda 1.5, p 10, K 2(p+1)^2, F 800,
+ * Fw 0, rule 0, M 10, gammas 0, nz 80, coulomb_k 1.                        */
+void hsma_params_default(hsma_params* p);
+
+/* Builds the per-geometry plan: check points, sphere quadrature, harmonic
+ * basis, the least-squares pseudo-inverse (host FP64 Householder QR) and
+ * the image tables; uploads them to the current HIP device.
+ * box_lo: lower box corner; box_len: edge lengths (all > 0).  In 2D the
+ * dielectric interfaces are the planes z = box_lo[2] and z = box_lo[2] +
+ * box_len[2].  Errors: INVALID_ARG, GEOMETRY, RANK, NO_DEVICE, OOM, DEVICE. */
+hsma_status hsma_plan_create(const hsma_params* params, const double box_lo[3],
+                             const double box_len[3], hsma_plan** out);
+
+void hsma_plan_destroy(hsma_plan* plan);
+
+/* Host-memory call (synchronous).  Validates the input on the host first:
+ * n >= 1, finite values, neutrality (NOT_NEUTRAL), slab domain
+ * (OUT_OF_DOMAIN).  Positions outside the box are wrapped along periodic
+ * axes.                                                                   */
+hsma_status hsma_compute(hsma_plan* plan, int64_t n, const double* xyz, const double* q,
+                         double* energy, double* potential, double* force);
+
+/* Device-memory call: enqueues the whole step on `stream` (a hipStream_t;
+ * NULL = default stream) and returns without waiting.  Validation runs on
+ * the device; an invalid input makes every requested output NaN and is
+ * reported by the next hsma_plan_device_status() on this plan.             */
+hsma_status hsma_compute_device(hsma_plan* plan, void* stream, int64_t n, const double* d_xyz,
+                                const double* d_q, double* d_energy, double* d_potential,
+                                double* d_force);
+
+/* Waits for the plan's last device call and returns the status that its
+ * device-side validation recorded (OK, NOT_NEUTRAL or OUT_OF_DOMAIN).      */
+hsma_status hsma_plan_device_status(hsma_plan* plan);
+
+/* Per-stage device times (ms) of the last hsma_compute on this plan and
+ * plan facts.  Fields set to -1 when unavailable.                          */
+typedef struct hsma_plan_info {
+  int nb;                /* unknowns (p+1)^2 - 1                                */
+  int n_rows;            /* least-squares rows                                  */
+  int n_check;           /* check targets evaluated per step                    */
+  int n_desc;            /* near-set image descriptors per particle             */
+  double radius;         /* R                                                   */
+  double cond;           /* condition number estimate of the (scaled) fit       */
+  int64_t near_pairs;    /* pair interactions of the last step: particles      */
+  int64_t check_pairs;   /*   check targets                                     */
+  int64_t surface_pairs; /*   sphere sources                                    */
+} hsma_plan_info;
+hsma_status hsma_plan_get_info(const hsma_plan* plan, hsma_plan_info* info);
+
+/* Thread-local description of the last error on this thread.               */
+const char* hsma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSMA_H */

@@ -1,0 +1,10 @@
+"""MI355X (gfx950) HSMA hot path: Python binding of the C-ABI library.
+
+The binding only marshals arguments; every step of the method runs in the
+HIP kernels of libhsma.so.  Importing works without a GPU; plan creation
+needs one (HSMA_ERR_NO_DEVICE otherwise).
+"""
+from .hsma import (  # noqa: F401
+    HSMAError, Params, Plan, HostPlan, lib_path, load_library, solid_harmonics,
+    STATUS, GEOM_3D, GEOM_2D, FP64, FP32C,
+)

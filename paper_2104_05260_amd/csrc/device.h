@@ -1,0 +1,85 @@
+// Device-resident plan and per-step buffers of the HSMA library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "hsma_internal.h"
+
+namespace hsma {
+
+struct DevicePlan {
+  HostPlan host;
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+
+  // tuning of the work decomposition
+  int part_target = 32768;     // waves per particle pair launch (about)
+  int check_target = 4096;     // waves per check pair launch (about)
+  double close_factor = 0.1;   // close-pair radius / typical tile extent (FP32 path)
+
+  // plan constants on the device
+  Desc* d_desc_part = nullptr;
+  Desc* d_desc_check = nullptr;
+  double4* d_check_pos = nullptr;
+  int* d_check_axis = nullptr;
+  Group* d_check_groups = nullptr;
+  int* d_check_tgroup = nullptr;
+  double* d_Praw = nullptr;
+  double* d_SQ = nullptr;
+  double* d_SD = nullptr;
+  double* d_ysurf = nullptr;
+  double* d_nsurf = nullptr;
+  double* d_v = nullptr;
+  double* d_A = nullptr;
+  float4* d_surf32 = nullptr;
+  double4* d_surf64 = nullptr;
+  double* d_qd = nullptr;
+  int* d_status = nullptr;
+  double* d_energy_scratch = nullptr;
+
+  // per-size arena
+  int64_t cap_n = 0, cur_n = -1;
+  size_t part_cap = 0, cpart_cap = 0, work_cap = 0, cwork_cap = 0, group_cap = 0;
+  uint32_t* d_key[2] = {nullptr, nullptr};
+  int* d_val[2] = {nullptr, nullptr};
+  uint32_t* d_hist = nullptr;
+  double4* d_pos_w = nullptr;
+  double4* d_pos64 = nullptr;
+  float4* d_src32 = nullptr;
+  double4* d_src64 = nullptr;
+  double4* d_tile_c = nullptr;
+  float4* d_tile_h = nullptr;
+  int* d_perm = nullptr;
+  double* d_red = nullptr;
+  double* d_epart = nullptr;
+  void* d_part = nullptr;
+  void* d_cpart = nullptr;
+  Group* d_groups = nullptr;
+  Work* d_work = nullptr;
+  Work* d_cwork = nullptr;
+  int2* d_cg_work = nullptr;
+  int ntiles_ = 0, ngroups_ = 0, nwork_ = 0, ncwork_ = 0, nchunks_ = 0, nrsblk_ = 0;
+
+  // host-call staging
+  int64_t stage_cap = 0;
+  double* d_in_xyz = nullptr;
+  double* d_in_q = nullptr;
+  double* d_out_pot = nullptr;
+  double* d_out_force = nullptr;
+  double* d_out_energy = nullptr;
+
+  // last-step facts
+  long long near_pairs = 0, check_pairs = 0, sphere_pairs = 0;
+  hipStream_t last_stream = nullptr;
+
+  hsma_status init(std::string& err);
+  hsma_status prepare(int64_t n, std::string& err);
+  hsma_status run(hipStream_t st, int64_t n, const double* d_xyz, const double* d_q, double* d_energy,
+                  double* d_pot, double* d_force, std::string& err);
+  void free_arena();
+  ~DevicePlan();
+};
+
+}  // namespace hsma

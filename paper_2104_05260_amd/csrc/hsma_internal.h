@@ -1,0 +1,81 @@
+// Internal declarations shared by the plan builder, the device runtime and
+// the C interface of the HSMA library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hsma.h"
+
+namespace hsma {
+
+// Work decomposition of the pair kernels.
+constexpr int kWave = 64;               // wavefront width on CDNA
+constexpr int kTPL = 2;                 // targets per lane
+constexpr int kGroup = kWave * kTPL;    // targets per wave (one "target group")
+constexpr int kTile = 64;               // sources per tile
+
+// One entry of an image table: the source set is every particle mapped by
+//   (x, y, z) -> (x + sx, y + sy, sigma * z + sz)  with charge scaled by `scale`.
+// 32 bytes, read by scalar loads on the device.
+struct Desc {
+  double sx, sy, sz;
+  float sigma, scale;
+};
+static_assert(sizeof(Desc) == 32, "Desc layout");
+
+// A target group: `count` targets starting at `first`, summed over the image
+// table entries [desc_off, desc_off + ndesc).
+struct Group {
+  int first, count, desc_off, ndesc;
+};
+
+// One wave's work: group `group`, flattened (image, tile) range [f0, f1),
+// partial results written to slot `slot`.
+struct Work {
+  int group, f0, f1, slot;
+};
+
+// Host-side FP64 plan: everything that depends on the box and the method
+// parameters but not on the particles.
+struct HostPlan {
+  hsma_params prm{};
+  double lo[3]{}, L[3]{};
+  double R = 0;
+  int nb = 0;                       // unknowns (p+1)^2 - 1
+  int nrows = 0;                    // least-squares rows
+  double cond = 0;
+
+  std::vector<Desc> desc_particles; // near set for particle targets
+  std::vector<Desc> desc_check;     // concatenated tables of the check groups
+
+  // Check targets (box-centred FP64), grouped; each group uses its own
+  // image table.  Outputs per target: value and one field component.
+  std::vector<double> check_pos;    // ncheck * 3
+  std::vector<int> check_axis;      // field component reported per target
+  std::vector<Group> check_groups;
+
+  // A = Praw * v,  v[2t] = value at check target t, v[2t+1] = field
+  // component check_axis[t] at t.  Row-major nb x (2*ncheck).
+  std::vector<double> Praw;
+
+  // Sphere: points, normals, and the maps A -> Q (charges), A -> D
+  // (double-layer strengths), row-major F x nb.
+  std::vector<double> ysurf, nsurf;
+  std::vector<double> SQ, SD;
+};
+
+// Builds the plan; returns HSMA_OK or an error with *msg set.
+hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const double L[3],
+                            HostPlan& out, std::string& msg);
+
+// Real solid harmonics (scaled coordinates xi = r / R): values (nb) and,
+// if grad != nullptr, gradients w.r.t. xi (nb x 3).  Ordering: degree
+// n = 1..p, within a degree m = 0, then (cos, sin) parts for m = 1..n.
+void solid_harmonics(int p, const double xi[3], double* val, double* grad);
+
+// Lattice generator of the surface rule (Fibonacci or best Zaremba index).
+int lattice_generator(int F, int Fw);
+
+}  // namespace hsma

@@ -1,0 +1,235 @@
+"""ctypes binding of include/hsma.h and include/hsma_debug.h.
+
+Argument marshalling only.  The shared library must have been built
+(`python -m paper_2104_05260_amd.build` or `__graft_entry__.build()`);
+there is no fallback: a missing library raises at load time.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhsma.so")
+
+STATUS = {
+    0: "HSMA_OK", -1: "HSMA_ERR_INVALID_ARG", -2: "HSMA_ERR_NOT_NEUTRAL", -3: "HSMA_ERR_OUT_OF_DOMAIN",
+    -4: "HSMA_ERR_GEOMETRY", -5: "HSMA_ERR_RANK", -6: "HSMA_ERR_NO_DEVICE", -7: "HSMA_ERR_OOM",
+    -8: "HSMA_ERR_DEVICE", -9: "HSMA_ERR_BUSY", -10: "HSMA_ERR_CANCELLED",
+}
+GEOM_3D, GEOM_2D = 0, 1
+FP64, FP32C = 0, 1
+
+
+class HSMAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [
+        ("geometry", ctypes.c_int), ("precision", ctypes.c_int), ("lambda_", ctypes.c_double),
+        ("p", ctypes.c_int), ("K", ctypes.c_int), ("F", ctypes.c_int), ("Fw", ctypes.c_int),
+        ("surface_rule", ctypes.c_int), ("M", ctypes.c_int), ("gamma_up", ctypes.c_double),
+        ("gamma_low", ctypes.c_double), ("nz", ctypes.c_int), ("coulomb_k", ctypes.c_double),
+    ]
+
+
+class _CInfo(ctypes.Structure):
+    _fields_ = [
+        ("nb", ctypes.c_int), ("n_rows", ctypes.c_int), ("n_check", ctypes.c_int), ("n_desc", ctypes.c_int),
+        ("radius", ctypes.c_double), ("cond", ctypes.c_double), ("near_pairs", ctypes.c_int64),
+        ("check_pairs", ctypes.c_int64), ("surface_pairs", ctypes.c_int64),
+    ]
+
+
+@dataclass
+class Params:
+    geometry: int = GEOM_3D
+    precision: int = FP32C
+    lam: float = 1.5
+    p: int = 10
+    K: int = 242
+    F: int = 800
+    Fw: int = 0
+    surface_rule: int = 0
+    M: int = 10
+    gamma_up: float = 0.0
+    gamma_low: float = 0.0
+    nz: int = 80
+    coulomb_k: float = 1.0
+
+    @staticmethod
+    def from_workload(w, precision: Optional[int] = None) -> "Params":
+        return Params(geometry=w.geometry, precision=w.precision if precision is None else precision,
+                      lam=w.lam, p=w.p, K=w.K, F=w.F, Fw=w.Fw, surface_rule=w.surface_rule, M=w.M,
+                      gamma_up=w.gamma_up, gamma_low=w.gamma_low, nz=w.nz)
+
+    def _c(self) -> _CParams:
+        return _CParams(self.geometry, self.precision, self.lam, self.p, self.K, self.F, self.Fw,
+                        self.surface_rule, self.M, self.gamma_up, self.gamma_low, self.nz, self.coulomb_k)
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2104_05260_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    d, i64, vp = ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_void_p
+    lib.hsma_params_default.argtypes = [ctypes.POINTER(_CParams)]
+    lib.hsma_plan_create.argtypes = [ctypes.POINTER(_CParams), d, d, ctypes.POINTER(vp)]
+    lib.hsma_plan_destroy.argtypes = [vp]
+    lib.hsma_compute.argtypes = [vp, i64, d, d, d, d, d]
+    lib.hsma_compute_device.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.hsma_plan_device_status.argtypes = [vp]
+    lib.hsma_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
+    lib.hsma_last_error.restype = ctypes.c_char_p
+    lib.hsma_debug_solid_harmonics.argtypes = [ctypes.c_int, d, d, d]
+    lib.hsma_debug_host_plan_create.argtypes = [ctypes.POINTER(_CParams), d, d, ctypes.POINTER(vp)]
+    lib.hsma_debug_host_plan_destroy.argtypes = [vp]
+    lib.hsma_debug_host_plan_get.argtypes = [vp, ctypes.c_char_p, d, i64]
+    lib.hsma_debug_host_plan_get.restype = i64
+    for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_plan_device_status",
+                 "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_debug_host_plan_create"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise HSMAError(st, load_library().hsma_last_error().decode())
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _vec3(v):
+    a = np.ascontiguousarray(v, dtype=np.float64).reshape(3)
+    return a
+
+
+def solid_harmonics(p: int, xi, grad: bool = False):
+    lib = load_library()
+    x = _vec3(xi)
+    nb = (p + 1) ** 2 - 1
+    val = np.zeros(nb)
+    g = np.zeros((nb, 3)) if grad else None
+    _check(lib.hsma_debug_solid_harmonics(p, _dp(x), _dp(val), _dp(g)))
+    return (val, g) if grad else val
+
+
+class HostPlan:
+    """Host-only part of a plan (no GPU needed), for tests."""
+
+    def __init__(self, params: Params, box_lo, box_len):
+        lib = load_library()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        lo, L = _vec3(box_lo), _vec3(box_len)
+        cp = params._c()
+        _check(lib.hsma_debug_host_plan_create(ctypes.byref(cp), _dp(lo), _dp(L), ctypes.byref(self._h)))
+
+    def get(self, name: str) -> np.ndarray:
+        n = self._lib.hsma_debug_host_plan_get(self._h, name.encode(), None, 0)
+        if n < 0:
+            raise KeyError(name)
+        out = np.zeros(n)
+        self._lib.hsma_debug_host_plan_get(self._h, name.encode(), _dp(out), n)
+        return out
+
+    def close(self):
+        if self._h:
+            self._lib.hsma_debug_host_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A device plan for one box and parameter set (hsma_plan_create)."""
+
+    def __init__(self, params: Params, box_lo, box_len):
+        lib = load_library()
+        self._lib = lib
+        self.params = params
+        self._p = ctypes.c_void_p()
+        lo, L = _vec3(box_lo), _vec3(box_len)
+        cp = params._c()
+        _check(lib.hsma_plan_create(ctypes.byref(cp), _dp(lo), _dp(L), ctypes.byref(self._p)))
+
+    def compute(self, xyz, q, energy=True, potential=True, force=True):
+        """Host arrays in, (energy, potential, force) out (hsma_compute)."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        if qq.shape[0] != x.shape[0]:
+            raise ValueError("positions and charges differ in length")
+        n = x.shape[0]
+        e = np.zeros(1) if energy else None
+        pot = np.zeros(n) if potential else None
+        f = np.zeros((n, 3)) if force else None
+        _check(self._lib.hsma_compute(self._p, n, _dp(x), _dp(qq), _dp(e), _dp(pot), _dp(f)))
+        return (float(e[0]) if energy else None), pot, f
+
+    def compute_device(self, xyz, q, energy=None, potential=None, force=None, stream=None):
+        """Device tensors in/out (hsma_compute_device); asynchronous on
+        `stream` (default: torch's current stream).  Arguments are torch
+        tensors of dtype float64 on the plan's device."""
+        import torch
+        n = xyz.shape[0]
+        for t in (xyz, q, energy, potential, force):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError("device arguments must be contiguous float64 GPU tensors")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _check(self._lib.hsma_compute_device(self._p, ctypes.c_void_p(stream), n, ptr(xyz), ptr(q),
+                                             ptr(energy), ptr(potential), ptr(force)))
+
+    def device_status(self) -> int:
+        st = self._lib.hsma_plan_device_status(self._p)
+        return st
+
+    def info(self) -> dict:
+        inf = _CInfo()
+        _check(self._lib.hsma_plan_get_info(self._p, ctypes.byref(inf)))
+        return {f[0]: getattr(inf, f[0]) for f in _CInfo._fields_}
+
+    def close(self):
+        if self._p:
+            self._lib.hsma_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
