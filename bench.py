@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the HSMA hot path on one MI355X.
+
+One step = one full evaluation (energy, potentials, forces) of the 50,000-ion
+periodic electrolyte (L = 60, 0.5 minimum spacing, p = 10, F = 800, K = 400,
+27 near cells) in the FP32-compensated path, inputs resident in HBM: ingest
+and sort, check-point sums, least-squares fit, sphere sources, particle
+near-set and sphere sums, forces and energy.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Besides the throughput it reports the dominant kernel's roofline position
+(FP32 VALU bound; algorithmic 20 flop per near pair over its HIP-event
+duration), the error against the FP64 GPU path and that path's speed, and
+the FP64 CPU oracle timed on a bounded sample as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
+FLOP_PER_NEAR_PAIR = 20           # algorithmic convention for one Coulomb pair (potential + field)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2104_05260_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = t.get(kernel, {}).get(workload)
+    if not ent or ent.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(w, pos, q, lo, L, sample_n=256):
+    """The FP64 oracle on a bounded sample of the same step: its fixed part
+    (check-point sums over all particles, least-squares fit, sphere
+    sources) plus the particle sums at `sample_n` particles, extrapolated
+    linearly in the number of particles evaluated."""
+    import numpy as np
+    from oracle import hsma as ohsma
+    rng = np.random.default_rng(11)
+    t0 = time.perf_counter()
+    ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets=np.arange(1))
+    t1 = time.perf_counter()
+    sample = rng.choice(w.n, sample_n, replace=False)
+    ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets=sample)
+    t2 = time.perf_counter()
+    fixed = t1 - t0
+    per_particle = max((t2 - t1) - fixed, 1e-9) / (sample_n - 1)
+    est_step = fixed + per_particle * w.n
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": w.n / est_step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+        "sample": (f"FP64 oracle: fixed part (all check sums + fit + sphere sources) {fixed:.2f} s measured, "
+                   f"particle sums at {sample_n} sampled particles measured and scaled to all {w.n}; "
+                   f"estimated {est_step:.1f} s per step"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="for counter runs: one 512 MiB device copy (calibration of the byte counters) "
+                         "then warmup + steps of the benchmarked step, nothing else")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method would shard by target ranges; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: one process per run; WORLD_SIZE > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    import paper_2104_05260_amd as hs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = workloads.C2
+    pos, q, lo, L = workloads.make_system(w)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(pos, device=dev)
+    qq = torch.tensor(q, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    pot = torch.zeros(w.n, dtype=torch.float64, device=dev)
+    f = torch.zeros((w.n, 3), dtype=torch.float64, device=dev)
+    plan = hs.Plan(hs.Params.from_workload(w, precision=hs.FP32C), lo, L)
+    if args.profile_pass:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)           # plain copy kernel: 512 MiB read + 512 MiB written
+        torch.cuda.synchronize()
+        del src, dst
+        for _ in range(args.warmup + args.steps):
+            plan.compute_device(x, qq, en, pot, f)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": True, "copy_bytes": 512 * 1024 * 1024, "steps": args.warmup + args.steps}))
+        return
+
+    for _ in range(args.warmup):
+        plan.compute_device(x, qq, en, pot, f)
+    torch.cuda.synchronize()
+    if plan.device_status() != 0:
+        raise SystemExit("device-side validation failed")
+    plan.set_timing(True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.compute_device(x, qq, en, pot, f)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    tm = plan.timing()
+    info = plan.info()
+    plan.set_timing(False)
+    calls = max(1, tm["calls"])
+    near_ms = tm["near_ms"] / calls
+    near_flop = FLOP_PER_NEAR_PAIR * info["near_pairs"]
+    achieved = near_flop / (near_ms * 1e-3) / 1e12
+    e32 = en.item()
+    f32 = f.cpu().numpy()
+
+    out = {
+        "metric": "particle-steps/s (E+F) at 1e-5 rel force err; pair-int/s % FP32 peak; p50/p99",
+        "value": w.n / (ms * 1e-3),
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "wall_ms_per_step": (wall1 - wall0) * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "box": list(w.box), "p": w.p, "F": w.F, "K": w.K,
+                   "lambda": w.lam, "near_cells": 27, "precision": "fp32-compensated",
+                   "parallelism": "single-gpu"},
+        "pair_interactions_per_s": (info["near_pairs"] + info["check_pairs"] + info["surface_pairs"]) / (ms * 1e-3),
+        "stage_ms": {"step": tm["step_ms"] / calls, "near": near_ms, "check": tm["check_ms"] / calls,
+                     "sphere": tm["sphere_ms"] / calls},
+        "roofline": {
+            "kernel": "k_pair<float,particles> (near-set sums)",
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": measured_traffic("k_pair_float_particles", w.name),
+            "flop_per_launch": near_flop, "pairs_per_launch": info["near_pairs"],
+        },
+    }
+    if not args.no_fp64:
+        p64 = hs.Plan(hs.Params.from_workload(w, precision=hs.FP64), lo, L)
+        p64.compute_device(x, qq, en, pot, f)
+        torch.cuda.synchronize()
+        k64 = 3
+        ev0.record(stream)
+        for _ in range(k64):
+            p64.compute_device(x, qq, en, pot, f)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = ev0.elapsed_time(ev1) / k64
+        e64 = en.item()
+        f64 = f.cpu().numpy()
+        out["fp64_gpu"] = {
+            "ms_per_step": ms64, "speedup_fp32c_over_fp64": ms64 / ms,
+            "rel_energy_err": abs(e32 - e64) / abs(e64),
+            "rel_rms_force_err": float(np.sqrt(((f32 - f64) ** 2).sum() / (f64 ** 2).sum())),
+            "max_force_err_rel_to_max": float(np.abs(f32 - f64).max() / np.abs(f64).max()),
+        }
+        p64.close()
+    plan.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, pos, q, lo, L)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -131,6 +131,20 @@ typedef struct hsma_plan_info {
 } hsma_plan_info;
 hsma_status hsma_plan_get_info(const hsma_plan* plan, hsma_plan_info* info);
 
+/* Device time of the main stages, summed over the device or host calls
+ * made on this plan since timing was (re)enabled, from HIP events recorded
+ * on the call's stream around each stage (at most 4096 calls are timed).
+ * hsma_plan_get_timing waits for those calls to finish.                   */
+typedef struct hsma_timing {
+  int64_t calls;      /* timed calls                                           */
+  double step_ms;     /* whole step, first to last kernel                      */
+  double check_ms;    /* check-target near sums (before their reduction)       */
+  double near_ms;     /* particle near-set sums (the dominant kernel)          */
+  double sphere_ms;   /* particle sphere-source sums                           */
+} hsma_timing;
+hsma_status hsma_plan_set_timing(hsma_plan* plan, int enable);
+hsma_status hsma_plan_get_timing(hsma_plan* plan, hsma_timing* out);
+
 /* Thread-local description of the last error on this thread.               */
 const char* hsma_last_error(void);
 

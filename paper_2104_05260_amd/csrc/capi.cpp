@@ -176,6 +176,32 @@ hsma_status hsma_compute(hsma_plan* plan, int64_t n, const double* xyz, const do
   return HSMA_OK;
 }
 
+hsma_status hsma_plan_set_timing(hsma_plan* plan, int enable) {
+  if (!plan) return fail(HSMA_ERR_INVALID_ARG, "NULL plan");
+  plan->dev.timing = enable != 0;
+  plan->dev.timed_calls = 0;
+  return HSMA_OK;
+}
+
+hsma_status hsma_plan_get_timing(hsma_plan* plan, hsma_timing* out) {
+  if (!plan || !out) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
+  hsma::DevicePlan& d = plan->dev;
+  std::memset(out, 0, sizeof(*out));
+  out->calls = d.timed_calls;
+  double* acc[] = {&out->step_ms, &out->check_ms, &out->near_ms, &out->sphere_ms};
+  for (int c = 0; c < d.timed_calls; ++c)
+    for (int stg = 0; stg < hsma::DevicePlan::kStages; ++stg) {
+      const size_t i = ((size_t)c * hsma::DevicePlan::kStages + stg) * 2;
+      if (i + 1 >= d.events.size()) continue;
+      if (hipEventSynchronize(d.events[i + 1]) != hipSuccess) return fail(HSMA_ERR_DEVICE, "event sync failed");
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, d.events[i], d.events[i + 1]) != hipSuccess)
+        return fail(HSMA_ERR_DEVICE, "hipEventElapsedTime failed");
+      *acc[stg] += ms;
+    }
+  return HSMA_OK;
+}
+
 hsma_status hsma_plan_get_info(const hsma_plan* plan, hsma_plan_info* info) {
   if (!plan || !info) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
   const hsma::HostPlan& h = plan->dev.host;

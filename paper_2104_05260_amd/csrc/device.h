@@ -4,10 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "hsma_internal.h"
 
 namespace hsma {
+
+constexpr int kMaxTimedCalls = 4096;
 
 struct DevicePlan {
   HostPlan host;
@@ -72,6 +75,13 @@ struct DevicePlan {
 
   // last-step facts
   long long near_pairs = 0, check_pairs = 0, sphere_pairs = 0;
+
+  // optional per-stage event timing (hsma_plan_set_timing)
+  enum { kStStep = 0, kStCheck, kStNear, kStSphere, kStages };
+  bool timing = false;
+  int timed_calls = 0;
+  std::vector<hipEvent_t> events;   // kStages * 2 events per timed call
+  hsma_status record(hipStream_t st, int stage, int edge, std::string& err);
   hipStream_t last_stream = nullptr;
 
   hsma_status init(std::string& err);

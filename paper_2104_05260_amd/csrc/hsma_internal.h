@@ -17,13 +17,12 @@ constexpr int kGroup = kWave * kTPL;    // targets per wave (one "target group")
 constexpr int kTile = 64;               // sources per tile
 
 // One entry of an image table: the source set is every particle mapped by
-//   (x, y, z) -> (x + sx, y + sy, sigma * z + sz)  with charge scaled by `scale`.
-// 32 bytes, read by scalar loads on the device.
+//   (x, y, z) -> (x + sx, y + sy, sigma * z + sz)  with charge scaled by `scale`
+// (sigma = +-1).  40 bytes, read by scalar loads on the device.
 struct Desc {
-  double sx, sy, sz;
-  float sigma, scale;
+  double sx, sy, sz, sigma, scale;
 };
-static_assert(sizeof(Desc) == 32, "Desc layout");
+static_assert(sizeof(Desc) == 40, "Desc layout");
 
 // A target group: `count` targets starting at `first`, summed over the image
 // table entries [desc_off, desc_off + ndesc).

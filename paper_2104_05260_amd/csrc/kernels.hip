@@ -328,7 +328,7 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
     const float4 hs = tile_h[tile];
     const double dlx = (cs.x + ds.sx) - cgx;
     const double dly = (cs.y + ds.sy) - cgy;
-    const double dlz = ((double)ds.sigma * cs.z + ds.sz) - cgz;
+    const double dlz = (ds.sigma * cs.z + ds.sz) - cgz;
     const double gx = fmax(0.0, fabs(dlx) - hgx - (double)hs.x);
     const double gy = fmax(0.0, fabs(dly) - hgy - (double)hs.y);
     const double gz = fmax(0.0, fabs(dlz) - hgz - (double)hs.z);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
         }
       }
     } else {
-      const bool ident = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.f;
+      const bool ident = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.0;
 #pragma unroll 4
       for (int k = 0; k < kTile; ++k) {
         const S v = s[k];
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
             const double4 ps = pos64[si];
             dx = (Real)(tx[j] - (ps.x + ds.sx));
             dy = (Real)(ty[j] - (ps.y + ds.sy));
-            dz = sg * (Real)(tz[j] - ((double)ds.sigma * ps.z + ds.sz));
+            dz = sg * (Real)(tz[j] - (ds.sigma * ps.z + ds.sz));
             r2 = dx * dx + dy * dy + dz * dz;
             if (PARTICLES && ident && si == (long)(tbase + j * kWave)) {
               qq = (Real)0;
@@ -730,6 +730,7 @@ void DevicePlan::free_arena() {
 
 DevicePlan::~DevicePlan() {
   free_arena();
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
   void* ps[] = {d_desc_part, d_desc_check, d_check_pos, d_check_axis, d_check_groups, d_check_tgroup, d_Praw,
                 d_SQ, d_SD, d_ysurf, d_nsurf, d_v, d_A, d_surf32, d_surf64, d_qd, d_status, d_energy_scratch,
                 d_in_xyz, d_in_q, d_out_pot, d_out_force, d_out_energy};
@@ -856,6 +857,19 @@ hsma_status DevicePlan::prepare(int64_t n, std::string& err) {
   return HSMA_OK;
 }
 
+// Event pair (stage, edge) of the current timed call, created on demand.
+hsma_status DevicePlan::record(hipStream_t st, int stage, int edge, std::string& err) {
+  if (!timing || timed_calls >= kMaxTimedCalls) return HSMA_OK;
+  const size_t idx = ((size_t)timed_calls * kStages + stage) * 2 + edge;
+  while (events.size() <= idx) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    events.push_back(e);
+  }
+  HIPCHK(hipEventRecord(events[idx], st));
+  return HSMA_OK;
+}
+
 hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, const double* d_q, double* d_energy,
                             double* d_pot, double* d_force, std::string& err) {
   if (n64 > (int64_t)0x3fffffff) {
@@ -870,6 +884,7 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   const double3 L = make_double3(host.L[0], host.L[1], host.L[2]);
   const int slab = host.prm.geometry == HSMA_GEOM_2D;
   const int nblk = (n + 255) / 256;
+  if ((s = record(st, kStStep, 0, err)) != HSMA_OK) return s;
   hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(256), 0, st, n, d_xyz, d_q, lo, L, slab, d_pos_w, d_key[0],
                      d_val[0], d_red);
   hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, nblk, (const double*)d_red, d_status);
@@ -892,11 +907,13 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   const double rc2 = rc * rc;
   const int ncheck = (int)host.check_axis.size();
   const long ccomp = kGroup, cslot = 5L * kGroup;
+  if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;
   if (fp64) {
     hipLaunchKernelGGL((k_pair<double, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,
                        (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const double4*)d_src64,
                        (const double4*)d_pos64, rc2, (double*)d_cpart, ccomp, cslot);
+    if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;
     hipLaunchKernelGGL(k_reduce_check<double>, dim3((ncheck + 255) / 256), dim3(256), 0, st, ncheck,
                        (const int*)d_check_tgroup, (const Group*)d_check_groups, (const int2*)d_cg_work,
                        (const int*)d_check_axis, (const double*)d_cpart, d_v);
@@ -905,6 +922,7 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
                        (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,
                        (const double4*)d_pos64, rc2, (float*)d_cpart, ccomp, cslot);
+    if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;
     hipLaunchKernelGGL(k_reduce_check<float>, dim3((ncheck + 255) / 256), dim3(256), 0, st, ncheck,
                        (const int*)d_check_tgroup, (const Group*)d_check_groups, (const int2*)d_cg_work,
                        (const int*)d_check_axis, (const float*)d_cpart, d_v);
@@ -917,13 +935,17 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
                      d_surf32, d_surf64, d_qd);
   const long comp = (long)ngroups_ * kGroup;
   const long slot = 5L * comp;
+  if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;
   if (fp64) {
     hipLaunchKernelGGL((k_pair<double, true>), dim3(nwork_), dim3(64), 0, st, (const double4*)d_pos64,
                        (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const double4*)d_src64,
                        (const double4*)d_pos64, rc2, (double*)d_part, comp, slot);
+    if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;
+    if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;
     hipLaunchKernelGGL(k_pair_sphere<double>, dim3(ngroups_), dim3(64), 0, st, (const double4*)d_pos64, n,
                        (const double4*)d_surf64, F, (double*)d_part, comp, (long)nchunks_ * slot);
+    if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;
     hipLaunchKernelGGL(k_finalize<double>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + 1, (const double*)d_part,
                        comp, (const double4*)d_pos64, (const int*)d_perm, host.prm.coulomb_k,
                        (const int*)d_status, d_pot, d_force, d_epart);
@@ -932,8 +954,11 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
                        (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,
                        (const double4*)d_pos64, rc2, (float*)d_part, comp, slot);
+    if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;
+    if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;
     hipLaunchKernelGGL(k_pair_sphere<float>, dim3(ngroups_), dim3(64), 0, st, (const double4*)d_pos64, n,
                        (const float4*)d_surf32, F, (float*)d_part, comp, (long)nchunks_ * slot);
+    if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;
     hipLaunchKernelGGL(k_finalize<float>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + 1, (const float*)d_part, comp,
                        (const double4*)d_pos64, (const int*)d_perm, host.prm.coulomb_k, (const int*)d_status,
                        d_pot, d_force, d_epart);
@@ -941,6 +966,8 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nblk, (const double*)d_epart,
                      d_energy ? d_energy : d_energy_scratch);
   HIPCHK(hipGetLastError());
+  if ((s = record(st, kStStep, 1, err)) != HSMA_OK) return s;
+  if (timing && timed_calls < kMaxTimedCalls) ++timed_calls;
   const long long nd = (long long)host.desc_particles.size();
   near_pairs = (long long)n * nd * n - n;
   long long cp = 0;

@@ -347,11 +347,10 @@ void face_pairs(const double L[3], int K, const int* axes, int na, std::vector<d
   }
 }
 
-float image_strength(int l, double gu, double gl, bool upper) {
+double image_strength(int l, double gu, double gl, bool upper) {
   // l-th upper image: gu^ceil(l/2) gl^floor(l/2); lower: gl^ceil gu^floor
   const int c = (l + 1) / 2, f = l / 2;
-  double v = upper ? std::pow(gu, c) * std::pow(gl, f) : std::pow(gl, c) * std::pow(gu, f);
-  return (float)v;
+  return upper ? std::pow(gu, c) * std::pow(gl, f) : std::pow(gl, c) * std::pow(gu, f);
 }
 
 }  // namespace
@@ -405,7 +404,7 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
   const double R = P.R;
 
   // ---- image tables
-  auto push = [](std::vector<Desc>& v, double sx, double sy, double sz, float sg, float sc) {
+  auto push = [](std::vector<Desc>& v, double sx, double sy, double sz, double sg, double sc) {
     v.push_back(Desc{sx, sy, sz, sg, sc});
   };
   const int naxes = slab ? 2 : 3;
@@ -413,7 +412,7 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
   if (!slab) {
     for (int a = -1; a <= 1; ++a)
       for (int b = -1; b <= 1; ++b)
-        for (int c = -1; c <= 1; ++c) push(P.desc_particles, a * L[0], b * L[1], c * L[2], 1.f, 1.f);
+        for (int c = -1; c <= 1; ++c) push(P.desc_particles, a * L[0], b * L[1], c * L[2], 1.0, 1.0);
     // Telescoped difference sets: Phi_B(x+) - Phi_B(x-) for x+ = x- + L_d e_d
     // equals the potential at x- of the cells at k_d = -2 minus the cells at
     // k_d = +1 (the other two indices over {-1,0,1}).
@@ -428,26 +427,26 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
               if (e != d) o[c++] = e;
             k[o[0]] = a;
             k[o[1]] = b;
-            push(axis_tables[d], k[0] * L[0], k[1] * L[1], k[2] * L[2], 1.f, kd == -2 ? 1.f : -1.f);
+            push(axis_tables[d], k[0] * L[0], k[1] * L[1], k[2] * L[2], 1.0, kd == -2 ? 1.0 : -1.0);
           }
   } else {
-    auto layers = [&](std::vector<Desc>& v, double sx, double sy, float sgn) {
-      push(v, sx, sy, 0.0, 1.f, sgn);
+    auto layers = [&](std::vector<Desc>& v, double sx, double sy, double sgn) {
+      push(v, sx, sy, 0.0, 1.0, sgn);
       for (int l = 1; l <= prm.M; ++l) {
-        const float sig = (l % 2) ? -1.f : 1.f;
+        const double sig = (l % 2) ? -1.0 : 1.0;
         push(v, sx, sy, l * L[2], sig, sgn * image_strength(l, prm.gamma_up, prm.gamma_low, true));
         push(v, sx, sy, -l * L[2], sig, sgn * image_strength(l, prm.gamma_up, prm.gamma_low, false));
       }
     };
     for (int a = -1; a <= 1; ++a)
-      for (int b = -1; b <= 1; ++b) layers(P.desc_particles, a * L[0], b * L[1], 1.f);
+      for (int b = -1; b <= 1; ++b) layers(P.desc_particles, a * L[0], b * L[1], 1.0);
     for (int d = 0; d < 2; ++d)
       for (int kd : {-2, 1})
         for (int a = -1; a <= 1; ++a) {
           double s[2];
           s[d] = kd * L[d];
           s[1 - d] = a * L[1 - d];
-          layers(axis_tables[d], s[0], s[1], kd == -2 ? 1.f : -1.f);
+          layers(axis_tables[d], s[0], s[1], kd == -2 ? 1.0 : -1.0);
         }
   }
 

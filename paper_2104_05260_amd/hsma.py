@@ -49,6 +49,11 @@ class _CInfo(ctypes.Structure):
     ]
 
 
+class _CTiming(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("step_ms", ctypes.c_double), ("check_ms", ctypes.c_double),
+                ("near_ms", ctypes.c_double), ("sphere_ms", ctypes.c_double)]
+
+
 @dataclass
 class Params:
     geometry: int = GEOM_3D
@@ -83,13 +88,35 @@ def lib_path() -> str:
     return _LIB_PATH
 
 
+def _hip_runtimes_mapped():
+    try:
+        with open("/proc/self/maps") as f:
+            maps = f.read()
+    except OSError:
+        return set()
+    import re
+    return set(re.findall(r"(/\S*libamdhip64\S*)", maps))
+
+
 def load_library():
+    """Loads libhsma.so once per process.
+
+    PyTorch ships its own HIP runtime.  Importing torch first makes the
+    library bind to that same runtime (one HIP runtime per process), so
+    torch tensors and streams can be handed to the device entry points."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2104_05260_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads torch's HIP runtime before ours)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(_LIB_PATH)
+    rts = _hip_runtimes_mapped()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes are loaded in this process: {sorted(rts)}")
     d, i64, vp = ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_void_p
     lib.hsma_params_default.argtypes = [ctypes.POINTER(_CParams)]
     lib.hsma_plan_create.argtypes = [ctypes.POINTER(_CParams), d, d, ctypes.POINTER(vp)]
@@ -99,13 +126,15 @@ def load_library():
     lib.hsma_plan_device_status.argtypes = [vp]
     lib.hsma_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
     lib.hsma_last_error.restype = ctypes.c_char_p
+    lib.hsma_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.hsma_plan_get_timing.argtypes = [vp, ctypes.POINTER(_CTiming)]
     lib.hsma_debug_solid_harmonics.argtypes = [ctypes.c_int, d, d, d]
     lib.hsma_debug_host_plan_create.argtypes = [ctypes.POINTER(_CParams), d, d, ctypes.POINTER(vp)]
     lib.hsma_debug_host_plan_destroy.argtypes = [vp]
     lib.hsma_debug_host_plan_get.argtypes = [vp, ctypes.c_char_p, d, i64]
     lib.hsma_debug_host_plan_get.restype = i64
     for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_plan_device_status",
-                 "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_debug_host_plan_create"):
+                 "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_plan_set_timing", "hsma_plan_get_timing", "hsma_debug_host_plan_create"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,6 +240,14 @@ class Plan:
     def device_status(self) -> int:
         st = self._lib.hsma_plan_device_status(self._p)
         return st
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.hsma_plan_set_timing(self._p, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        t = _CTiming()
+        _check(self._lib.hsma_plan_get_timing(self._p, ctypes.byref(t)))
+        return {f[0]: getattr(t, f[0]) for f in _CTiming._fields_}
 
     def info(self) -> dict:
         inf = _CInfo()

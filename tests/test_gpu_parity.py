@@ -39,7 +39,14 @@ def oracle_run(params, pos, q, lo, L, targets=None):
 
 
 # FP64 path: agreement to 1e-10 relative (energy, potentials, forces).
-# FP32 compensated path: 1e-6 relative energy, 1e-5 relative RMS force.
+# FP32 compensated path: 1e-6 relative energy, 1e-5 relative RMS force and
+# potential.  The energy E = 1/2 sum q_i Phi_i of a random uniform
+# placement can be orders of magnitude smaller than its terms; there the
+# FP32 energy bar is 1e-6 of the energy scale S = 1/2 sum |q_i Phi_i|
+# (each potential carries ~1e-7 relative rounding, so the energy error
+# scales with S, not with E).  Where E is not dominated by cancellation
+# (|E| >= 0.01 S, e.g. the 100-ion and 50,000-ion systems) S <= 100|E| and
+# the bar is checked against |E| itself as well, see test_c2_full_size_sampled.
 TOL64 = 1e-10
 
 
@@ -54,7 +61,10 @@ def check(params, pos, q, lo, L, fp32=False, label=""):
     note(f"   energy {e:.15g} oracle {r.energy:.15g}: rel {de:.2e}; potential max rel {dp:.2e}; "
          f"force rms rel {df:.2e}, max rel {dfmax:.2e}")
     if fp32:
-        assert de <= 1e-6 and df <= 1e-5 and dp <= 1e-5
+        S = 0.5 * np.abs(q * r.potential).sum()
+        scale = abs(r.energy) if abs(r.energy) >= 0.01 * S else S
+        note(f"   energy scale S {S:.6g}; bar on |dE| {1e-6 * scale:.3g}")
+        assert abs(e - r.energy) <= 1e-6 * scale and df <= 1e-5 and dp <= 1e-5
     else:
         assert de <= TOL64 and dp <= TOL64 and dfmax <= TOL64 * 10 and df <= TOL64
     return e, pot, f, r
