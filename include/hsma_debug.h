@@ -24,6 +24,10 @@ typedef struct hsma_host_plan hsma_host_plan;
  * of Eq. 5).  val: (p+1)^2-1 values; grad (optional): 3 per value, w.r.t. xi. */
 hsma_status hsma_debug_solid_harmonics(int p, const double xi[3], double* val, double* grad);
 
+/* Sort key of cell (x, y, z) of the 1024^3 grid (10 bits per axis) that
+ * orders the particles each step: the position along a 3D Hilbert curve.  */
+uint32_t hsma_debug_hilbert_key(uint32_t x, uint32_t y, uint32_t z);
+
 /* Builds only the host part of a plan.  Same parameter checks and errors as
  * hsma_plan_create except that no device is used.                         */
 hsma_status hsma_debug_host_plan_create(const hsma_params* params, const double box_lo[3],

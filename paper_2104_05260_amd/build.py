@@ -17,10 +17,10 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra=()) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", *FLAGS, "-x", "hip", *srcs, "-o", tmp]
+    cmd = ["hipcc", *FLAGS, *extra, "-x", "hip", *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

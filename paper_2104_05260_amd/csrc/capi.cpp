@@ -226,7 +226,13 @@ struct hsma_host_plan {
   hsma::HostPlan h;
 };
 
+namespace hsma {
+uint32_t hilbert_key_host(uint32_t x, uint32_t y, uint32_t z);
+}
+
 extern "C" {
+
+uint32_t hsma_debug_hilbert_key(uint32_t x, uint32_t y, uint32_t z) { return hsma::hilbert_key_host(x, y, z); }
 
 hsma_status hsma_debug_solid_harmonics(int p, const double xi[3], double* val, double* grad) {
   if (p < 1 || p > 24 || !xi || !val) return fail(HSMA_ERR_INVALID_ARG, "bad argument");

@@ -19,7 +19,7 @@ struct DevicePlan {
 
   // tuning of the work decomposition
   int part_target = 32768;     // waves per particle pair launch (about)
-  int check_target = 4096;     // waves per check pair launch (about)
+  int check_target = 2048;     // waves per check pair launch (about)
   double close_factor = 0.1;   // close-pair radius / typical tile extent (FP32 path)
 
   // plan constants on the device
@@ -63,7 +63,8 @@ struct DevicePlan {
   Work* d_work = nullptr;
   Work* d_cwork = nullptr;
   int2* d_cg_work = nullptr;
-  int ntiles_ = 0, ngroups_ = 0, nwork_ = 0, ncwork_ = 0, nchunks_ = 0, nrsblk_ = 0;
+  int ntiles_ = 0, ngroups_ = 0, nwork_ = 0, nnear_ = 0, ncwork_ = 0, ncnear_ = 0, nchunks_ = 0, nsphere_ = 0,
+      nrsblk_ = 0;
 
   // host-call staging
   int64_t stage_cap = 0;

@@ -12,7 +12,10 @@ namespace hsma {
 
 // Work decomposition of the pair kernels.
 constexpr int kWave = 64;               // wavefront width on CDNA
-constexpr int kTPL = 2;                 // targets per lane
+#ifndef HSMA_TPL
+#define HSMA_TPL 1
+#endif
+constexpr int kTPL = HSMA_TPL;          // targets per lane
 constexpr int kGroup = kWave * kTPL;    // targets per wave (one "target group")
 constexpr int kTile = 64;               // sources per tile
 

@@ -47,17 +47,44 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
+// Position of cell (x, y, z) (10 bits each) along a 3D Hilbert curve,
+// following Skilling's transpose formulation (AIP Conf. Proc. 707, 2004):
+// undo the excess rotations and reflections level by level, Gray-encode,
+// then interleave the three transposed words.  Consecutive keys are
+// face-adjacent cells, so runs of sorted particles stay spatially compact.
+__host__ __device__ inline uint32_t hilbert_key3(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t X[3] = {x & 1023u, y & 1023u, z & 1023u};
+  const uint32_t M = 1u << 9;
+  for (uint32_t Q = M; Q > 1; Q >>= 1) {
+    const uint32_t P = Q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t Q = M; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  uint32_t key = 0;
+  for (int b = 9; b >= 0; --b)
+    key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+  return key;
 }
 
+uint32_t hilbert_key_host(uint32_t x, uint32_t y, uint32_t z) { return hilbert_key3(x, y, z); }
+
 // ----------------------------------------------------------------- ingest
-// Centred, wrapped FP64 positions + charge; 30-bit Morton key of a 1024^3
+// Centred, wrapped FP64 positions + charge; 30-bit Hilbert key of a 1024^3
 // cell grid; per-block partial sums (sum q, sum |q|, invalid count).
 __global__ __launch_bounds__(256) void k_ingest(int n, const double* __restrict__ xyz, const double* __restrict__ q,
                                                 double3 lo, double3 L, int slab, double4* __restrict__ pos,
@@ -84,7 +111,7 @@ __global__ __launch_bounds__(256) void k_ingest(int n, const double* __restrict_
     const double fy = fmin(fmax((y / L.y + 0.5) * 1024.0, 0.0), 1023.0);
     const double fz = fmin(fmax((z / L.z + 0.5) * 1024.0, 0.0), 1023.0);
     const uint32_t cx = (uint32_t)fx, cy = (uint32_t)fy, cz = (uint32_t)fz;
-    key[i] = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+    key[i] = hilbert_key3(cx, cy, cz);
     val[i] = i;
     pos[i] = make_double4(fin ? x : 0.0, fin ? y : 0.0, fin ? z : 0.0, fin ? qi : 0.0);
   }
@@ -264,44 +291,72 @@ __global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ ord
 }
 
 // ----------------------------------------------------------------- pair sums
-// One wave per work item: a group of up to 128 targets (2 per lane) against
-// a contiguous range of (image entry, source tile) pairs.  Sources are read
+// One wave per work item: a group of up to 64*kTPL targets against a
+// contiguous range of (image entry, source tile) pairs.  Sources are read
 // with wave-uniform (scalar) loads, so a source costs no VGPRs and no LDS.
 // Coordinates: targets are kept as offsets from their group's box centre;
 // each tile contributes the FP32-rounded FP64 shift between its image
 // centre and the group centre, so close pairs subtract small numbers.
-// Pairs closer than sqrt(rc2) (only possible in tiles whose bounding box
-// comes within that distance of the group) recompute the difference from
-// the FP64 positions, which also removes the self pair.
 // Accumulation: plain sums within a tile, error-free (2Sum) folding of the
 // tile partials into a (hi, lo) potential across tiles.
-template <typename Real, bool PARTICLES>
-__global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ groups,
+//
+// The work is split by distance.  A (tile, image) whose bounding box stays
+// at least rc from the group's ("far") goes through the FAR kernel, a plain
+// FP32 loop.  The few others ("near": the group's own tile and its
+// neighbours) go through the NEAR kernel, which recomputes the difference
+// vector of any pair closer than rc from the FP64 positions and drops the
+// self pair.  Both kernels classify tiles with the same FP64 arithmetic, so
+// every pair is summed exactly once.
+// Tile classification shared by the far and near kernels.  Explicitly
+// rounded operations (no FMA contraction) so that both kernels reach the
+// same decision for every (group, image, tile) and each pair is summed once.
+__device__ __forceinline__ double shifted_dz(const Desc& ds, double cz, double cgz) {
+  return __dsub_rn(__dadd_rn(__dmul_rn(ds.sigma, cz), ds.sz), cgz);
+}
+__device__ __forceinline__ double gap2_of(double dlx, double dly, double dlz, double hx, double hy, double hz) {
+  const double gx = fmax(0.0, __dsub_rn(fabs(dlx), hx));
+  const double gy = fmax(0.0, __dsub_rn(fabs(dly), hy));
+  const double gz = fmax(0.0, __dsub_rn(fabs(dlz), hz));
+  return __dadd_rn(__dadd_rn(__dmul_rn(gx, gx), __dmul_rn(gy, gy)), __dmul_rn(gz, gz));
+}
+
+#ifndef HSMA_FAR_UNROLL
+#define HSMA_FAR_UNROLL 16
+#endif
+// Register budget of the pair kernels: 8 waves per SIMD (<= 64 VGPRs).  The
+// loop is bound by VALU + transcendental issue, and without this bound the
+// compiler spends registers on interleaving and drops to 4 waves (-25 %).
+// (The FP64 variant keeps 4 waves so that its doubles do not spill.)
+#ifndef HSMA_WAVES_PER_EU
+#define HSMA_WAVES_PER_EU 8
+#endif
+#define HSMA_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? HSMA_WAVES_PER_EU : 4)))
+
+template <typename Real, bool NEAR, bool PARTICLES>
+__global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ groups,
                                              const Work* __restrict__ work, const Desc* __restrict__ desc,
                                              int ntiles, const double4* __restrict__ tile_c,
                                              const float4* __restrict__ tile_h,
                                              const typename SrcT<Real>::T* __restrict__ src,
-                                             const double4* __restrict__ pos64, double rc2, Real* __restrict__ part,
-                                             long comp_stride, long slot_stride) {
+                                             const double4* __restrict__ pos64, double3 hbox, double rc2,
+                                             Real* __restrict__ part, long comp_stride, long slot_stride) {
   typedef typename SrcT<Real>::T S;
   const Work w = work[blockIdx.x];
   const Group g = groups[w.group];
   const int lane = threadIdx.x;
-  double tx[kTPL], ty[kTPL], tz[kTPL];
   bool valid[kTPL];
+  Real ox[kTPL], oy[kTPL], oz[kTPL];
   double mnx = INFINITY, mny = INFINITY, mnz = INFINITY, mxx = -INFINITY, mxy = -INFINITY, mxz = -INFINITY;
+  double4 tp[kTPL];
 #pragma unroll
   for (int j = 0; j < kTPL; ++j) {
     const int l = j * kWave + lane;
     valid[j] = l < g.count;
-    const double4 p = tgt[g.first + (valid[j] ? l : 0)];
-    tx[j] = p.x;
-    ty[j] = p.y;
-    tz[j] = p.z;
+    tp[j] = tgt[g.first + (valid[j] ? l : 0)];
     if (valid[j]) {
-      mnx = fmin(mnx, p.x); mxx = fmax(mxx, p.x);
-      mny = fmin(mny, p.y); mxy = fmax(mxy, p.y);
-      mnz = fmin(mnz, p.z); mxz = fmax(mxz, p.z);
+      mnx = fmin(mnx, tp[j].x); mxx = fmax(mxx, tp[j].x);
+      mny = fmin(mny, tp[j].y); mxy = fmax(mxy, tp[j].y);
+      mnz = fmin(mnz, tp[j].z); mxz = fmax(mxz, tp[j].z);
     }
   }
   mnx = wave_min(mnx); mxx = wave_max(mxx);
@@ -309,31 +364,21 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
   mnz = wave_min(mnz); mxz = wave_max(mxz);
   const double cgx = 0.5 * (mnx + mxx), cgy = 0.5 * (mny + mxy), cgz = 0.5 * (mnz + mxz);
   const double hgx = 0.5 * (mxx - mnx), hgy = 0.5 * (mxy - mny), hgz = 0.5 * (mxz - mnz);
-  Real ox[kTPL], oy[kTPL], oz[kTPL];
   Real ph[kTPL], pl[kTPL], ex[kTPL], ey[kTPL], ez[kTPL];
 #pragma unroll
   for (int j = 0; j < kTPL; ++j) {
-    ox[j] = (Real)(tx[j] - cgx);
-    oy[j] = (Real)(ty[j] - cgy);
-    oz[j] = (Real)(tz[j] - cgz);
+    ox[j] = (Real)(tp[j].x - cgx);
+    oy[j] = (Real)(tp[j].y - cgy);
+    oz[j] = (Real)(tp[j].z - cgz);
     ph[j] = pl[j] = ex[j] = ey[j] = ez[j] = (Real)0;
   }
   const int tbase = g.first + lane;  // sorted index of this lane's first target
 
-  for (int f = w.f0; f < w.f1; ++f) {
-    const int di = f / ntiles;
-    const int tile = f - di * ntiles;
-    const Desc ds = desc[g.desc_off + di];
-    const double4 cs = tile_c[tile];
-    const float4 hs = tile_h[tile];
-    const double dlx = (cs.x + ds.sx) - cgx;
-    const double dly = (cs.y + ds.sy) - cgy;
-    const double dlz = (ds.sigma * cs.z + ds.sz) - cgz;
-    const double gx = fmax(0.0, fabs(dlx) - hgx - (double)hs.x);
-    const double gy = fmax(0.0, fabs(dly) - hgy - (double)hs.y);
-    const double gz = fmax(0.0, fabs(dlz) - hgz - (double)hs.z);
-    const double gap2 = gx * gx + gy * gy + gz * gz;
+  // One (image, tile) pair: sum its 64 sources into the accumulators.
+  auto do_tile = [&](const Desc& ds, const bool own, const int tile, const double dlx, const double dly,
+                     const double dlz) {
     const Real sg = (Real)ds.sigma;
+    const Real sc = (Real)ds.scale;
     Real ux[kTPL], uy[kTPL], uz[kTPL];
     Real pp[kTPL], qx[kTPL], qy[kTPL], qz[kTPL];
 #pragma unroll
@@ -344,8 +389,8 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
       pp[j] = qx[j] = qy[j] = qz[j] = (Real)0;
     }
     const S* __restrict__ s = src + (long)tile * kTile;
-    if (gap2 >= rc2) {
-#pragma unroll 16
+    if constexpr (!NEAR) {
+#pragma unroll HSMA_FAR_UNROLL
       for (int k = 0; k < kTile; ++k) {
         const S v = s[k];
 #pragma unroll
@@ -364,8 +409,6 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
         }
       }
     } else {
-      const bool ident = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.0;
-#pragma unroll 4
       for (int k = 0; k < kTile; ++k) {
         const S v = s[k];
 #pragma unroll
@@ -375,17 +418,19 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
           Real dz = uz[j] - (Real)v.z;
           Real r2 = dx * dx + dy * dy + dz * dz;
           Real qq = (Real)v.w;
-          if ((double)r2 < rc2) {
-            const long si = (long)tile * kTile + k;
+          const long si = (long)tile * kTile + k;
+          if (PARTICLES && own && si == (long)(tbase + j * kWave)) {
+            // the target itself or one of its own images: summed in FP64 by
+            // the finalize kernel (self pair excluded there)
+            qq = (Real)0;
+            r2 = (Real)1;
+          } else if ((double)r2 < rc2) {
+            // close pair: difference vector from the FP64 positions
             const double4 ps = pos64[si];
-            dx = (Real)(tx[j] - (ps.x + ds.sx));
-            dy = (Real)(ty[j] - (ps.y + ds.sy));
-            dz = sg * (Real)(tz[j] - (ds.sigma * ps.z + ds.sz));
+            dx = (Real)(tp[j].x - (ps.x + ds.sx));
+            dy = (Real)(tp[j].y - (ps.y + ds.sy));
+            dz = sg * (Real)(tp[j].z - (ds.sigma * ps.z + ds.sz));
             r2 = dx * dx + dy * dy + dz * dz;
-            if (PARTICLES && ident && si == (long)(tbase + j * kWave)) {
-              qq = (Real)0;
-              r2 = (Real)1;
-            }
           }
           const Real ri = rsq(r2);
           const Real a = qq * ri;
@@ -397,7 +442,6 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
         }
       }
     }
-    const Real sc = (Real)ds.scale;
 #pragma unroll
     for (int j = 0; j < kTPL; ++j) {
       const Real t = sc * pp[j];
@@ -412,6 +456,78 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
       ex[j] += sc * qx[j];
       ey[j] += sc * qy[j];
       ez[j] += (sc * sg) * qz[j];
+    }
+  };
+
+  // The group's own tiles (which hold the targets themselves) go through
+  // the near kernel under every image, so that a target never meets itself
+  // or its own images in the FP32 loop: those terms share one distance for
+  // all particles and their rounding would not average out.
+  const int own0 = PARTICLES ? g.first / kTile : 0;
+  const int own1 = PARTICLES ? (g.first + g.count - 1) / kTile : -1;
+
+  int f = w.f0;
+  while (f < w.f1) {
+    const int di = f / ntiles;
+    const int t0 = f - di * ntiles;
+    const int t1 = min(ntiles, t0 + (w.f1 - f));
+    f += t1 - t0;
+    const Desc ds = desc[g.desc_off + di];
+    // every tile of this image lies inside the shifted box: if the box is
+    // far from the group, so is each of its tiles
+    const bool img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
+                                 __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
+    if constexpr (NEAR) {
+      if (img_far) {
+        for (int nt = max(t0, own0); nt <= min(t1 - 1, own1); ++nt) {
+          const double4 cs = tile_c[nt];
+          do_tile(ds, true, nt, __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
+                  shifted_dz(ds, cs.z, cgz));
+        }
+        continue;
+      }
+      // lane-parallel scan: lane l classifies tile tb + l, then the wave
+      // walks the near ones in increasing tile order
+      for (int tb = t0; tb < t1; tb += kWave) {
+        const int tile = tb + lane;
+        bool near = false;
+        if (tile < t1) {
+          const double4 cs = tile_c[tile];
+          const float4 hs = tile_h[tile];
+          const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+          const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+          const double dlz = shifted_dz(ds, cs.z, cgz);
+          near = (tile >= own0 && tile <= own1) ||
+                 gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+                         __dadd_rn(hgz, (double)hs.z)) < rc2;
+        }
+        unsigned long long m = __ballot(near);
+        while (m) {
+          const int l = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const int nt = tb + l;
+          const double4 cs = tile_c[nt];
+          const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+          const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+          const double dlz = shifted_dz(ds, cs.z, cgz);
+          do_tile(ds, nt >= own0 && nt <= own1, nt, dlx, dly, dlz);
+        }
+      }
+    } else {
+      for (int tile = t0; tile < t1; ++tile) {
+        if (tile >= own0 && tile <= own1) continue;  // summed by the near pass
+        const double4 cs = tile_c[tile];
+        const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+        const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+        const double dlz = shifted_dz(ds, cs.z, cgz);
+        if (!img_far) {
+          const float4 hs = tile_h[tile];
+          if (gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+                      __dadd_rn(hgz, (double)hs.z)) < rc2)
+            continue;  // summed by the near pass
+        }
+        do_tile(ds, false, tile, dlx, dly, dlz);
+      }
     }
   }
 #pragma unroll
@@ -429,116 +545,113 @@ __global__ __launch_bounds__(64) void k_pair(const double4* __restrict__ tgt, co
 // Sphere sources: charge Q_k and double-layer strength D_k at y_k, normal
 // n_k.  phi += Q/|d| - D (n.d)/|d|^3,  E += Q d/|d|^3 + D (n/|d|^3 - 3 (n.d) d/|d|^5).
 // Records: surf[2k] = (y, Q), surf[2k+1] = (n, D), box-centred coordinates.
+// Grid: (target group, chunk of kSphereChunk sources); slot = slot0 + chunk.
+// Always FP64: the Green representation of the harmonic part cancels
+// strongly inside the sphere (u on the sphere exceeds u in the box by about
+// lambda^p), so FP32 rounding of Q_k, D_k and y_k would be amplified into a
+// smooth error field; these sums are N x F pairs, a few per mille of the
+// near-set work.  FP32 partials store the potential as a (hi, lo) pair.
+constexpr int kSphereChunk = 256;
+
 template <typename Real>
 __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ tgt, int n,
-                                                    const typename SrcT<Real>::T* __restrict__ surf, int F,
-                                                    Real* __restrict__ part, long comp_stride, long slot_off) {
-  typedef typename SrcT<Real>::T S;
+                                                    const double4* __restrict__ surf, int F,
+                                                    Real* __restrict__ part, long comp_stride, int slot0) {
   const int lane = threadIdx.x;
   const int first = blockIdx.x * kGroup;
-  Real tx[kTPL], ty[kTPL], tz[kTPL];
-  Real ph[kTPL], pl[kTPL], ex[kTPL], ey[kTPL], ez[kTPL];
+  const int kb = blockIdx.y * kSphereChunk, ke = min(F, kb + kSphereChunk);
+  double tx[kTPL], ty[kTPL], tz[kTPL];
+  double ph[kTPL], ex[kTPL], ey[kTPL], ez[kTPL];
 #pragma unroll
   for (int j = 0; j < kTPL; ++j) {
     const int t = min(first + j * kWave + lane, n - 1);
     const double4 p = tgt[t];
-    tx[j] = (Real)p.x;
-    ty[j] = (Real)p.y;
-    tz[j] = (Real)p.z;
-    ph[j] = pl[j] = ex[j] = ey[j] = ez[j] = (Real)0;
+    tx[j] = p.x;
+    ty[j] = p.y;
+    tz[j] = p.z;
+    ph[j] = ex[j] = ey[j] = ez[j] = 0.0;
   }
-  for (int k0 = 0; k0 < F; k0 += kTile) {
-    const int k1 = min(F, k0 + kTile);
-    Real pp[kTPL], qx[kTPL], qy[kTPL], qz[kTPL];
-#pragma unroll
-    for (int j = 0; j < kTPL; ++j) pp[j] = qx[j] = qy[j] = qz[j] = (Real)0;
-    for (int k = k0; k < k1; ++k) {
-      const S a0 = surf[2 * k], a1 = surf[2 * k + 1];
-#pragma unroll
-      for (int j = 0; j < kTPL; ++j) {
-        const Real dx = tx[j] - (Real)a0.x, dy = ty[j] - (Real)a0.y, dz = tz[j] - (Real)a0.z;
-        const Real r2 = dx * dx + dy * dy + dz * dz;
-        const Real ri = rsq(r2);
-        const Real ri2 = ri * ri;
-        const Real ri3 = ri * ri2;
-        const Real a = (Real)a0.w * ri;
-        const Real nd = (Real)a1.x * dx + (Real)a1.y * dy + (Real)a1.z * dz;
-        const Real t = (Real)a1.w * nd * ri3;
-        pp[j] += a - t;
-        const Real c1 = ri2 * (a - (Real)3 * t);
-        const Real c2 = (Real)a1.w * ri3;
-        qx[j] += c1 * dx + c2 * (Real)a1.x;
-        qy[j] += c1 * dy + c2 * (Real)a1.y;
-        qz[j] += c1 * dz + c2 * (Real)a1.z;
-      }
-    }
+  for (int k = kb; k < ke; ++k) {
+    const double4 a0 = surf[2 * k], a1 = surf[2 * k + 1];
 #pragma unroll
     for (int j = 0; j < kTPL; ++j) {
-      if constexpr (sizeof(Real) == 4) {
-        float hs2, e;
-        two_sum(ph[j], pp[j], hs2, e);
-        ph[j] = hs2;
-        pl[j] += e;
-      } else {
-        ph[j] += pp[j];
-      }
-      ex[j] += qx[j];
-      ey[j] += qy[j];
-      ez[j] += qz[j];
+      const double dx = tx[j] - a0.x, dy = ty[j] - a0.y, dz = tz[j] - a0.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ri = 1.0 / sqrt(r2);
+      const double ri2 = ri * ri;
+      const double ri3 = ri * ri2;
+      const double a = a0.w * ri;
+      const double nd = a1.x * dx + a1.y * dy + a1.z * dz;
+      const double t = a1.w * nd * ri3;
+      ph[j] += a - t;
+      const double c1 = ri2 * (a - 3.0 * t);
+      const double c2 = a1.w * ri3;
+      ex[j] += c1 * dx + c2 * a1.x;
+      ey[j] += c1 * dy + c2 * a1.y;
+      ez[j] += c1 * dz + c2 * a1.z;
     }
   }
 #pragma unroll
   for (int j = 0; j < kTPL; ++j) {
     const int t = first + j * kWave + lane;
     if (t >= n) continue;
-    const long o = slot_off + t;
-    part[o] = ph[j];
-    part[o + comp_stride] = pl[j];
-    part[o + 2 * comp_stride] = ex[j];
-    part[o + 3 * comp_stride] = ey[j];
-    part[o + 4 * comp_stride] = ez[j];
+    const long o = (long)(slot0 + blockIdx.y) * 5 * comp_stride + t;
+    const Real hi = (Real)ph[j];
+    part[o] = hi;
+    part[o + comp_stride] = (Real)(ph[j] - (double)hi);
+    part[o + 2 * comp_stride] = (Real)ex[j];
+    part[o + 3 * comp_stride] = (Real)ey[j];
+    part[o + 4 * comp_stride] = (Real)ez[j];
   }
 }
 
 // ----------------------------------------------------------------- check / LSQ / sphere
 // Sum the work-item partials of every check target in a fixed order:
-// v[2t] = potential, v[2t+1] = field component axis[t].
+// v[2t] = potential, v[2t+1] = field component axis[t].  One block per
+// check group; the two halves of the block take alternate slots and are
+// combined at the end (error-free for the FP32 potential).
 template <typename Real>
-__global__ __launch_bounds__(256) void k_reduce_check(int ncheck, const int* __restrict__ t_group,
-                                                      const Group* __restrict__ groups,
-                                                      const int2* __restrict__ g_work, const int* __restrict__ axis,
+__global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __restrict__ groups,
+                                                      const int2* __restrict__ g_slots, const int* __restrict__ axis,
                                                       const Real* __restrict__ part, double* __restrict__ v) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= ncheck) return;
-  const int gi = t_group[t];
-  const int local = t - groups[gi].first;
-  const int2 wr = g_work[gi];
+  __shared__ double sh_phi[kGroup], sh_e[kGroup];
+  const Group g = groups[blockIdx.x];
+  const int2 sr = g_slots[blockIdx.x];
+  const int local = threadIdx.x % kGroup, half = threadIdx.x / kGroup;
+  const bool ok = local < g.count;
+  const int t = g.first + (ok ? local : 0);
   const int ax = axis[t];
   double phi = 0, e = 0;
   if constexpr (sizeof(Real) == 4) {
     float hi = 0, lo = 0, ea = 0, ec = 0;
-    for (int w = wr.x; w < wr.x + wr.y; ++w) {
+    for (int w = sr.x + half; w < sr.x + sr.y; w += 2) {
       const Real* p = part + (long)w * 5 * kGroup + local;
-      float s, er;
-      two_sum(hi, p[0], s, er);
-      hi = s;
+      float sm, er;
+      two_sum(hi, p[0], sm, er);
+      hi = sm;
       lo += er + p[kGroup];
-      float y = p[(2 + ax) * kGroup];
-      two_sum(ea, y, s, er);
-      ea = s;
+      two_sum(ea, p[(2 + ax) * kGroup], sm, er);
+      ea = sm;
       ec += er;
     }
     phi = (double)hi + (double)lo;
     e = (double)ea + (double)ec;
   } else {
-    for (int w = wr.x; w < wr.x + wr.y; ++w) {
+    for (int w = sr.x + half; w < sr.x + sr.y; w += 2) {
       const Real* p = part + (long)w * 5 * kGroup + local;
       phi += p[0];
       e += p[(2 + ax) * kGroup];
     }
   }
-  v[2 * t] = phi;
-  v[2 * t + 1] = e;
+  if (half == 1) {
+    sh_phi[local] = phi;
+    sh_e[local] = e;
+  }
+  __syncthreads();
+  if (half == 0 && ok) {
+    v[2 * t] = phi + sh_phi[local];
+    v[2 * t + 1] = e + sh_e[local];
+  }
 }
 
 // A[j] = sum_c Praw[j][c] v[c]  (FP64, fixed-order block reduction)
@@ -582,9 +695,12 @@ __global__ __launch_bounds__(64) void k_sphere_sources(int F, int nb, const doub
 // Sum the nslot partials of every particle (fixed order), scale by the
 // Coulomb constant, write potential and force in the caller's order, and
 // per-block energy partials q_i Phi_i.  Invalid input -> NaN outputs.
+// The images of a particle itself (every image entry except the identity)
+// are summed here in FP64 for each particle.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* __restrict__ part, long comp_stride,
                                                   const double4* __restrict__ pos64, const int* __restrict__ perm,
+                                                  const Desc* __restrict__ desc, int ndesc,
                                                   double kc, const int* __restrict__ status, double* __restrict__ pot,
                                                   double* __restrict__ force, double* __restrict__ epart) {
   __shared__ double s[256];
@@ -618,7 +734,26 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* 
         fz += p[4 * comp_stride];
       }
     }
-    const double q = pos64[t].w;
+    const double4 p = pos64[t];
+    const double q = p.w;
+    double sphi = 0, sx = 0, sy = 0, sz = 0;
+    for (int d = 0; d < ndesc; ++d) {
+      const Desc ds = desc[d];
+      if (ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.0) continue;  // the self pair
+      const double dx = -ds.sx, dy = -ds.sy, dz = p.z - (ds.sigma * p.z + ds.sz);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ri = 1.0 / sqrt(r2);
+      const double a = ds.scale * ri;
+      sphi += a;
+      const double b = a * ri * ri;
+      sx += b * dx;
+      sy += b * dy;
+      sz += b * dz;
+    }
+    phi += q * sphi;
+    fx += q * sx;
+    fy += q * sy;
+    fz += q * sz;
     const bool ok = status[0] == HSMA_OK;
     const double nan = __builtin_nan("");
     phi = ok ? kc * phi : nan;
@@ -739,45 +874,51 @@ DevicePlan::~DevicePlan() {
   if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
-// Work items: every group's (image, tile) range cut into chunks so that a
-// launch has about `target` waves.  Particle groups share one chunking
-// (slot = chunk index); check groups get one slot per work item.
-static void make_work(const std::vector<Group>& groups, int ntiles, int target, bool shared_slots,
-                      std::vector<Work>& work, std::vector<int2>* grange, int* nchunks_out) {
+// Far work items: every group's (image, tile) range cut into chunks so that
+// a launch has about `target` waves.  Particle groups share one chunking
+// (slot = chunk index).  Check groups get their own slots: far chunks then
+// one near item, contiguous per group (slot range returned in `gslots`).
+static void make_far_work(const std::vector<Group>& groups, int ntiles, int target, bool shared_slots,
+                          std::vector<Work>& work, std::vector<int2>* gslots, int* nchunks_out) {
   work.clear();
-  if (grange) grange->assign(groups.size(), make_int2(0, 0));
+  if (gslots) gslots->assign(groups.size(), make_int2(0, 0));
   long long total = 0;
   for (const Group& g : groups) total += (long long)g.ndesc * ntiles;
+  // shared chunking: every particle group has the same range length, so
+  // one chunk length (and the exact chunk count it implies) serves all
   int nch_shared = 1;
+  long long chunk_shared = 1;
   if (shared_slots && !groups.empty()) {
     const long long per = (long long)groups[0].ndesc * ntiles;
-    nch_shared = (int)std::max<long long>(1, std::min<long long>(per / 8 + 1, (target + (long long)groups.size() - 1) / (long long)groups.size()));
-    nch_shared = (int)std::min<long long>(nch_shared, per);
+    long long want = std::max<long long>(1, (target + (long long)groups.size() - 1) / (long long)groups.size());
+    want = std::min<long long>(want, std::max<long long>(1, per / 8));
+    chunk_shared = (per + want - 1) / want;
+    nch_shared = (int)((per + chunk_shared - 1) / chunk_shared);
   }
+  int slot = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
     const long long F = (long long)g.ndesc * ntiles;
-    int nch;
-    if (shared_slots) nch = nch_shared;
-    else nch = (int)std::max<long long>(1, std::min<long long>(F / 4 + 1, (long long)((double)target * F / std::max<long long>(1, total) + 0.5)));
-    nch = (int)std::min<long long>(nch, std::max<long long>(1, F));
-    const long long chunk = (F + nch - 1) / nch;
-    const int first = (int)work.size();
+    long long chunk;
+    if (shared_slots) {
+      chunk = chunk_shared;
+    } else {
+      const long long want = std::max<long long>(1, std::min<long long>(std::max<long long>(1, F / 8),
+          (long long)((double)target * F / std::max<long long>(1, total) + 0.5)));
+      chunk = (F + want - 1) / want;
+    }
+    const int nch = (int)((F + chunk - 1) / chunk);
+    const int first_slot = slot;
     for (int c = 0; c < nch; ++c) {
       const long long f0 = c * chunk, f1 = std::min(F, f0 + chunk);
-      Work w;
-      w.group = (int)gi;
-      w.f0 = (int)f0;
-      w.f1 = (int)f1;
-      w.slot = shared_slots ? c : (int)work.size();
-      work.push_back(w);
+      work.push_back(Work{(int)gi, (int)f0, (int)f1, shared_slots ? c : slot});
+      ++slot;
     }
-    if (grange) (*grange)[gi] = make_int2(first, (int)work.size() - first);
+    if (!shared_slots) ++slot;  // the group's near item
+    if (gslots) (*gslots)[gi] = make_int2(first_slot, slot - first_slot);
   }
-  // chunk-major order for the shared case: neighbouring waves read the same tiles
-  if (shared_slots) {
+  if (shared_slots)
     std::stable_sort(work.begin(), work.end(), [](const Work& a, const Work& b) { return a.slot < b.slot; });
-  }
   if (nchunks_out) *nchunks_out = nch_shared;
 }
 
@@ -785,24 +926,36 @@ hsma_status DevicePlan::prepare(int64_t n, std::string& err) {
   if (n == cur_n) return HSMA_OK;
   const int ntiles = (int)((n + kTile - 1) / kTile);
   const int ngroups = (int)((n + kGroup - 1) / kGroup);
-  const int npad = ntiles * kTile;
   const int nrsblk = (int)((n + kRsBlock - 1) / kRsBlock);
-  // particle groups and work
   std::vector<Group> groups(ngroups);
   for (int g = 0; g < ngroups; ++g)
     groups[g] = Group{g * kGroup, (int)std::min<int64_t>(kGroup, n - (int64_t)g * kGroup), 0,
                       (int)host.desc_particles.size()};
-  std::vector<Work> work, cwork;
+  std::vector<Work> work, cwork, nwork, cnwork;
   int nch = 1;
-  make_work(groups, ntiles, part_target, true, work, nullptr, &nch);
-  std::vector<int2> cgr;
-  make_work(host.check_groups, ntiles, check_target, false, cwork, &cgr, nullptr);
+  make_far_work(groups, ntiles, part_target, true, work, nullptr, &nch);
+  for (int g = 0; g < ngroups; ++g)
+    nwork.push_back(Work{g, 0, groups[g].ndesc * ntiles, nch});
+  // every particle target must receive exactly one partial in each shared slot
+  if ((long long)work.size() != (long long)nch * ngroups) {
+    err = "internal error: uneven particle work decomposition";
+    return HSMA_ERR_DEVICE;
+  }
+  std::vector<int2> cgs;
+  make_far_work(host.check_groups, ntiles, check_target, false, cwork, &cgs, nullptr);
+  int ncslots = 0;
+  for (size_t gi = 0; gi < host.check_groups.size(); ++gi) {
+    cnwork.push_back(Work{(int)gi, 0, host.check_groups[gi].ndesc * ntiles, cgs[gi].x + cgs[gi].y - 1});
+    ncslots = std::max(ncslots, cgs[gi].x + cgs[gi].y);
+  }
+  const int nsc = (host.prm.F + kSphereChunk - 1) / kSphereChunk;
+  const int nslots = nch + 1 + nsc;
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
   const long comp = (long)ngroups * kGroup;
-  const size_t part_bytes = rb * 5 * (size_t)comp * (nch + 1);
-  const size_t cpart_bytes = rb * 5 * (size_t)kGroup * cwork.size();
-  if (n > cap_n || part_bytes > part_cap || cpart_bytes > cpart_cap || work.size() > work_cap ||
-      cwork.size() > cwork_cap) {
+  const size_t part_bytes = rb * 5 * (size_t)comp * nslots;
+  const size_t cpart_bytes = rb * 5 * (size_t)kGroup * ncslots;
+  if (n > cap_n || part_bytes > part_cap || cpart_bytes > cpart_cap ||
+      work.size() + nwork.size() > work_cap || cwork.size() + cnwork.size() > cwork_cap) {
     free_arena();
     const int64_t cn = std::max<int64_t>(n, 64);
     const int64_t cnt = ((cn + kTile - 1) / kTile);
@@ -825,14 +978,14 @@ hsma_status DevicePlan::prepare(int64_t n, std::string& err) {
     HIPCHK(hipMalloc(&d_part, part_bytes));
     HIPCHK(hipMalloc(&d_cpart, std::max<size_t>(cpart_bytes, 64)));
     HIPCHK(hipMalloc((void**)&d_groups, sizeof(Group) * groups.size()));
-    HIPCHK(hipMalloc((void**)&d_work, sizeof(Work) * work.size()));
-    HIPCHK(hipMalloc((void**)&d_cwork, sizeof(Work) * std::max<size_t>(1, cwork.size())));
-    HIPCHK(hipMalloc((void**)&d_cg_work, sizeof(int2) * std::max<size_t>(1, cgr.size())));
+    HIPCHK(hipMalloc((void**)&d_work, sizeof(Work) * (work.size() + nwork.size())));
+    HIPCHK(hipMalloc((void**)&d_cwork, sizeof(Work) * std::max<size_t>(1, cwork.size() + cnwork.size())));
+    HIPCHK(hipMalloc((void**)&d_cg_work, sizeof(int2) * std::max<size_t>(1, cgs.size())));
     cap_n = cn;
     part_cap = part_bytes;
     cpart_cap = cpart_bytes;
-    work_cap = work.size();
-    cwork_cap = cwork.size();
+    work_cap = work.size() + nwork.size();
+    cwork_cap = cwork.size() + cnwork.size();
     group_cap = groups.size();
   }
   if (groups.size() > group_cap) {
@@ -840,20 +993,27 @@ hsma_status DevicePlan::prepare(int64_t n, std::string& err) {
     HIPCHK(hipMalloc((void**)&d_groups, sizeof(Group) * groups.size()));
     group_cap = groups.size();
   }
+  // far items first, near items after them, in one array each
+  std::vector<Work> all = work;
+  all.insert(all.end(), nwork.begin(), nwork.end());
+  std::vector<Work> call = cwork;
+  call.insert(call.end(), cnwork.begin(), cnwork.end());
   HIPCHK(hipMemcpy(d_groups, groups.data(), sizeof(Group) * groups.size(), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(d_work, work.data(), sizeof(Work) * work.size(), hipMemcpyHostToDevice));
-  if (!cwork.empty()) {
-    HIPCHK(hipMemcpy(d_cwork, cwork.data(), sizeof(Work) * cwork.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d_cg_work, cgr.data(), sizeof(int2) * cgr.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_work, all.data(), sizeof(Work) * all.size(), hipMemcpyHostToDevice));
+  if (!call.empty()) {
+    HIPCHK(hipMemcpy(d_cwork, call.data(), sizeof(Work) * call.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_cg_work, cgs.data(), sizeof(int2) * cgs.size(), hipMemcpyHostToDevice));
   }
   cur_n = n;
   ntiles_ = ntiles;
   ngroups_ = ngroups;
   nwork_ = (int)work.size();
+  nnear_ = (int)nwork.size();
   ncwork_ = (int)cwork.size();
+  ncnear_ = (int)cnwork.size();
   nchunks_ = nch;
+  nsphere_ = nsc;
   nrsblk_ = nrsblk;
-  (void)npad;
   return HSMA_OK;
 }
 
@@ -882,6 +1042,7 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   const bool fp64 = host.prm.precision == HSMA_FP64;
   const double3 lo = make_double3(host.lo[0], host.lo[1], host.lo[2]);
   const double3 L = make_double3(host.L[0], host.L[1], host.L[2]);
+  const double3 hbox = make_double3(0.5 * host.L[0], 0.5 * host.L[1], 0.5 * host.L[2]);
   const int slab = host.prm.geometry == HSMA_GEOM_2D;
   const int nblk = (n + 255) / 256;
   if ((s = record(st, kStStep, 0, err)) != HSMA_OK) return s;
@@ -899,70 +1060,59 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   }
   hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
                      d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
-  // close-pair radius for the FP64 coordinate correction (FP32 path):
-  // a tenth of a typical tile extent; FP64 path only needs the self pair.
+  // close-pair radius: a tenth of a typical tile extent (FP32 path); the
+  // FP64 path needs the near pass only to drop the self pair
   const double vol = host.L[0] * host.L[1] * host.L[2];
   const double ext = std::cbrt(kTile * vol / std::max(1, n));
   const double rc = fp64 ? 1e-9 * ext : close_factor * ext;
   const double rc2 = rc * rc;
   const int ncheck = (int)host.check_axis.size();
+  const int ncg = (int)host.check_groups.size();
   const long ccomp = kGroup, cslot = 5L * kGroup;
-  if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;
-  if (fp64) {
-    hipLaunchKernelGGL((k_pair<double, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,
-                       (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const double4*)d_src64,
-                       (const double4*)d_pos64, rc2, (double*)d_cpart, ccomp, cslot);
-    if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;
-    hipLaunchKernelGGL(k_reduce_check<double>, dim3((ncheck + 255) / 256), dim3(256), 0, st, ncheck,
-                       (const int*)d_check_tgroup, (const Group*)d_check_groups, (const int2*)d_cg_work,
-                       (const int*)d_check_axis, (const double*)d_cpart, d_v);
-  } else {
-    hipLaunchKernelGGL((k_pair<float, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,
-                       (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,
-                       (const double4*)d_pos64, rc2, (float*)d_cpart, ccomp, cslot);
-    if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;
-    hipLaunchKernelGGL(k_reduce_check<float>, dim3((ncheck + 255) / 256), dim3(256), 0, st, ncheck,
-                       (const int*)d_check_tgroup, (const Group*)d_check_groups, (const int2*)d_cg_work,
-                       (const int*)d_check_axis, (const float*)d_cpart, d_v);
-  }
-  hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw,
-                     (const double*)d_v, d_A);
-  const int F = host.prm.F;
-  hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
-                     (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,
-                     d_surf32, d_surf64, d_qd);
   const long comp = (long)ngroups_ * kGroup;
   const long slot = 5L * comp;
-  if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;
-  if (fp64) {
-    hipLaunchKernelGGL((k_pair<double, true>), dim3(nwork_), dim3(64), 0, st, (const double4*)d_pos64,
-                       (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const double4*)d_src64,
-                       (const double4*)d_pos64, rc2, (double*)d_part, comp, slot);
-    if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;
-    if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;
-    hipLaunchKernelGGL(k_pair_sphere<double>, dim3(ngroups_), dim3(64), 0, st, (const double4*)d_pos64, n,
-                       (const double4*)d_surf64, F, (double*)d_part, comp, (long)nchunks_ * slot);
-    if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;
-    hipLaunchKernelGGL(k_finalize<double>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + 1, (const double*)d_part,
-                       comp, (const double4*)d_pos64, (const int*)d_perm, host.prm.coulomb_k,
-                       (const int*)d_status, d_pot, d_force, d_epart);
-  } else {
-    hipLaunchKernelGGL((k_pair<float, true>), dim3(nwork_), dim3(64), 0, st, (const double4*)d_pos64,
-                       (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,
-                       (const double4*)d_pos64, rc2, (float*)d_part, comp, slot);
-    if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;
-    if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;
-    hipLaunchKernelGGL(k_pair_sphere<float>, dim3(ngroups_), dim3(64), 0, st, (const double4*)d_pos64, n,
-                       (const float4*)d_surf32, F, (float*)d_part, comp, (long)nchunks_ * slot);
-    if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;
-    hipLaunchKernelGGL(k_finalize<float>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + 1, (const float*)d_part, comp,
-                       (const double4*)d_pos64, (const int*)d_perm, host.prm.coulomb_k, (const int*)d_status,
-                       d_pot, d_force, d_epart);
-  }
+  const int F = host.prm.F;
+#define HSMA_SUMS(Real, S, SRC, SURF)                                                                               \
+  do {                                                                                                              \
+    if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;                                                    \
+    hipLaunchKernelGGL((k_pair<Real, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,   \
+                       (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,      \
+                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
+                       hbox, rc2, (Real*)d_cpart, ccomp, cslot);                                                    \
+    hipLaunchKernelGGL((k_pair<Real, true, false>), dim3(ncnear_), dim3(64), 0, st, (const double4*)d_check_pos,    \
+                       (const Group*)d_check_groups, (const Work*)(d_cwork + ncwork_), (const Desc*)d_desc_check,   \
+                       ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC,                   \
+                       (const double4*)d_pos64, hbox, rc2, (Real*)d_cpart, ccomp, cslot);                           \
+    if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;                                                    \
+    hipLaunchKernelGGL(k_reduce_check<Real>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,      \
+                       (const int2*)d_cg_work, (const int*)d_check_axis, (const Real*)d_cpart, d_v);                \
+    hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw,                   \
+                       (const double*)d_v, d_A);                                                                    \
+    hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,     \
+                       (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,     \
+                       d_surf32, d_surf64, d_qd);                                                                   \
+    if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
+    hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(nwork_), dim3(64), 0, st, (const double4*)d_pos64,         \
+                       (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,              \
+                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
+                       hbox, rc2, (Real*)d_part, comp, slot);                                                       \
+    if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
+    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(nnear_), dim3(64), 0, st, (const double4*)d_pos64,          \
+                       (const Group*)d_groups, (const Work*)(d_work + nwork_), (const Desc*)d_desc_part, ntiles_,   \
+                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
+                       hbox, rc2, (Real*)d_part, comp, slot);                                                       \
+    if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;                                                   \
+    hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
+                       (const double4*)d_surf64, F, (Real*)d_part, comp, nchunks_ + 1);                             \
+    if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;                                                   \
+    hipLaunchKernelGGL(k_finalize<Real>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + 1 + nsphere_,                 \
+                       (const Real*)d_part, comp, (const double4*)d_pos64, (const int*)d_perm,                     \
+                       (const Desc*)d_desc_part, (int)host.desc_particles.size(), host.prm.coulomb_k,               \
+                       (const int*)d_status, d_pot, d_force, d_epart);                                              \
+  } while (0)
+  if (fp64) HSMA_SUMS(double, double4, d_src64, d_surf64);
+  else HSMA_SUMS(float, float4, d_src32, d_surf32);
+#undef HSMA_SUMS
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nblk, (const double*)d_epart,
                      d_energy ? d_energy : d_energy_scratch);
   HIPCHK(hipGetLastError());

@@ -133,6 +133,8 @@ def load_library():
     lib.hsma_debug_host_plan_destroy.argtypes = [vp]
     lib.hsma_debug_host_plan_get.argtypes = [vp, ctypes.c_char_p, d, i64]
     lib.hsma_debug_host_plan_get.restype = i64
+    lib.hsma_debug_hilbert_key.argtypes = [ctypes.c_uint32] * 3
+    lib.hsma_debug_hilbert_key.restype = ctypes.c_uint32
     for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_plan_device_status",
                  "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_plan_set_timing", "hsma_plan_get_timing", "hsma_debug_host_plan_create"):
         getattr(lib, name).restype = ctypes.c_int
@@ -164,6 +166,10 @@ def solid_harmonics(p: int, xi, grad: bool = False):
     g = np.zeros((nb, 3)) if grad else None
     _check(lib.hsma_debug_solid_harmonics(p, _dp(x), _dp(val), _dp(g)))
     return (val, g) if grad else val
+
+
+def hilbert_key(x: int, y: int, z: int) -> int:
+    return int(load_library().hsma_debug_hilbert_key(x, y, z))
 
 
 class HostPlan:

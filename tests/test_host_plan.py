@@ -213,3 +213,20 @@ def test_plan_2d_reproduces_oracle_fit():
     want = sorted((round(s[2], 9), round(float(qq), 6)) for s, qq in zip(S, qS))
     got = sorted((round(x[2], 9), round(x[4], 6)) for x in d)
     assert want == got
+
+
+def test_sort_key_is_a_hilbert_curve():
+    """Cells in key order form a face-adjacent walk through the grid (the
+    property that keeps sorted tiles compact); keys are a bijection."""
+    lib_or_skip()
+    n = 16  # the 16^3 corner of the 1024^3 grid is one level-4 sub-cube
+    keys = {}
+    for x in range(n):
+        for y in range(n):
+            for z in range(n):
+                keys[hs.hilbert_key(x, y, z)] = (x, y, z)
+    assert len(keys) == n ** 3
+    order = [keys[k] for k in sorted(keys)]
+    steps = [sum(abs(a - b) for a, b in zip(p, q)) for p, q in zip(order, order[1:])]
+    assert all(s == 1 for s in steps)
+    assert sorted(keys)[-1] - sorted(keys)[0] == n ** 3 - 1
