@@ -79,6 +79,66 @@ def cpu_baseline(w, pos, q, lo, L, sample_n=256):
     }
 
 
+def serving_bench(hs, workloads, n_systems=256, slots=8, loads=(0.5, 0.8, 0.95), seed=77):
+    """The serving mix: independent cubic systems (N uniform in [500, 20000],
+    L = (N/0.05)^(1/3), +-1, p 8, F 512, K 162) through the continuous
+    batching server.  Saturated throughput with every request queued at
+    once, the same with one slot (no overlap), then Poisson arrivals at
+    fractions of the saturated rate with p50/p99 submit-to-result latency."""
+    import numpy as np
+    ws = workloads.serving_systems(n_systems)
+    systems = []
+    for w in ws:
+        pos, q, lo, L = workloads.make_system(w)
+        systems.append((pos, q, lo, L[0]))
+    nmax = max(len(q) for _, q, _, _ in systems)
+    total_particles = sum(len(q) for _, q, _, _ in systems)
+    prm = hs.Params(precision=hs.FP32C, p=8, K=162, F=512, lam=1.5)
+    out = {"systems": n_systems, "particles": total_particles, "n_range": [min(len(q) for _, q, _, _ in systems), nmax]}
+
+    def run_all(sv):
+        t0 = time.perf_counter()
+        tickets = [sv.submit(pos, q, lo, L, potential=False) for pos, q, lo, L in systems]
+        res = [sv.wait(t) for t in tickets]
+        dt = time.perf_counter() - t0
+        assert all(r["status"] == 0 for r in res)
+        return dt, res
+
+    with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=1) as sv1:
+        run_all(sv1)  # warm-up
+        dt1, _ = run_all(sv1)
+    with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots) as sv:
+        nslots, per = sv.slots()
+        run_all(sv)  # warm-up
+        dt, res = run_all(sv)
+        rate = n_systems / dt
+        out.update({"slots": nslots, "bytes_per_slot": per,
+                    "saturated_requests_per_s": rate, "saturated_particle_steps_per_s": total_particles / dt,
+                    "one_slot_requests_per_s": n_systems / dt1, "batching_speedup": dt1 / dt})
+        rng = np.random.default_rng(seed)
+        out["poisson"] = []
+        for f in loads:
+            lam = f * rate
+            gaps = rng.exponential(1.0 / lam, n_systems)
+            order = rng.permutation(n_systems)
+            t0 = time.perf_counter()
+            arrivals = t0 + np.cumsum(gaps)
+            tickets = []
+            for k, i in enumerate(order):
+                delay = arrivals[k] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                pos, q, lo, L = systems[i]
+                tickets.append(sv.submit(pos, q, lo, L, potential=False))
+            rs = [sv.wait(t) for t in tickets]
+            lat = np.array([r["t_done"] - r["t_submit"] for r in rs]) * 1e3
+            span = max(r["t_done"] for r in rs) - min(r["t_submit"] for r in rs)
+            out["poisson"].append({"offered_fraction": f, "offered_requests_per_s": lam,
+                                   "achieved_requests_per_s": n_systems / span,
+                                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +146,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix measurement")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for counter runs: one 512 MiB device copy (calibration of the byte counters) "
                          "then warmup + steps of the benchmarked step, nothing else")
@@ -199,6 +260,8 @@ def main():
         }
         p64.close()
     plan.close()
+    if not args.no_serving:
+        out["serving"] = serving_bench(hs, workloads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, pos, q, lo, L)
     print(json.dumps(out), flush=True)

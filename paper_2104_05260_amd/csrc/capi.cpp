@@ -20,6 +20,44 @@ hsma_status fail(hsma_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+}  // namespace
+
+namespace hsma {
+hsma_status set_last_error(hsma_status s, const std::string& msg) { return fail(s, msg); }
+
+hsma_status validate_host_input(const hsma_params& prm, const double lo[3], const double L[3], int64_t n,
+                                const double* xyz, const double* q, std::string& msg) {
+  double sq = 0, sa = 0;
+  const bool slab = prm.geometry == HSMA_GEOM_2D;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(xyz[3 * i + c])) {
+        msg = "non-finite coordinate";
+        return HSMA_ERR_OUT_OF_DOMAIN;
+      }
+    if (!std::isfinite(q[i])) {
+      msg = "non-finite charge";
+      return HSMA_ERR_OUT_OF_DOMAIN;
+    }
+    if (slab) {
+      const double z = xyz[3 * i + 2] - lo[2];
+      if (!(z > 0.0 && z < L[2])) {
+        msg = "particle outside the slab";
+        return HSMA_ERR_OUT_OF_DOMAIN;
+      }
+    }
+    sq += q[i];
+    sa += std::fabs(q[i]);
+  }
+  if (!(std::fabs(sq) <= 1e-12 * sa)) {
+    msg = "system is not charge neutral";
+    return HSMA_ERR_NOT_NEUTRAL;
+  }
+  return HSMA_OK;
+}
+}  // namespace hsma
+
+namespace {
 
 hsma_status check_device() {
   int n = 0;
@@ -121,21 +159,11 @@ hsma_status hsma_compute(hsma_plan* plan, int64_t n, const double* xyz, const do
   if (!plan || !xyz || !q) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
   if (n < 1) return fail(HSMA_ERR_INVALID_ARG, "n must be >= 1");
   const hsma::HostPlan& hp = plan->dev.host;
-  // host-side validation
-  double sq = 0, sa = 0;
-  const bool slab = hp.prm.geometry == HSMA_GEOM_2D;
-  for (int64_t i = 0; i < n; ++i) {
-    for (int c = 0; c < 3; ++c)
-      if (!std::isfinite(xyz[3 * i + c])) return fail(HSMA_ERR_OUT_OF_DOMAIN, "non-finite coordinate");
-    if (!std::isfinite(q[i])) return fail(HSMA_ERR_OUT_OF_DOMAIN, "non-finite charge");
-    if (slab) {
-      const double z = xyz[3 * i + 2] - hp.lo[2];
-      if (!(z > 0.0 && z < hp.L[2])) return fail(HSMA_ERR_OUT_OF_DOMAIN, "particle outside the slab");
-    }
-    sq += q[i];
-    sa += std::fabs(q[i]);
+  {
+    std::string msg;
+    hsma_status vs = hsma::validate_host_input(hp.prm, hp.lo, hp.L, n, xyz, q, msg);
+    if (vs != HSMA_OK) return fail(vs, msg);
   }
-  if (!(std::fabs(sq) <= 1e-12 * sa)) return fail(HSMA_ERR_NOT_NEUTRAL, "system is not charge neutral");
   hsma::DevicePlan& d = plan->dev;
   auto hipfail = [](hipError_t e, const char* what) {
     return fail(e == hipErrorOutOfMemory ? HSMA_ERR_OOM : HSMA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));

@@ -19,7 +19,9 @@ struct DevicePlan {
 
   // tuning of the work decomposition
   int part_target = 32768;     // waves per particle pair launch (about)
-  int check_target = 2048;     // waves per check pair launch (about)
+  int check_target = 1024;     // minimum waves per check pair launch (about)
+  int check_target_max = 65536;
+  long long check_pairs_per_item = 400000;
   double close_factor = 0.1;   // close-pair radius / typical tile extent (FP32 path)
 
   // plan constants on the device
@@ -85,8 +87,28 @@ struct DevicePlan {
   hsma_status record(hipStream_t st, int stage, int edge, std::string& err);
   hipStream_t last_stream = nullptr;
 
+  void* h_stage = nullptr;       // pinned staging of the work tables
+  size_t stage_bytes = 0;
+  size_t arena_bytes = 0;        // device bytes of the per-size arena
+
+  // box re-targeting (serving: many boxes of one shape share one plan class)
+  bool scalable = false;
+  double unit_L[3] = {0, 0, 0}, unit_R = 0, cur_scale = 1.0;
+  Desc* d_unit_desc_part = nullptr;
+  Desc* d_unit_desc_check = nullptr;
+  double4* d_unit_check_pos = nullptr;
+  double* d_unit_Praw = nullptr;
+  double* d_unit_SQ = nullptr;
+  double* d_unit_SD = nullptr;
+  double* d_unit_ysurf = nullptr;
+  hsma_status init_scalable(std::string& err);
+  hsma_status set_box(const double lo[3], double scale, hipStream_t st, std::string& err);
+
   hsma_status init(std::string& err);
-  hsma_status prepare(int64_t n, std::string& err);
+  // Allocates the per-size arena for any particle count up to nmax.
+  hsma_status reserve(int64_t nmax, std::string& err);
+  void capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_bytes, size_t& nwork, size_t& ncwork) const;
+  hsma_status prepare(int64_t n, hipStream_t st, std::string& err);
   hsma_status run(hipStream_t st, int64_t n, const double* d_xyz, const double* d_q, double* d_energy,
                   double* d_pot, double* d_force, std::string& err);
   void free_arena();

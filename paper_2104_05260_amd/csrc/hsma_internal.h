@@ -80,4 +80,12 @@ void solid_harmonics(int p, const double xi[3], double* val, double* grad);
 // Lattice generator of the surface rule (Fibonacci or best Zaremba index).
 int lattice_generator(int F, int Fw);
 
+// Records msg as the calling thread's hsma_last_error() and returns s.
+hsma_status set_last_error(hsma_status s, const std::string& msg);
+
+// Host-side input validation of hsma_compute (finite values, neutrality,
+// slab domain) for a box with lower corner lo and lengths L.
+hsma_status validate_host_input(const hsma_params& prm, const double lo[3], const double L[3], int64_t n,
+                                const double* xyz, const double* q, std::string& msg);
+
 }  // namespace hsma

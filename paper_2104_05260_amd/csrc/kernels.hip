@@ -789,6 +789,56 @@ __global__ __launch_bounds__(256) void k_energy(int nblk, const double* __restri
   if (threadIdx.x == 0) energy[0] = 0.5 * s[0];
 }
 
+// Plan constants of a box scaled by s from the unit box the plan was built
+// for (all lengths times s): image shifts, check targets and sphere points
+// scale with s; the value columns of Praw are scale free and its field
+// columns scale with s; the sphere maps A -> Q and A -> D scale with s and
+// s^2.  blockIdx.y selects the array.
+__global__ __launch_bounds__(256) void k_scale_plan(double s, int ndp, const Desc* __restrict__ udp, Desc* __restrict__ dp,
+                                                    int ndc, const Desc* __restrict__ udc, Desc* __restrict__ dc,
+                                                    int nck, const double4* __restrict__ uck, double4* __restrict__ ck,
+                                                    long npr, const double* __restrict__ upr, double* __restrict__ pr,
+                                                    long nsq, const double* __restrict__ usq, double* __restrict__ sq,
+                                                    const double* __restrict__ usd, double* __restrict__ sd, int nys,
+                                                    const double* __restrict__ uys, double* __restrict__ ys) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  switch (blockIdx.y) {
+    case 0:
+      for (long i = i0; i < ndp; i += stride) {
+        Desc d = udp[i];
+        d.sx *= s; d.sy *= s; d.sz *= s;
+        dp[i] = d;
+      }
+      break;
+    case 1:
+      for (long i = i0; i < ndc; i += stride) {
+        Desc d = udc[i];
+        d.sx *= s; d.sy *= s; d.sz *= s;
+        dc[i] = d;
+      }
+      break;
+    case 2:
+      for (long i = i0; i < nck; i += stride) {
+        const double4 c = uck[i];
+        ck[i] = make_double4(c.x * s, c.y * s, c.z * s, c.w);
+      }
+      break;
+    case 3:
+      for (long i = i0; i < npr; i += stride) pr[i] = (i & 1) ? upr[i] * s : upr[i];
+      break;
+    case 4:
+      for (long i = i0; i < nsq; i += stride) {
+        sq[i] = usq[i] * s;
+        sd[i] = usd[i] * (s * s);
+      }
+      break;
+    default:
+      for (long i = i0; i < nys; i += stride) ys[i] = uys[i] * s;
+      break;
+  }
+}
+
 // ================================================================= host side
 #define HIPCHK(x)                                                                   \
   do {                                                                              \
@@ -859,13 +909,19 @@ void DevicePlan::free_arena() {
   d_groups = nullptr;
   d_work = d_cwork = nullptr;
   d_cg_work = nullptr;
+  if (h_stage) (void)hipHostFree(h_stage);
+  h_stage = nullptr;
   cap_n = 0;
   cur_n = -1;
+  arena_bytes = 0;
 }
 
 DevicePlan::~DevicePlan() {
   free_arena();
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  void* us[] = {d_unit_desc_part, d_unit_desc_check, d_unit_check_pos, d_unit_Praw, d_unit_SQ, d_unit_SD, d_unit_ysurf};
+  for (void* p : us)
+    if (p) (void)hipFree(p);
   void* ps[] = {d_desc_part, d_desc_check, d_check_pos, d_check_axis, d_check_groups, d_check_tgroup, d_Praw,
                 d_SQ, d_SD, d_ysurf, d_nsurf, d_v, d_A, d_surf32, d_surf64, d_qd, d_status, d_energy_scratch,
                 d_in_xyz, d_in_q, d_out_pot, d_out_force, d_out_energy};
@@ -922,8 +978,72 @@ static void make_far_work(const std::vector<Group>& groups, int ntiles, int targ
   if (nchunks_out) *nchunks_out = nch_shared;
 }
 
-hsma_status DevicePlan::prepare(int64_t n, std::string& err) {
+// Upper bounds of the per-size buffers for any particle count <= n, so that
+// an arena reserved once for n never has to grow for a smaller system.
+void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_bytes, size_t& nwork,
+                                 size_t& ncwork) const {
+  const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
+  const int64_t ngroups = (n + kGroup - 1) / kGroup;
+  const int nsc = (host.prm.F + kSphereChunk - 1) / kSphereChunk;
+  const size_t ncg = host.check_groups.size();
+  part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + (size_t)ngroups * (2 + nsc));
+  cpart_bytes = rb * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
+  nwork = (size_t)part_target + 2 * (size_t)ngroups + 2;
+  ncwork = (size_t)check_target_max + 2 * ncg + 2;
+}
+
+hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
+  if (nmax <= cap_n) return HSMA_OK;
+  free_arena();
+  const int64_t cn = std::max<int64_t>(nmax, 64);
+  const int64_t cnt = ((cn + kTile - 1) / kTile);
+  const int64_t cpad = cnt * kTile;
+  const int64_t crs = (cn + kRsBlock - 1) / kRsBlock;
+  size_t part_bytes, cpart_bytes, nwork, ncwork;
+  capacity_bounds(cn, part_bytes, cpart_bytes, nwork, ncwork);
+  const int64_t ngroups = (cn + kGroup - 1) / kGroup;
+  HIPCHK(hipMalloc((void**)&d_key[0], sizeof(uint32_t) * cn));
+  HIPCHK(hipMalloc((void**)&d_key[1], sizeof(uint32_t) * cn));
+  HIPCHK(hipMalloc((void**)&d_val[0], sizeof(int) * cn));
+  HIPCHK(hipMalloc((void**)&d_val[1], sizeof(int) * cn));
+  HIPCHK(hipMalloc((void**)&d_hist, sizeof(uint32_t) * 256 * crs));
+  HIPCHK(hipMalloc((void**)&d_pos_w, sizeof(double4) * cn));
+  HIPCHK(hipMalloc((void**)&d_pos64, sizeof(double4) * cpad));
+  HIPCHK(hipMalloc((void**)&d_src32, sizeof(float4) * cpad));
+  HIPCHK(hipMalloc((void**)&d_src64, sizeof(double4) * cpad));
+  HIPCHK(hipMalloc((void**)&d_tile_c, sizeof(double4) * cnt));
+  HIPCHK(hipMalloc((void**)&d_tile_h, sizeof(float4) * cnt));
+  HIPCHK(hipMalloc((void**)&d_perm, sizeof(int) * cpad));
+  HIPCHK(hipMalloc((void**)&d_red, sizeof(double) * 3 * ((cn + 255) / 256)));
+  HIPCHK(hipMalloc((void**)&d_epart, sizeof(double) * ((cn + 255) / 256)));
+  HIPCHK(hipMalloc(&d_part, part_bytes));
+  HIPCHK(hipMalloc(&d_cpart, cpart_bytes));
+  HIPCHK(hipMalloc((void**)&d_groups, sizeof(Group) * ngroups));
+  HIPCHK(hipMalloc((void**)&d_work, sizeof(Work) * nwork));
+  HIPCHK(hipMalloc((void**)&d_cwork, sizeof(Work) * ncwork));
+  HIPCHK(hipMalloc((void**)&d_cg_work, sizeof(int2) * std::max<size_t>(1, host.check_groups.size())));
+  const size_t stage = sizeof(Group) * ngroups + sizeof(Work) * (nwork + ncwork) +
+                       sizeof(int2) * (host.check_groups.size() + 1) + 256;
+  HIPCHK(hipHostMalloc(&h_stage, stage));
+  stage_bytes = stage;
+  cap_n = cn;
+  part_cap = part_bytes;
+  cpart_cap = cpart_bytes;
+  work_cap = nwork;
+  cwork_cap = ncwork;
+  group_cap = ngroups;
+  arena_bytes = sizeof(uint32_t) * cn * 2 + sizeof(int) * cn * 2 + sizeof(uint32_t) * 256 * crs +
+                sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
+                sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(Group) * ngroups +
+                sizeof(Work) * (nwork + ncwork);
+  cur_n = -1;
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   if (n == cur_n) return HSMA_OK;
+  hsma_status s = reserve(n, err);
+  if (s != HSMA_OK) return s;
   const int ntiles = (int)((n + kTile - 1) / kTile);
   const int ngroups = (int)((n + kGroup - 1) / kGroup);
   const int nrsblk = (int)((n + kRsBlock - 1) / kRsBlock);
@@ -941,69 +1061,46 @@ hsma_status DevicePlan::prepare(int64_t n, std::string& err) {
     err = "internal error: uneven particle work decomposition";
     return HSMA_ERR_DEVICE;
   }
+  // check work: about check_pairs_per_item pairs per wave, enough waves to
+  // fill the chip when there is that much work
+  long long cpairs = 0;
+  for (const Group& g : host.check_groups) cpairs += (long long)g.count * g.ndesc * n;
+  const int ctarget = (int)std::min<long long>(check_target_max, std::max<long long>(check_target,
+                          cpairs / std::max<long long>(1, check_pairs_per_item)));
   std::vector<int2> cgs;
-  make_far_work(host.check_groups, ntiles, check_target, false, cwork, &cgs, nullptr);
+  make_far_work(host.check_groups, ntiles, ctarget, false, cwork, &cgs, nullptr);
   int ncslots = 0;
   for (size_t gi = 0; gi < host.check_groups.size(); ++gi) {
     cnwork.push_back(Work{(int)gi, 0, host.check_groups[gi].ndesc * ntiles, cgs[gi].x + cgs[gi].y - 1});
     ncslots = std::max(ncslots, cgs[gi].x + cgs[gi].y);
   }
   const int nsc = (host.prm.F + kSphereChunk - 1) / kSphereChunk;
-  const int nslots = nch + 1 + nsc;
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
   const long comp = (long)ngroups * kGroup;
-  const size_t part_bytes = rb * 5 * (size_t)comp * nslots;
-  const size_t cpart_bytes = rb * 5 * (size_t)kGroup * ncslots;
-  if (n > cap_n || part_bytes > part_cap || cpart_bytes > cpart_cap ||
-      work.size() + nwork.size() > work_cap || cwork.size() + cnwork.size() > cwork_cap) {
-    free_arena();
-    const int64_t cn = std::max<int64_t>(n, 64);
-    const int64_t cnt = ((cn + kTile - 1) / kTile);
-    const int64_t cpad = cnt * kTile;
-    const int64_t crs = (cn + kRsBlock - 1) / kRsBlock;
-    HIPCHK(hipMalloc((void**)&d_key[0], sizeof(uint32_t) * cn));
-    HIPCHK(hipMalloc((void**)&d_key[1], sizeof(uint32_t) * cn));
-    HIPCHK(hipMalloc((void**)&d_val[0], sizeof(int) * cn));
-    HIPCHK(hipMalloc((void**)&d_val[1], sizeof(int) * cn));
-    HIPCHK(hipMalloc((void**)&d_hist, sizeof(uint32_t) * 256 * crs));
-    HIPCHK(hipMalloc((void**)&d_pos_w, sizeof(double4) * cn));
-    HIPCHK(hipMalloc((void**)&d_pos64, sizeof(double4) * cpad));
-    HIPCHK(hipMalloc((void**)&d_src32, sizeof(float4) * cpad));
-    HIPCHK(hipMalloc((void**)&d_src64, sizeof(double4) * cpad));
-    HIPCHK(hipMalloc((void**)&d_tile_c, sizeof(double4) * cnt));
-    HIPCHK(hipMalloc((void**)&d_tile_h, sizeof(float4) * cnt));
-    HIPCHK(hipMalloc((void**)&d_perm, sizeof(int) * cpad));
-    HIPCHK(hipMalloc((void**)&d_red, sizeof(double) * 3 * ((cn + 255) / 256)));
-    HIPCHK(hipMalloc((void**)&d_epart, sizeof(double) * ((cn + 255) / 256)));
-    HIPCHK(hipMalloc(&d_part, part_bytes));
-    HIPCHK(hipMalloc(&d_cpart, std::max<size_t>(cpart_bytes, 64)));
-    HIPCHK(hipMalloc((void**)&d_groups, sizeof(Group) * groups.size()));
-    HIPCHK(hipMalloc((void**)&d_work, sizeof(Work) * (work.size() + nwork.size())));
-    HIPCHK(hipMalloc((void**)&d_cwork, sizeof(Work) * std::max<size_t>(1, cwork.size() + cnwork.size())));
-    HIPCHK(hipMalloc((void**)&d_cg_work, sizeof(int2) * std::max<size_t>(1, cgs.size())));
-    cap_n = cn;
-    part_cap = part_bytes;
-    cpart_cap = cpart_bytes;
-    work_cap = work.size() + nwork.size();
-    cwork_cap = cwork.size() + cnwork.size();
-    group_cap = groups.size();
+  if (rb * 5 * (size_t)comp * (nch + 1 + nsc) > part_cap || rb * 5 * (size_t)kGroup * ncslots > cpart_cap ||
+      work.size() + nwork.size() > work_cap || cwork.size() + cnwork.size() > cwork_cap ||
+      groups.size() > group_cap) {
+    err = "internal error: work decomposition exceeds the reserved arena";
+    return HSMA_ERR_DEVICE;
   }
-  if (groups.size() > group_cap) {
-    if (d_groups) (void)hipFree(d_groups);
-    HIPCHK(hipMalloc((void**)&d_groups, sizeof(Group) * groups.size()));
-    group_cap = groups.size();
-  }
-  // far items first, near items after them, in one array each
-  std::vector<Work> all = work;
-  all.insert(all.end(), nwork.begin(), nwork.end());
-  std::vector<Work> call = cwork;
-  call.insert(call.end(), cnwork.begin(), cnwork.end());
-  HIPCHK(hipMemcpy(d_groups, groups.data(), sizeof(Group) * groups.size(), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(d_work, all.data(), sizeof(Work) * all.size(), hipMemcpyHostToDevice));
-  if (!call.empty()) {
-    HIPCHK(hipMemcpy(d_cwork, call.data(), sizeof(Work) * call.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d_cg_work, cgs.data(), sizeof(int2) * cgs.size(), hipMemcpyHostToDevice));
-  }
+  // stage the tables in pinned memory and copy them on the call's stream;
+  // the stream is drained first so that the staging buffer is free
+  HIPCHK(hipStreamSynchronize(st));
+  char* h = (char*)h_stage;
+  size_t off = 0;
+  auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    std::memcpy(h + off, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, h + off, bytes, hipMemcpyHostToDevice, st);
+    off += (bytes + 15) & ~size_t(15);
+    return e;
+  };
+  HIPCHK(put(d_groups, groups.data(), sizeof(Group) * groups.size()));
+  HIPCHK(put(d_work, work.data(), sizeof(Work) * work.size()));
+  HIPCHK(put(d_work + work.size(), nwork.data(), sizeof(Work) * nwork.size()));
+  if (!cwork.empty()) HIPCHK(put(d_cwork, cwork.data(), sizeof(Work) * cwork.size()));
+  if (!cnwork.empty()) HIPCHK(put(d_cwork + cwork.size(), cnwork.data(), sizeof(Work) * cnwork.size()));
+  if (!cgs.empty()) HIPCHK(put(d_cg_work, cgs.data(), sizeof(int2) * cgs.size()));
+  HIPCHK(hipStreamSynchronize(st));
   cur_n = n;
   ntiles_ = ntiles;
   ngroups_ = ngroups;
@@ -1036,7 +1133,7 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
     err = "too many particles for one call";
     return HSMA_ERR_INVALID_ARG;
   }
-  hsma_status s = prepare(n64, err);
+  hsma_status s = prepare(n64, st, err);
   if (s != HSMA_OK) return s;
   const int n = (int)n64;
   const bool fp64 = host.prm.precision == HSMA_FP64;
@@ -1124,6 +1221,56 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   for (const Group& g : host.check_groups) cp += (long long)g.count * g.ndesc * n;
   check_pairs = cp;
   sphere_pairs = (long long)n * F;
+  return HSMA_OK;
+}
+
+
+// Keeps a copy of the plan constants for the unit box so that the plan can
+// be re-targeted to any box len = s * unit_len with one kernel.
+hsma_status DevicePlan::init_scalable(std::string& err) {
+  if (scalable) return HSMA_OK;
+  const size_t ndp = host.desc_particles.size(), ndc = host.desc_check.size(), nck = host.check_axis.size();
+  const size_t npr = host.Praw.size(), nsq = host.SQ.size(), nys = host.ysurf.size();
+  HIPCHK(hipMalloc((void**)&d_unit_desc_part, sizeof(Desc) * std::max<size_t>(1, ndp)));
+  HIPCHK(hipMalloc((void**)&d_unit_desc_check, sizeof(Desc) * std::max<size_t>(1, ndc)));
+  HIPCHK(hipMalloc((void**)&d_unit_check_pos, sizeof(double4) * std::max<size_t>(1, nck)));
+  HIPCHK(hipMalloc((void**)&d_unit_Praw, sizeof(double) * std::max<size_t>(1, npr)));
+  HIPCHK(hipMalloc((void**)&d_unit_SQ, sizeof(double) * std::max<size_t>(1, nsq)));
+  HIPCHK(hipMalloc((void**)&d_unit_SD, sizeof(double) * std::max<size_t>(1, nsq)));
+  HIPCHK(hipMalloc((void**)&d_unit_ysurf, sizeof(double) * std::max<size_t>(1, nys)));
+  HIPCHK(hipMemcpy(d_unit_desc_part, d_desc_part, sizeof(Desc) * ndp, hipMemcpyDeviceToDevice));
+  if (ndc) HIPCHK(hipMemcpy(d_unit_desc_check, d_desc_check, sizeof(Desc) * ndc, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(d_unit_check_pos, d_check_pos, sizeof(double4) * nck, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(d_unit_Praw, d_Praw, sizeof(double) * npr, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(d_unit_SQ, d_SQ, sizeof(double) * nsq, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(d_unit_SD, d_SD, sizeof(double) * nsq, hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemcpy(d_unit_ysurf, d_ysurf, sizeof(double) * nys, hipMemcpyDeviceToDevice));
+  for (int k = 0; k < 3; ++k) unit_L[k] = host.L[k];
+  unit_R = host.R;
+  scalable = true;
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::set_box(const double lo[3], double scale, hipStream_t st, std::string& err) {
+  if (!scalable) {
+    err = "plan is not scalable";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < 3; ++k) {
+    host.lo[k] = lo[k];
+    host.L[k] = unit_L[k] * scale;
+  }
+  host.R = unit_R * scale;
+  if (scale == cur_scale) return HSMA_OK;
+  const long npr = (long)host.Praw.size(), nsq = (long)host.SQ.size();
+  hipLaunchKernelGGL(k_scale_plan, dim3(16, 6), dim3(256), 0, st, scale, (int)host.desc_particles.size(),
+                     (const Desc*)d_unit_desc_part, d_desc_part, (int)host.desc_check.size(),
+                     (const Desc*)d_unit_desc_check, d_desc_check, (int)host.check_axis.size(),
+                     (const double4*)d_unit_check_pos, d_check_pos, npr, (const double*)d_unit_Praw, d_Praw, nsq,
+                     (const double*)d_unit_SQ, d_SQ, (const double*)d_unit_SD, d_SD, (int)host.ysurf.size(),
+                     (const double*)d_unit_ysurf, d_ysurf);
+  HIPCHK(hipGetLastError());
+  cur_scale = scale;
   return HSMA_OK;
 }
 

@@ -54,6 +54,22 @@ class _CTiming(ctypes.Structure):
                 ("near_ms", ctypes.c_double), ("sphere_ms", ctypes.c_double)]
 
 
+class _CServerCfg(ctypes.Structure):
+    _fields_ = [("params", _CParams), ("box_len", ctypes.c_double * 3), ("max_n", ctypes.c_int64),
+                ("max_slots", ctypes.c_int), ("hbm_budget", ctypes.c_int64), ("queue_capacity", ctypes.c_int)]
+
+
+class _CRequest(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("box_lo", ctypes.c_double * 3), ("scale", ctypes.c_double), ("potential", ctypes.c_void_p),
+                ("force", ctypes.c_void_p)]
+
+
+class _CResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("energy", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("slot", ctypes.c_int)]
+
+
 @dataclass
 class Params:
     geometry: int = GEOM_3D
@@ -133,6 +149,14 @@ def load_library():
     lib.hsma_debug_host_plan_destroy.argtypes = [vp]
     lib.hsma_debug_host_plan_get.argtypes = [vp, ctypes.c_char_p, d, i64]
     lib.hsma_debug_host_plan_get.restype = i64
+    lib.hsma_server_create.argtypes = [ctypes.POINTER(_CServerCfg), ctypes.POINTER(vp)]
+    lib.hsma_server_submit.argtypes = [vp, ctypes.POINTER(_CRequest), ctypes.POINTER(ctypes.c_uint64)]
+    lib.hsma_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(_CResult)]
+    lib.hsma_server_get_slots.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
+    lib.hsma_server_destroy.argtypes = [vp]
+    lib.hsma_server_shutdown.argtypes = [vp]
+    for name in ("hsma_server_create", "hsma_server_submit", "hsma_server_wait", "hsma_server_get_slots"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.hsma_debug_hilbert_key.argtypes = [ctypes.c_uint32] * 3
     lib.hsma_debug_hilbert_key.restype = ctypes.c_uint32
     for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_plan_device_status",
@@ -264,6 +288,82 @@ class Plan:
         if self._p:
             self._lib.hsma_plan_destroy(self._p)
             self._p = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server for one plan class (hsma_server_*)."""
+
+    def __init__(self, params: Params, box_len, max_n: int, max_slots: int = 8, hbm_budget: int = 0,
+                 queue_capacity: int = 0):
+        lib = load_library()
+        self._lib = lib
+        self._s = ctypes.c_void_p()
+        cfg = _CServerCfg()
+        cfg.params = params._c()
+        for k in range(3):
+            cfg.box_len[k] = float(box_len[k])
+        cfg.max_n = int(max_n)
+        cfg.max_slots = int(max_slots)
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.queue_capacity = int(queue_capacity)
+        _check(lib.hsma_server_create(ctypes.byref(cfg), ctypes.byref(self._s)))
+        self._keep = {}
+
+    def slots(self):
+        n, b = ctypes.c_int(), ctypes.c_int64()
+        _check(self._lib.hsma_server_get_slots(self._s, ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def submit(self, xyz, q, box_lo, scale: float, potential: bool = True, force: bool = True) -> int:
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        n = x.shape[0]
+        pot = np.zeros(n) if potential else None
+        f = np.zeros((n, 3)) if force else None
+        r = _CRequest()
+        r.n = n
+        r.xyz = x.ctypes.data
+        r.q = qq.ctypes.data
+        for k in range(3):
+            r.box_lo[k] = float(box_lo[k])
+        r.scale = float(scale)
+        r.potential = pot.ctypes.data if pot is not None else None
+        r.force = f.ctypes.data if f is not None else None
+        t = ctypes.c_uint64()
+        _check(self._lib.hsma_server_submit(self._s, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (x, qq, pot, f)
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        res = _CResult()
+        st = self._lib.hsma_server_wait(self._s, ctypes.c_uint64(ticket), ctypes.byref(res))
+        _, _, pot, f = self._keep.pop(ticket, (None, None, None, None))
+        out = {k[0]: getattr(res, k[0]) for k in _CResult._fields_}
+        out["status_name"] = STATUS.get(st, str(st))
+        out["potential"], out["force"] = pot, f
+        return out
+
+    def shutdown(self):
+        """Cancel queued requests, finish admitted ones; wait() still works."""
+        if self._s:
+            self._lib.hsma_server_shutdown(self._s)
+
+    def close(self):
+        if self._s:
+            self._lib.hsma_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
 
     def __enter__(self):
         return self

@@ -200,3 +200,54 @@ def test_c2_full_size_sampled():
     assert rel_rms(res[1][2], res[0][2]) <= 1e-5
     # net force of a periodic system vanishes within the method error
     assert np.abs(res[0][2].sum(0)).max() <= 1e-4 * np.sqrt((res[0][2] ** 2).sum())
+
+
+def test_c3_slab_full_size_sampled():
+    """The 20,000-ion dielectric slab (gamma = -0.94, M = 10 image layers,
+    80 x 80 interface grids) against the oracle at 256 sampled particles."""
+    w = workloads.C3
+    pos, q, lo, L = workloads.make_system(w)
+    sample = np.random.default_rng(6).choice(w.n, 256, replace=False)
+    note("[parity] C3 oracle (sampled)")
+    r = _sampled_oracle(w, hs.Params.from_workload(w), pos, q, lo, L, sample)
+    res = {}
+    for prec in (1, 0):
+        note(f"[parity] C3 gpu precision={prec}")
+        e, pot, f = run_gpu(hs.Params.from_workload(w, precision=prec), pos, q, lo, L)
+        res[prec] = (e, pot, f)
+        dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
+        df = rel_rms(f[sample], r.force)
+        note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}")
+        if prec == 0:
+            assert dp < 1e-10 and df < 1e-10
+        else:
+            assert dp < 1e-5 and df < 1e-5
+    e32, e64 = res[1][0], res[0][0]
+    S = 0.5 * np.abs(q * res[0][1]).sum()
+    scale = abs(e64) if abs(e64) >= 0.01 * S else S
+    note(f"   energy fp32c {e32:.12g} fp64 {e64:.12g} rel {abs(e32 - e64) / abs(e64):.2e}; S {S:.6g}")
+    assert abs(e32 - e64) <= 1e-6 * scale
+    assert rel_rms(res[1][2], res[0][2]) <= 1e-5
+    # in-plane net force vanishes within the method error
+    f64 = res[0][2]
+    assert np.abs(f64[:, :2].sum(0)).max() <= 1e-3 * np.sqrt((f64 ** 2).sum())
+
+
+def test_c5_million_ions_sampled():
+    """999,999 ions (2:1 valence) in L = 200, p = 12, F = 1152, K = 800:
+    the FP32 compensated path against the oracle at 128 sampled particles
+    (the oracle's check sums and fit use every particle)."""
+    w = workloads.C5
+    pos, q, lo, L = workloads.make_system(w)
+    sample = np.random.default_rng(7).choice(w.n, 128, replace=False)
+    note("[parity] C5 gpu fp32c")
+    e, pot, f = run_gpu(hs.Params.from_workload(w, precision=1), pos, q, lo, L)
+    note("[parity] C5 oracle (sampled)")
+    r = _sampled_oracle(w, hs.Params.from_workload(w), pos, q, lo, L, sample)
+    dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
+    df = rel_rms(f[sample], r.force)
+    dfm = np.abs(f[sample] - r.force).max() / np.abs(r.force).max()
+    note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}, force max rel {dfm:.2e}")
+    assert dp < 1e-5 and df < 1e-5
+    assert np.isfinite(e)
+    assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())

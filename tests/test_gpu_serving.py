@@ -1,0 +1,123 @@
+"""Serving form on the GPU: continuous batching of independent systems."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import hsma as ohsma
+
+pytestmark = pytest.mark.gpu
+
+hs = pytest.importorskip("paper_2104_05260_amd")
+
+UNIT = (1.0, 1.0, 1.0)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def mix(count=6, seed0=2000, n_lo=300, n_hi=3000):
+    """Serving-shaped systems: N uniform, L = (N / 0.05)^(1/3), +-1."""
+    ws = workloads.serving_systems(count, n_lo, n_hi, seed0=seed0)
+    out = []
+    for w in ws:
+        pos, q, lo, L = workloads.make_system(w)
+        out.append((w, pos + 1.5, q, lo + 1.5, L[0]))
+    return ws[0], out
+
+
+def params(prec=1):
+    return hs.Params(precision=prec, p=8, K=162, F=512, lam=1.5)
+
+
+def test_alone_equals_mix_bitwise():
+    w0, systems = mix()
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    note(f"[serving] {len(systems)} systems, n up to {nmax}")
+    with hs.Server(params(), UNIT, max_n=nmax, max_slots=4) as sv:
+        alone = []
+        for _, pos, q, lo, L in systems:
+            alone.append(sv.wait(sv.submit(pos, q, lo, L)))
+        tickets = [sv.submit(pos, q, lo, L) for _, pos, q, lo, L in systems]
+        together = [sv.wait(t) for t in tickets]
+    slots_used = {r["slot"] for r in together}
+    note(f"   slots used in the mix: {sorted(slots_used)}")
+    assert len(slots_used) > 1
+    for a, b in zip(alone, together):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["energy"] == b["energy"]
+        assert np.array_equal(a["potential"], b["potential"]) and np.array_equal(a["force"], b["force"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_served_results_match_plan_and_oracle(prec):
+    _, systems = mix(count=3, seed0=2100)
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    with hs.Server(params(prec), UNIT, max_n=nmax, max_slots=3) as sv:
+        tickets = [sv.submit(pos, q, lo, L) for _, pos, q, lo, L in systems]
+        res = [sv.wait(t) for t in tickets]
+    for (w, pos, q, lo, L), r in zip(systems, res):
+        ref = ohsma.hsma3d(pos, q, lo, np.array([L, L, L]), 8, 162, 512, 1.5)
+        with hs.Plan(params(prec), lo, [L, L, L]) as plan:
+            e1, p1, f1 = plan.compute(pos, q)
+        de = abs(r["energy"] - ref.energy)
+        S = 0.5 * np.abs(q * ref.potential).sum()
+        df = np.sqrt(((r["force"] - ref.force) ** 2).sum() / (ref.force ** 2).sum())
+        note(f"   n={len(q)} L={L:.3f}: energy {r['energy']:.12g} oracle {ref.energy:.12g} dE/S {de / S:.2e} "
+             f"force rel {df:.2e}; vs direct plan dE {abs(r['energy'] - e1):.2e}")
+        if prec == 0:
+            assert de <= 1e-10 * S and df <= 1e-10
+        else:
+            assert de <= 1e-6 * S and df <= 1e-5
+        # a server slot re-targets a unit-box plan; a plan built for the box
+        # itself agrees to rounding
+        assert abs(r["energy"] - e1) <= 1e-10 * S
+        assert np.abs(r["force"] - f1).max() <= 1e-6 * np.abs(f1).max()
+
+
+def test_budget_and_per_request_errors():
+    _, systems = mix(count=4, seed0=2200)
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    with hs.Server(params(), UNIT, max_n=nmax, max_slots=8) as probe:
+        n_full, per = probe.slots()
+    note(f"   bytes per slot {per}, slots with default budget {n_full}")
+    # a budget of two slots admits two requests at a time; everything completes
+    with hs.Server(params(), UNIT, max_n=nmax, max_slots=8, hbm_budget=2 * per + per // 2) as sv:
+        assert sv.slots()[0] == 2
+        big = np.zeros((nmax + 1, 3))
+        qbig = np.zeros(nmax + 1)
+        with pytest.raises(hs.HSMAError) as e:
+            sv.submit(big, qbig, (0, 0, 0), 10.0)
+        assert e.value.name == "HSMA_ERR_OOM"
+        w, pos, q, lo, L = systems[0]
+        with pytest.raises(hs.HSMAError) as e:
+            sv.submit(pos, q + 0.5, lo, L)
+        assert e.value.name == "HSMA_ERR_NOT_NEUTRAL"
+        tickets = [sv.submit(pos, q, lo, L) for _, pos, q, lo, L in systems]
+        res = [sv.wait(t) for t in tickets]
+        assert all(r["status"] == 0 for r in res)
+        assert {r["slot"] for r in res} <= {0, 1}
+    with pytest.raises(hs.HSMAError) as e:
+        hs.Server(params(), UNIT, max_n=nmax, max_slots=2, hbm_budget=per // 2)
+    assert e.value.name == "HSMA_ERR_OOM"
+
+
+def test_shutdown_cancels_queued_requests():
+    _, systems = mix(count=3, seed0=2300, n_lo=2000, n_hi=3000)
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    sv = hs.Server(params(0), UNIT, max_n=nmax, max_slots=1)
+    tickets = []
+    for _ in range(10):
+        for _, pos, q, lo, L in systems:
+            tickets.append(sv.submit(pos, q, lo, L))
+    sv.shutdown()
+    with pytest.raises(hs.HSMAError) as e:
+        sv.submit(systems[0][1], systems[0][2], systems[0][3], systems[0][4])
+    assert e.value.name == "HSMA_ERR_CANCELLED"
+    codes = [sv.wait(t)["status"] for t in tickets]
+    note(f"   statuses after shutdown: {codes.count(0)} done, {codes.count(-10)} cancelled")
+    assert set(codes) <= {0, -10} and codes.count(-10) >= 1
+    sv.close()
