@@ -19,9 +19,9 @@ struct DevicePlan {
 
   // tuning of the work decomposition
   int part_target = 32768;     // waves per particle pair launch (about)
-  int check_target = 1024;     // minimum waves per check pair launch (about)
+  int check_target = 2048;     // minimum waves per check pair launch (about)
   int check_target_max = 65536;
-  long long check_pairs_per_item = 400000;
+  long long check_pairs_per_item = 100000;
   double close_factor = 0.1;   // close-pair radius / typical tile extent (FP32 path)
 
   // plan constants on the device

@@ -389,7 +389,29 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       pp[j] = qx[j] = qy[j] = qz[j] = (Real)0;
     }
     const S* __restrict__ s = src + (long)tile * kTile;
-    if constexpr (!NEAR) {
+    if (!NEAR && PARTICLES && own) {
+      // a far tile that holds the group's own particles under a shifted
+      // image: drop each target's own image (summed in FP64 by finalize)
+      for (int k = 0; k < kTile; ++k) {
+        const S v = s[k];
+        const long si = (long)tile * kTile + k;
+#pragma unroll
+        for (int j = 0; j < kTPL; ++j) {
+          const bool self = si == (long)(tbase + j * kWave);
+          const Real dx = ux[j] - (Real)v.x;
+          const Real dy = uy[j] - (Real)v.y;
+          const Real dz = uz[j] - (Real)v.z;
+          const Real r2 = self ? (Real)1 : dx * dx + dy * dy + dz * dz;
+          const Real ri = rsq(r2);
+          const Real a = (self ? (Real)0 : (Real)v.w) * ri;
+          pp[j] += a;
+          const Real b = a * (ri * ri);
+          qx[j] += b * dx;
+          qy[j] += b * dy;
+          qz[j] += b * dz;
+        }
+      }
+    } else if constexpr (!NEAR) {
 #pragma unroll HSMA_FAR_UNROLL
       for (int k = 0; k < kTile; ++k) {
         const S v = s[k];
@@ -459,10 +481,11 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     }
   };
 
-  // The group's own tiles (which hold the targets themselves) go through
-  // the near kernel under every image, so that a target never meets itself
-  // or its own images in the FP32 loop: those terms share one distance for
-  // all particles and their rounding would not average out.
+  // The group's own tiles hold the targets themselves: under every image a
+  // target must not meet itself or its own image in the FP32 sums (those
+  // terms share one distance for all particles, so their rounding would not
+  // average out; finalize sums them in FP64).  Near kernel and far kernel
+  // both drop source index == target index inside own tiles.
   const int own0 = PARTICLES ? g.first / kTile : 0;
   const int own1 = PARTICLES ? (g.first + g.count - 1) / kTile : -1;
 
@@ -478,14 +501,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     const bool img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
                                  __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
     if constexpr (NEAR) {
-      if (img_far) {
-        for (int nt = max(t0, own0); nt <= min(t1 - 1, own1); ++nt) {
-          const double4 cs = tile_c[nt];
-          do_tile(ds, true, nt, __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
-                  shifted_dz(ds, cs.z, cgz));
-        }
-        continue;
-      }
+      if (img_far) continue;
       // lane-parallel scan: lane l classifies tile tb + l, then the wave
       // walks the near ones in increasing tile order
       for (int tb = t0; tb < t1; tb += kWave) {
@@ -497,8 +513,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
           const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
           const double dlz = shifted_dz(ds, cs.z, cgz);
-          near = (tile >= own0 && tile <= own1) ||
-                 gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+          near = gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
                          __dadd_rn(hgz, (double)hs.z)) < rc2;
         }
         unsigned long long m = __ballot(near);
@@ -515,7 +530,6 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       }
     } else {
       for (int tile = t0; tile < t1; ++tile) {
-        if (tile >= own0 && tile <= own1) continue;  // summed by the near pass
         const double4 cs = tile_c[tile];
         const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
         const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
@@ -526,7 +540,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                       __dadd_rn(hgz, (double)hs.z)) < rc2)
             continue;  // summed by the near pass
         }
-        do_tile(ds, false, tile, dlx, dly, dlz);
+        do_tile(ds, tile >= own0 && tile <= own1, tile, dlx, dly, dlz);
       }
     }
   }
