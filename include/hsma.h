@@ -145,6 +145,16 @@ typedef struct hsma_timing {
 hsma_status hsma_plan_set_timing(hsma_plan* plan, int enable);
 hsma_status hsma_plan_get_timing(hsma_plan* plan, hsma_timing* out);
 
+/* Step graphs (default off).  When on, a device call on a non-NULL stream
+ * that repeats the previous call's particle count, buffers and stream is
+ * captured once into a HIP graph (on that second call) and replayed on
+ * later calls, so a repeated step costs one graph launch instead of ~20
+ * kernel launches.  Positions, charges and box may change between calls:
+ * the graph reads them from the buffers and from a device parameter block
+ * written by an ordinary launch before each replay.  Results are identical
+ * to eager execution.  Timing (hsma_plan_set_timing) forces eager launches. */
+hsma_status hsma_plan_set_graph(hsma_plan* plan, int enable);
+
 /* Thread-local description of the last error on this thread.               */
 const char* hsma_last_error(void);
 

@@ -230,6 +230,12 @@ hsma_status hsma_plan_get_timing(hsma_plan* plan, hsma_timing* out) {
   return HSMA_OK;
 }
 
+hsma_status hsma_plan_set_graph(hsma_plan* plan, int enable) {
+  if (!plan) return fail(HSMA_ERR_INVALID_ARG, "NULL plan");
+  plan->dev.use_graph = enable != 0;
+  return HSMA_OK;
+}
+
 hsma_status hsma_plan_get_info(const hsma_plan* plan, hsma_plan_info* info) {
   if (!plan || !info) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
   const hsma::HostPlan& h = plan->dev.host;

@@ -12,6 +12,17 @@ namespace hsma {
 
 constexpr int kMaxTimedCalls = 4096;
 
+// What a captured step graph depends on.
+struct GraphKey {
+  int64_t n = -1;
+  const void *xyz = nullptr, *q = nullptr, *energy = nullptr, *pot = nullptr, *force = nullptr;
+  hipStream_t stream = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return n == o.n && xyz == o.xyz && q == o.q && energy == o.energy && pot == o.pot && force == o.force &&
+           stream == o.stream;
+  }
+};
+
 struct DevicePlan {
   HostPlan host;
   int device = 0;
@@ -103,6 +114,15 @@ struct DevicePlan {
   double* d_unit_ysurf = nullptr;
   hsma_status init_scalable(std::string& err);
   hsma_status set_box(const double lo[3], double scale, hipStream_t st, std::string& err);
+
+  // step-parameter block and graph replay
+  void* d_sp = nullptr;
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey, last_key;
+  long long graph_replays = 0;
+  hsma_status enqueue_step(hipStream_t st, int n, const double* d_xyz, const double* d_q, double* d_energy,
+                           double* d_pot, double* d_force, std::string& err);
 
   hsma_status init(std::string& err);
   // Allocates the per-size arena for any particle count up to nmax.

@@ -83,15 +83,30 @@ __host__ __device__ inline uint32_t hilbert_key3(uint32_t x, uint32_t y, uint32_
 
 uint32_t hilbert_key_host(uint32_t x, uint32_t y, uint32_t z) { return hilbert_key3(x, y, z); }
 
+// Box-dependent scalars of one step, read from device memory by the
+// kernels so that a captured step graph does not depend on the box.
+struct StepParams {
+  double3 lo, L, hbox;
+  double rc2;
+};
+
+__global__ void k_set_params(StepParams* sp, double3 lo, double3 L, double3 hbox, double rc2) {
+  sp->lo = lo;
+  sp->L = L;
+  sp->hbox = hbox;
+  sp->rc2 = rc2;
+}
+
 // ----------------------------------------------------------------- ingest
 // Centred, wrapped FP64 positions + charge; 30-bit Hilbert key of a 1024^3
 // cell grid; per-block partial sums (sum q, sum |q|, invalid count).
 __global__ __launch_bounds__(256) void k_ingest(int n, const double* __restrict__ xyz, const double* __restrict__ q,
-                                                double3 lo, double3 L, int slab, double4* __restrict__ pos,
+                                                const StepParams* __restrict__ sp, int slab, double4* __restrict__ pos,
                                                 uint32_t* __restrict__ key, int* __restrict__ val,
                                                 double* __restrict__ red) {
   __shared__ double s0[256], s1[256], s2[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
+  const double3 lo = sp->lo, L = sp->L;
   double sq = 0, sa = 0, bad = 0;
   if (i < n) {
     double x = xyz[3 * (size_t)i] - (lo.x + 0.5 * L.x);
@@ -338,11 +353,13 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                                              int ntiles, const double4* __restrict__ tile_c,
                                              const float4* __restrict__ tile_h,
                                              const typename SrcT<Real>::T* __restrict__ src,
-                                             const double4* __restrict__ pos64, double3 hbox, double rc2,
+                                             const double4* __restrict__ pos64, const StepParams* __restrict__ sp,
                                              Real* __restrict__ part, long comp_stride, long slot_stride) {
   typedef typename SrcT<Real>::T S;
   const Work w = work[blockIdx.x];
   const Group g = groups[w.group];
+  const double3 hbox = sp->hbox;
+  const double rc2 = sp->rc2;
   const int lane = threadIdx.x;
   bool valid[kTPL];
   Real ox[kTPL], oy[kTPL], oz[kTPL];
@@ -901,6 +918,7 @@ hsma_status DevicePlan::init(std::string& err) {
   HIPCHK(hipMalloc((void**)&d_status, sizeof(int)));
   HIPCHK(hipMemset(d_status, 0, sizeof(int)));
   HIPCHK(hipMalloc((void**)&d_energy_scratch, sizeof(double)));
+  HIPCHK(hipMalloc(&d_sp, sizeof(StepParams)));
   return HSMA_OK;
 }
 
@@ -931,6 +949,8 @@ void DevicePlan::free_arena() {
 }
 
 DevicePlan::~DevicePlan() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (d_sp) (void)hipFree(d_sp);
   free_arena();
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   void* us[] = {d_unit_desc_part, d_unit_desc_check, d_unit_check_pos, d_unit_Praw, d_unit_SQ, d_unit_SD, d_unit_ysurf};
@@ -1008,6 +1028,12 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
 
 hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   if (nmax <= cap_n) return HSMA_OK;
+  if (gexec) {
+    (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+  gkey = GraphKey();
+  last_key = GraphKey();
   free_arena();
   const int64_t cn = std::max<int64_t>(nmax, 64);
   const int64_t cnt = ((cn + kTile - 1) / kTile);
@@ -1056,6 +1082,7 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
 
 hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   if (n == cur_n) return HSMA_OK;
+  gkey = GraphKey();  // the captured step used the tables of another size
   hsma_status s = reserve(n, err);
   if (s != HSMA_OK) return s;
   const int ntiles = (int)((n + kTile - 1) / kTile);
@@ -1141,23 +1168,16 @@ hsma_status DevicePlan::record(hipStream_t st, int stage, int edge, std::string&
   return HSMA_OK;
 }
 
-hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, const double* d_q, double* d_energy,
-                            double* d_pot, double* d_force, std::string& err) {
-  if (n64 > (int64_t)0x3fffffff) {
-    err = "too many particles for one call";
-    return HSMA_ERR_INVALID_ARG;
-  }
-  hsma_status s = prepare(n64, st, err);
-  if (s != HSMA_OK) return s;
-  const int n = (int)n64;
+// The kernels of one step, in order, on stream st (no host synchronisation:
+// this sequence is what a step graph captures).
+hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz, const double* d_q,
+                                     double* d_energy, double* d_pot, double* d_force, std::string& err) {
+  hsma_status s = HSMA_OK;
   const bool fp64 = host.prm.precision == HSMA_FP64;
-  const double3 lo = make_double3(host.lo[0], host.lo[1], host.lo[2]);
-  const double3 L = make_double3(host.L[0], host.L[1], host.L[2]);
-  const double3 hbox = make_double3(0.5 * host.L[0], 0.5 * host.L[1], 0.5 * host.L[2]);
   const int slab = host.prm.geometry == HSMA_GEOM_2D;
   const int nblk = (n + 255) / 256;
   if ((s = record(st, kStStep, 0, err)) != HSMA_OK) return s;
-  hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(256), 0, st, n, d_xyz, d_q, lo, L, slab, d_pos_w, d_key[0],
+  hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(256), 0, st, n, d_xyz, d_q, (const StepParams*)d_sp, slab, d_pos_w, d_key[0],
                      d_val[0], d_red);
   hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, nblk, (const double*)d_red, d_status);
   // radix sort: 4 passes of 8 bits over the 30-bit keys (result back in buffer 0)
@@ -1171,12 +1191,6 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   }
   hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
                      d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
-  // close-pair radius: a tenth of a typical tile extent (FP32 path); the
-  // FP64 path needs the near pass only to drop the self pair
-  const double vol = host.L[0] * host.L[1] * host.L[2];
-  const double ext = std::cbrt(kTile * vol / std::max(1, n));
-  const double rc = fp64 ? 1e-9 * ext : close_factor * ext;
-  const double rc2 = rc * rc;
   const int ncheck = (int)host.check_axis.size();
   const int ncg = (int)host.check_groups.size();
   const long ccomp = kGroup, cslot = 5L * kGroup;
@@ -1189,11 +1203,11 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
     hipLaunchKernelGGL((k_pair<Real, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,   \
                        (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,      \
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
-                       hbox, rc2, (Real*)d_cpart, ccomp, cslot);                                                    \
+                       (const StepParams*)d_sp, (Real*)d_cpart, ccomp, cslot);                                                    \
     hipLaunchKernelGGL((k_pair<Real, true, false>), dim3(ncnear_), dim3(64), 0, st, (const double4*)d_check_pos,    \
                        (const Group*)d_check_groups, (const Work*)(d_cwork + ncwork_), (const Desc*)d_desc_check,   \
                        ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC,                   \
-                       (const double4*)d_pos64, hbox, rc2, (Real*)d_cpart, ccomp, cslot);                           \
+                       (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_cpart, ccomp, cslot);                           \
     if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;                                                    \
     hipLaunchKernelGGL(k_reduce_check<Real>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,      \
                        (const int2*)d_cg_work, (const int*)d_check_axis, (const Real*)d_cpart, d_v);                \
@@ -1206,12 +1220,12 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
     hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(nwork_), dim3(64), 0, st, (const double4*)d_pos64,         \
                        (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,              \
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
-                       hbox, rc2, (Real*)d_part, comp, slot);                                                       \
+                       (const StepParams*)d_sp, (Real*)d_part, comp, slot);                                                       \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(nnear_), dim3(64), 0, st, (const double4*)d_pos64,          \
                        (const Group*)d_groups, (const Work*)(d_work + nwork_), (const Desc*)d_desc_part, ntiles_,   \
                        (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
-                       hbox, rc2, (Real*)d_part, comp, slot);                                                       \
+                       (const StepParams*)d_sp, (Real*)d_part, comp, slot);                                                       \
     if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;                                                   \
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
                        (const double4*)d_surf64, F, (Real*)d_part, comp, nchunks_ + 1);                             \
@@ -1229,12 +1243,73 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   HIPCHK(hipGetLastError());
   if ((s = record(st, kStStep, 1, err)) != HSMA_OK) return s;
   if (timing && timed_calls < kMaxTimedCalls) ++timed_calls;
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, const double* d_q, double* d_energy,
+                            double* d_pot, double* d_force, std::string& err) {
+  if (n64 > (int64_t)0x3fffffff) {
+    err = "too many particles for one call";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  hsma_status s = prepare(n64, st, err);
+  if (s != HSMA_OK) return s;
+  const int n = (int)n64;
+  const bool fp64 = host.prm.precision == HSMA_FP64;
+  const double3 lo = make_double3(host.lo[0], host.lo[1], host.lo[2]);
+  const double3 L = make_double3(host.L[0], host.L[1], host.L[2]);
+  const double3 hbox = make_double3(0.5 * host.L[0], 0.5 * host.L[1], 0.5 * host.L[2]);
+  // close-pair radius: a tenth of a typical tile extent (FP32 path); the
+  // FP64 path needs the near pass only to drop the self pair
+  const double vol = host.L[0] * host.L[1] * host.L[2];
+  const double ext = std::cbrt(kTile * vol / std::max(1, n));
+  const double rc = fp64 ? 1e-9 * ext : close_factor * ext;
+  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, st, (StepParams*)d_sp, lo, L, hbox, rc * rc);
+  HIPCHK(hipGetLastError());
+  // Graph replay: a step depends only on (n, buffers, stream) once the box
+  // scalars live in d_sp.  It is captured on the second consecutive call
+  // with the same key and replayed afterwards.
+  const GraphKey key{n, d_xyz, d_q, d_energy, d_pot, d_force, st};
+  const bool graphable = use_graph && !timing && st != nullptr;
+  if (graphable && gexec && key == gkey) {
+    HIPCHK(hipGraphLaunch(gexec, st));
+    ++graph_replays;
+  } else if (graphable && key == last_key) {
+    if (gexec) {
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hsma_status es = enqueue_step(st, n, d_xyz, d_q, d_energy, d_pot, d_force, err);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (es != HSMA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return es;
+    }
+    if (ce != hipSuccess) {
+      err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ce);
+      return HSMA_ERR_DEVICE;
+    }
+    hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      gexec = nullptr;
+      err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ie);
+      return HSMA_ERR_DEVICE;
+    }
+    gkey = key;
+    HIPCHK(hipGraphLaunch(gexec, st));
+  } else {
+    if ((s = enqueue_step(st, n, d_xyz, d_q, d_energy, d_pot, d_force, err)) != HSMA_OK) return s;
+  }
+  last_key = key;
   const long long nd = (long long)host.desc_particles.size();
   near_pairs = (long long)n * nd * n - n;
   long long cp = 0;
   for (const Group& g : host.check_groups) cp += (long long)g.count * g.ndesc * n;
   check_pairs = cp;
-  sphere_pairs = (long long)n * F;
+  sphere_pairs = (long long)n * host.prm.F;
   return HSMA_OK;
 }
 

@@ -192,6 +192,7 @@ hsma_status hsma_server_create(const hsma_server_cfg* cfg, hsma_server** out) {
     if ((st = s.plan->init(msg)) != HSMA_OK) return hsma::set_last_error(st, msg);
     if ((st = s.plan->init_scalable(msg)) != HSMA_OK) return hsma::set_last_error(st, msg);
     if ((st = s.plan->reserve(cfg->max_n, msg)) != HSMA_OK) return hsma::set_last_error(st, msg);
+    s.plan->use_graph = true;  // repeated sizes in a slot replay a captured step
     s.cap = cfg->max_n;
     const int64_t io_bytes = (int64_t)sizeof(double) * (8 * s.cap + 2);
     const int64_t plan_bytes = (int64_t)(sizeof(double) * 2 * (hp.Praw.size() + hp.SQ.size() * 2 + hp.ysurf.size() * 2) +

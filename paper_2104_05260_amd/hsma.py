@@ -143,6 +143,7 @@ def load_library():
     lib.hsma_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
     lib.hsma_last_error.restype = ctypes.c_char_p
     lib.hsma_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.hsma_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.hsma_plan_get_timing.argtypes = [vp, ctypes.POINTER(_CTiming)]
     lib.hsma_debug_solid_harmonics.argtypes = [ctypes.c_int, d, d, d]
     lib.hsma_debug_host_plan_create.argtypes = [ctypes.POINTER(_CParams), d, d, ctypes.POINTER(vp)]
@@ -160,7 +161,7 @@ def load_library():
     lib.hsma_debug_hilbert_key.argtypes = [ctypes.c_uint32] * 3
     lib.hsma_debug_hilbert_key.restype = ctypes.c_uint32
     for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_plan_device_status",
-                 "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_plan_set_timing", "hsma_plan_get_timing", "hsma_debug_host_plan_create"):
+                 "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_plan_set_timing", "hsma_plan_get_timing", "hsma_plan_set_graph", "hsma_debug_host_plan_create"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -270,6 +271,9 @@ class Plan:
     def device_status(self) -> int:
         st = self._lib.hsma_plan_device_status(self._p)
         return st
+
+    def set_graph(self, enable: bool = True):
+        _check(self._lib.hsma_plan_set_graph(self._p, 1 if enable else 0))
 
     def set_timing(self, enable: bool = True):
         _check(self._lib.hsma_plan_set_timing(self._p, 1 if enable else 0))

@@ -251,3 +251,35 @@ def test_c5_million_ions_sampled():
     assert dp < 1e-5 and df < 1e-5
     assert np.isfinite(e)
     assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())
+
+
+def test_step_graph_replays_match_eager():
+    """A plan in graph mode captures the step on the second identical call
+    and replays it; every replay (new positions each time, eager work and
+    synchronisations in between) equals the eager result bitwise."""
+    import torch
+    dev = torch.device("cuda:0")
+    pos0, q, lo, L = workloads.small_system(2000, (20.0, 20.0, 20.0), 31)
+    rng = np.random.default_rng(4)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5)
+    stream = torch.cuda.Stream()
+    with hs.Plan(params, lo, L) as eager, hs.Plan(params, lo, L) as graphed:
+        graphed.set_graph(True)
+        x = torch.empty((len(q), 3), dtype=torch.float64, device=dev)
+        qq = torch.tensor(q, device=dev)
+        en = torch.zeros(1, dtype=torch.float64, device=dev)
+        pot = torch.zeros(len(q), dtype=torch.float64, device=dev)
+        f = torch.zeros((len(q), 3), dtype=torch.float64, device=dev)
+        for it in range(6):
+            pos = pos0 + rng.normal(0, 0.05, pos0.shape)
+            with torch.cuda.stream(stream):
+                x.copy_(torch.tensor(pos, device=dev))
+                graphed.compute_device(x, qq, en, pot, f, stream=stream.cuda_stream)
+                junk = torch.randn(1000, device=dev).sum()   # eager work on the same stream
+            stream.synchronize()
+            e_ref, p_ref, f_ref = eager.compute(pos, q)
+            assert en.item() == e_ref, it
+            assert np.array_equal(pot.cpu().numpy(), p_ref), it
+            assert np.array_equal(f.cpu().numpy(), f_ref), it
+            del junk
+        assert graphed.device_status() == 0
