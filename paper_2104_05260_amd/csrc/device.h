@@ -57,7 +57,7 @@ struct DevicePlan {
 
   // per-size arena
   int64_t cap_n = 0, cur_n = -1;
-  size_t part_cap = 0, cpart_cap = 0, work_cap = 0, cwork_cap = 0, group_cap = 0;
+  size_t part_cap = 0, cpart_cap = 0, work_cap = 0, cwork_cap = 0;
   uint32_t* d_key[2] = {nullptr, nullptr};
   int* d_val[2] = {nullptr, nullptr};
   uint32_t* d_hist = nullptr;
@@ -72,11 +72,10 @@ struct DevicePlan {
   double* d_epart = nullptr;
   void* d_part = nullptr;
   void* d_cpart = nullptr;
-  Group* d_groups = nullptr;
-  Work* d_work = nullptr;
-  Work* d_cwork = nullptr;
-  int2* d_cg_work = nullptr;
-  int ntiles_ = 0, ngroups_ = 0, nwork_ = 0, nnear_ = 0, ncwork_ = 0, ncnear_ = 0, nchunks_ = 0, nsphere_ = 0,
+  CheckSched* d_csched = nullptr;
+  hipEvent_t stage_ev = nullptr;
+  PartSched psched_{};
+  int ntiles_ = 0, ngroups_ = 0, ncwork_ = 0, nchunks_ = 0, nsphere_ = 0,
       nrsblk_ = 0;
 
   // host-call staging
@@ -98,7 +97,7 @@ struct DevicePlan {
   hsma_status record(hipStream_t st, int stage, int edge, std::string& err);
   hipStream_t last_stream = nullptr;
 
-  void* h_stage = nullptr;       // pinned staging of the work tables
+  void* h_stage = nullptr;       // pinned staging of the check schedule
   size_t stage_bytes = 0;
   size_t arena_bytes = 0;        // device bytes of the per-size arena
 

@@ -39,6 +39,22 @@ struct Work {
   int group, f0, f1, slot;
 };
 
+// Particle work schedule (computed from the wave index, not stored): group
+// g = 0..ngroups-1 of kGroup sorted particles; its range [0, F) of (image,
+// tile) pairs cut into nch chunks of `chunk`; far wave b takes chunk
+// b / ngroups of group b % ngroups and writes slot = chunk index; the near
+// wave of group g writes slot nch.
+struct PartSched {
+  int n, ngroups, ndesc, F, nch, chunk;
+};
+
+// Check-target schedule of one check group: far waves first_work ..
+// first_work + nch - 1 take chunks of `chunk` and write slots slot0 + c;
+// the group's near wave writes slot0 + nch.
+struct CheckSched {
+  int first_work, nch, chunk, slot0;
+};
+
 // Host-side FP64 plan: everything that depends on the box and the method
 // parameters but not on the particles.
 struct HostPlan {

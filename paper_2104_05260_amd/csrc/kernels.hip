@@ -348,16 +348,54 @@ __device__ __forceinline__ double gap2_of(double dlx, double dly, double dlz, do
 #define HSMA_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? HSMA_WAVES_PER_EU : 4)))
 
 template <typename Real, bool NEAR, bool PARTICLES>
-__global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ groups,
-                                             const Work* __restrict__ work, const Desc* __restrict__ desc,
+__global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ cgroups,
+                                             const CheckSched* __restrict__ csched, int ncg, PartSched ps,
+                                             const Desc* __restrict__ desc,
                                              int ntiles, const double4* __restrict__ tile_c,
                                              const float4* __restrict__ tile_h,
                                              const typename SrcT<Real>::T* __restrict__ src,
                                              const double4* __restrict__ pos64, const StepParams* __restrict__ sp,
                                              Real* __restrict__ part, long comp_stride, long slot_stride) {
   typedef typename SrcT<Real>::T S;
-  const Work w = work[blockIdx.x];
-  const Group g = groups[w.group];
+  Work w;
+  Group g;
+  if constexpr (PARTICLES) {
+    int gi;
+    if constexpr (NEAR) {
+      gi = blockIdx.x;
+      w = Work{gi, 0, ps.F, ps.nch};
+    } else {
+      const int c = blockIdx.x / ps.ngroups;
+      gi = blockIdx.x - c * ps.ngroups;
+      const int f0 = c * ps.chunk;
+      w = Work{gi, f0, min(ps.F, f0 + ps.chunk), c};
+    }
+    g = Group{gi * kGroup, min(kGroup, ps.n - gi * kGroup), 0, ps.ndesc};
+  } else {
+    int gi;
+    if constexpr (NEAR) {
+      gi = blockIdx.x;
+    } else {
+      // the check group whose far waves include this one (binary search)
+      int lo = 0, hi = ncg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (csched[mid].first_work <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+      }
+      gi = lo;
+    }
+    const CheckSched cs = csched[gi];
+    g = cgroups[gi];
+    const int F = g.ndesc * ntiles;
+    if constexpr (NEAR) {
+      w = Work{gi, 0, F, cs.slot0 + cs.nch};
+    } else {
+      const int c = blockIdx.x - cs.first_work;
+      const int f0 = c * cs.chunk;
+      w = Work{gi, f0, min(F, f0 + cs.chunk), cs.slot0 + c};
+    }
+  }
   const double3 hbox = sp->hbox;
   const double rc2 = sp->rc2;
   const int lane = threadIdx.x;
@@ -643,11 +681,12 @@ __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ 
 // combined at the end (error-free for the FP32 potential).
 template <typename Real>
 __global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __restrict__ groups,
-                                                      const int2* __restrict__ g_slots, const int* __restrict__ axis,
+                                                      const CheckSched* __restrict__ csched, const int* __restrict__ axis,
                                                       const Real* __restrict__ part, double* __restrict__ v) {
   __shared__ double sh_phi[kGroup], sh_e[kGroup];
   const Group g = groups[blockIdx.x];
-  const int2 sr = g_slots[blockIdx.x];
+  const CheckSched cs = csched[blockIdx.x];
+  const int2 sr = make_int2(cs.slot0, cs.nch + 1);
   const int local = threadIdx.x % kGroup, half = threadIdx.x / kGroup;
   const bool ok = local < g.count;
   const int t = g.first + (ok ? local : 0);
@@ -924,7 +963,7 @@ hsma_status DevicePlan::init(std::string& err) {
 
 void DevicePlan::free_arena() {
   void* ps[] = {d_key[0], d_key[1], d_val[0], d_val[1], d_hist, d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
-                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_groups, d_work, d_cwork, d_cg_work};
+                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   d_key[0] = d_key[1] = nullptr;
@@ -938,9 +977,8 @@ void DevicePlan::free_arena() {
   d_perm = nullptr;
   d_red = d_epart = nullptr;
   d_part = d_cpart = nullptr;
-  d_groups = nullptr;
-  d_work = d_cwork = nullptr;
-  d_cg_work = nullptr;
+  d_csched = nullptr;
+  if (stage_ev) (void)hipEventSynchronize(stage_ev);  // an upload may still read the staging
   if (h_stage) (void)hipHostFree(h_stage);
   h_stage = nullptr;
   cap_n = 0;
@@ -953,6 +991,7 @@ DevicePlan::~DevicePlan() {
   if (d_sp) (void)hipFree(d_sp);
   free_arena();
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  if (stage_ev) (void)hipEventDestroy(stage_ev);
   void* us[] = {d_unit_desc_part, d_unit_desc_check, d_unit_check_pos, d_unit_Praw, d_unit_SQ, d_unit_SD, d_unit_ysurf};
   for (void* p : us)
     if (p) (void)hipFree(p);
@@ -964,52 +1003,41 @@ DevicePlan::~DevicePlan() {
   if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
-// Far work items: every group's (image, tile) range cut into chunks so that
-// a launch has about `target` waves.  Particle groups share one chunking
-// (slot = chunk index).  Check groups get their own slots: far chunks then
-// one near item, contiguous per group (slot range returned in `gslots`).
-static void make_far_work(const std::vector<Group>& groups, int ntiles, int target, bool shared_slots,
-                          std::vector<Work>& work, std::vector<int2>* gslots, int* nchunks_out) {
-  work.clear();
-  if (gslots) gslots->assign(groups.size(), make_int2(0, 0));
+// Particle schedule for n particles: chunks sized so that a launch has
+// about `target` waves (and at least 8 tiles per chunk).
+static PartSched part_schedule(int64_t n, int ndesc, int target) {
+  PartSched ps;
+  ps.n = (int)n;
+  ps.ngroups = (int)((n + kGroup - 1) / kGroup);
+  const int ntiles = (int)((n + kTile - 1) / kTile);
+  ps.ndesc = ndesc;
+  ps.F = ndesc * ntiles;
+  long long want = std::max<long long>(1, (target + (long long)ps.ngroups - 1) / ps.ngroups);
+  want = std::min<long long>(want, std::max<long long>(1, ps.F / 8));
+  ps.chunk = (int)((ps.F + want - 1) / want);
+  ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
+  return ps;
+}
+
+// Check schedule: each check group's range cut in proportion to its share
+// of the check pairs; returns the number of far waves and of slots.
+static void check_schedule(const std::vector<Group>& groups, int ntiles, int target, std::vector<CheckSched>& cs,
+                           int& nfar, int& nslots) {
+  cs.assign(groups.size(), CheckSched{0, 0, 1, 0});
   long long total = 0;
   for (const Group& g : groups) total += (long long)g.ndesc * ntiles;
-  // shared chunking: every particle group has the same range length, so
-  // one chunk length (and the exact chunk count it implies) serves all
-  int nch_shared = 1;
-  long long chunk_shared = 1;
-  if (shared_slots && !groups.empty()) {
-    const long long per = (long long)groups[0].ndesc * ntiles;
-    long long want = std::max<long long>(1, (target + (long long)groups.size() - 1) / (long long)groups.size());
-    want = std::min<long long>(want, std::max<long long>(1, per / 8));
-    chunk_shared = (per + want - 1) / want;
-    nch_shared = (int)((per + chunk_shared - 1) / chunk_shared);
-  }
-  int slot = 0;
+  nfar = 0;
+  nslots = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const Group& g = groups[gi];
-    const long long F = (long long)g.ndesc * ntiles;
-    long long chunk;
-    if (shared_slots) {
-      chunk = chunk_shared;
-    } else {
-      const long long want = std::max<long long>(1, std::min<long long>(std::max<long long>(1, F / 8),
-          (long long)((double)target * F / std::max<long long>(1, total) + 0.5)));
-      chunk = (F + want - 1) / want;
-    }
+    const long long F = (long long)groups[gi].ndesc * ntiles;
+    const long long want = std::max<long long>(1, std::min<long long>(std::max<long long>(1, F / 8),
+        (long long)((double)target * F / std::max<long long>(1, total) + 0.5)));
+    const long long chunk = (F + want - 1) / want;
     const int nch = (int)((F + chunk - 1) / chunk);
-    const int first_slot = slot;
-    for (int c = 0; c < nch; ++c) {
-      const long long f0 = c * chunk, f1 = std::min(F, f0 + chunk);
-      work.push_back(Work{(int)gi, (int)f0, (int)f1, shared_slots ? c : slot});
-      ++slot;
-    }
-    if (!shared_slots) ++slot;  // the group's near item
-    if (gslots) (*gslots)[gi] = make_int2(first_slot, slot - first_slot);
+    cs[gi] = CheckSched{nfar, nch, (int)chunk, nslots};
+    nfar += nch;
+    nslots += nch + 1;  // far chunks + the near slot
   }
-  if (shared_slots)
-    std::stable_sort(work.begin(), work.end(), [](const Work& a, const Work& b) { return a.slot < b.slot; });
-  if (nchunks_out) *nchunks_out = nch_shared;
 }
 
 // Upper bounds of the per-size buffers for any particle count <= n, so that
@@ -1041,7 +1069,7 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   const int64_t crs = (cn + kRsBlock - 1) / kRsBlock;
   size_t part_bytes, cpart_bytes, nwork, ncwork;
   capacity_bounds(cn, part_bytes, cpart_bytes, nwork, ncwork);
-  const int64_t ngroups = (cn + kGroup - 1) / kGroup;
+  const size_t ncg = std::max<size_t>(1, host.check_groups.size());
   HIPCHK(hipMalloc((void**)&d_key[0], sizeof(uint32_t) * cn));
   HIPCHK(hipMalloc((void**)&d_key[1], sizeof(uint32_t) * cn));
   HIPCHK(hipMalloc((void**)&d_val[0], sizeof(int) * cn));
@@ -1058,100 +1086,62 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   HIPCHK(hipMalloc((void**)&d_epart, sizeof(double) * ((cn + 255) / 256)));
   HIPCHK(hipMalloc(&d_part, part_bytes));
   HIPCHK(hipMalloc(&d_cpart, cpart_bytes));
-  HIPCHK(hipMalloc((void**)&d_groups, sizeof(Group) * ngroups));
-  HIPCHK(hipMalloc((void**)&d_work, sizeof(Work) * nwork));
-  HIPCHK(hipMalloc((void**)&d_cwork, sizeof(Work) * ncwork));
-  HIPCHK(hipMalloc((void**)&d_cg_work, sizeof(int2) * std::max<size_t>(1, host.check_groups.size())));
-  const size_t stage = sizeof(Group) * ngroups + sizeof(Work) * (nwork + ncwork) +
-                       sizeof(int2) * (host.check_groups.size() + 1) + 256;
-  HIPCHK(hipHostMalloc(&h_stage, stage));
-  stage_bytes = stage;
+  HIPCHK(hipMalloc((void**)&d_csched, sizeof(CheckSched) * ncg));
+  HIPCHK(hipHostMalloc(&h_stage, sizeof(CheckSched) * ncg + 64));
+  if (!stage_ev) HIPCHK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
+  stage_bytes = sizeof(CheckSched) * ncg + 64;
   cap_n = cn;
   part_cap = part_bytes;
   cpart_cap = cpart_bytes;
   work_cap = nwork;
   cwork_cap = ncwork;
-  group_cap = ngroups;
   arena_bytes = sizeof(uint32_t) * cn * 2 + sizeof(int) * cn * 2 + sizeof(uint32_t) * 256 * crs +
                 sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
-                sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(Group) * ngroups +
-                sizeof(Work) * (nwork + ncwork);
+                sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(CheckSched) * ncg;
   cur_n = -1;
   return HSMA_OK;
 }
 
 hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   if (n == cur_n) return HSMA_OK;
-  gkey = GraphKey();  // the captured step used the tables of another size
+  gkey = GraphKey();  // a captured step used the schedule of another size
   hsma_status s = reserve(n, err);
   if (s != HSMA_OK) return s;
   const int ntiles = (int)((n + kTile - 1) / kTile);
-  const int ngroups = (int)((n + kGroup - 1) / kGroup);
-  const int nrsblk = (int)((n + kRsBlock - 1) / kRsBlock);
-  std::vector<Group> groups(ngroups);
-  for (int g = 0; g < ngroups; ++g)
-    groups[g] = Group{g * kGroup, (int)std::min<int64_t>(kGroup, n - (int64_t)g * kGroup), 0,
-                      (int)host.desc_particles.size()};
-  std::vector<Work> work, cwork, nwork, cnwork;
-  int nch = 1;
-  make_far_work(groups, ntiles, part_target, true, work, nullptr, &nch);
-  for (int g = 0; g < ngroups; ++g)
-    nwork.push_back(Work{g, 0, groups[g].ndesc * ntiles, nch});
-  // every particle target must receive exactly one partial in each shared slot
-  if ((long long)work.size() != (long long)nch * ngroups) {
-    err = "internal error: uneven particle work decomposition";
-    return HSMA_ERR_DEVICE;
-  }
+  const PartSched ps = part_schedule(n, (int)host.desc_particles.size(), part_target);
   // check work: about check_pairs_per_item pairs per wave, enough waves to
   // fill the chip when there is that much work
   long long cpairs = 0;
   for (const Group& g : host.check_groups) cpairs += (long long)g.count * g.ndesc * n;
   const int ctarget = (int)std::min<long long>(check_target_max, std::max<long long>(check_target,
                           cpairs / std::max<long long>(1, check_pairs_per_item)));
-  std::vector<int2> cgs;
-  make_far_work(host.check_groups, ntiles, ctarget, false, cwork, &cgs, nullptr);
-  int ncslots = 0;
-  for (size_t gi = 0; gi < host.check_groups.size(); ++gi) {
-    cnwork.push_back(Work{(int)gi, 0, host.check_groups[gi].ndesc * ntiles, cgs[gi].x + cgs[gi].y - 1});
-    ncslots = std::max(ncslots, cgs[gi].x + cgs[gi].y);
-  }
+  std::vector<CheckSched> cs;
+  int ncfar = 0, ncslots = 0;
+  check_schedule(host.check_groups, ntiles, ctarget, cs, ncfar, ncslots);
   const int nsc = (host.prm.F + kSphereChunk - 1) / kSphereChunk;
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
-  const long comp = (long)ngroups * kGroup;
-  if (rb * 5 * (size_t)comp * (nch + 1 + nsc) > part_cap || rb * 5 * (size_t)kGroup * ncslots > cpart_cap ||
-      work.size() + nwork.size() > work_cap || cwork.size() + cnwork.size() > cwork_cap ||
-      groups.size() > group_cap) {
+  const long comp = (long)ps.ngroups * kGroup;
+  if (rb * 5 * (size_t)comp * (ps.nch + 1 + nsc) > part_cap || rb * 5 * (size_t)kGroup * ncslots > cpart_cap ||
+      (size_t)ps.nch * ps.ngroups + ps.ngroups > work_cap || (size_t)ncfar + cs.size() > cwork_cap) {
     err = "internal error: work decomposition exceeds the reserved arena";
     return HSMA_ERR_DEVICE;
   }
-  // stage the tables in pinned memory and copy them on the call's stream;
-  // the stream is drained first so that the staging buffer is free
-  HIPCHK(hipStreamSynchronize(st));
-  char* h = (char*)h_stage;
-  size_t off = 0;
-  auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-    std::memcpy(h + off, src, bytes);
-    hipError_t e = hipMemcpyAsync(dst, h + off, bytes, hipMemcpyHostToDevice, st);
-    off += (bytes + 15) & ~size_t(15);
-    return e;
-  };
-  HIPCHK(put(d_groups, groups.data(), sizeof(Group) * groups.size()));
-  HIPCHK(put(d_work, work.data(), sizeof(Work) * work.size()));
-  HIPCHK(put(d_work + work.size(), nwork.data(), sizeof(Work) * nwork.size()));
-  if (!cwork.empty()) HIPCHK(put(d_cwork, cwork.data(), sizeof(Work) * cwork.size()));
-  if (!cnwork.empty()) HIPCHK(put(d_cwork + cwork.size(), cnwork.data(), sizeof(Work) * cnwork.size()));
-  if (!cgs.empty()) HIPCHK(put(d_cg_work, cgs.data(), sizeof(int2) * cgs.size()));
-  HIPCHK(hipStreamSynchronize(st));
+  // the check schedule goes through pinned staging on the call's stream;
+  // the previous upload from the staging buffer must have completed
+  if (!cs.empty()) {
+    HIPCHK(hipEventSynchronize(stage_ev));
+    std::memcpy(h_stage, cs.data(), sizeof(CheckSched) * cs.size());
+    HIPCHK(hipMemcpyAsync(d_csched, h_stage, sizeof(CheckSched) * cs.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(stage_ev, st));
+  }
   cur_n = n;
   ntiles_ = ntiles;
-  ngroups_ = ngroups;
-  nwork_ = (int)work.size();
-  nnear_ = (int)nwork.size();
-  ncwork_ = (int)cwork.size();
-  ncnear_ = (int)cnwork.size();
-  nchunks_ = nch;
+  ngroups_ = ps.ngroups;
+  psched_ = ps;
+  ncwork_ = ncfar;
+  nchunks_ = ps.nch;
   nsphere_ = nsc;
-  nrsblk_ = nrsblk;
+  nrsblk_ = (int)((n + kRsBlock - 1) / kRsBlock);
   return HSMA_OK;
 }
 
@@ -1201,31 +1191,33 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   do {                                                                                                              \
     if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;                                                    \
     hipLaunchKernelGGL((k_pair<Real, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,   \
-                       (const Group*)d_check_groups, (const Work*)d_cwork, (const Desc*)d_desc_check, ntiles_,      \
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
-                       (const StepParams*)d_sp, (Real*)d_cpart, ccomp, cslot);                                                    \
-    hipLaunchKernelGGL((k_pair<Real, true, false>), dim3(ncnear_), dim3(64), 0, st, (const double4*)d_check_pos,    \
-                       (const Group*)d_check_groups, (const Work*)(d_cwork + ncwork_), (const Desc*)d_desc_check,   \
-                       ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC,                   \
-                       (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_cpart, ccomp, cslot);                           \
+                       (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
+                       (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_cpart, ccomp,     \
+                       cslot);                                                                                      \
+    hipLaunchKernelGGL((k_pair<Real, true, false>), dim3(ncg), dim3(64), 0, st, (const double4*)d_check_pos,        \
+                       (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
+                       (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_cpart, ccomp,     \
+                       cslot);                                                                                      \
     if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;                                                    \
     hipLaunchKernelGGL(k_reduce_check<Real>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,      \
-                       (const int2*)d_cg_work, (const int*)d_check_axis, (const Real*)d_cpart, d_v);                \
+                       (const CheckSched*)d_csched, (const int*)d_check_axis, (const Real*)d_cpart, d_v);          \
     hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw,                   \
                        (const double*)d_v, d_A);                                                                    \
     hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,     \
                        (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,     \
                        d_surf32, d_surf64, d_qd);                                                                   \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
-    hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(nwork_), dim3(64), 0, st, (const double4*)d_pos64,         \
-                       (const Group*)d_groups, (const Work*)d_work, (const Desc*)d_desc_part, ntiles_,              \
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
-                       (const StepParams*)d_sp, (Real*)d_part, comp, slot);                                                       \
+    hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
+                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
+                       (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_part, comp, slot); \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
-    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(nnear_), dim3(64), 0, st, (const double4*)d_pos64,          \
-                       (const Group*)d_groups, (const Work*)(d_work + nwork_), (const Desc*)d_desc_part, ntiles_,   \
-                       (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC, (const double4*)d_pos64,   \
-                       (const StepParams*)d_sp, (Real*)d_part, comp, slot);                                                       \
+    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
+                       (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_, (const Desc*)d_desc_part,     \
+                       ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC,                   \
+                       (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_part, comp, slot);                \
     if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;                                                   \
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
                        (const double4*)d_surf64, F, (Real*)d_part, comp, nchunks_ + 1);                             \
