@@ -4,7 +4,8 @@ The steps follow the paper's overview of the method (Sec. 2.2 and the flow
 chart there):
   1. collect the sources and images inside the auxiliary region (the near
      set S: 27 cells for the periodic box, Eq. 3; 9 cells x (2M+1) image
-     layers for the dielectric slab, Eq. 4);
+     layers for the dielectric slab, Eq. 4); with near_rule=1 only the
+     images inside the auxiliary sphere itself, as Sec. 2.2 words it;
   2. evaluate the near potential Phi_B at the check points and fit the
      harmonic coefficients A by least squares, Eqs. (5)-(6);
   3. map the harmonic series to charges and dipoles on the sphere of radius
@@ -41,7 +42,26 @@ def _check_neutral(q):
 
 
 def _radius(L, lam):
-    return lam * 0.5 * float(np.linalg.norm(L))
+    """R = lambda x half box diagonal; the diagonal as sqrt(Lx^2+Ly^2+Lz^2)
+    summed left to right, so that the inside-the-sphere decision below is
+    taken on exactly this R."""
+    L = [float(v) for v in L]
+    return lam * 0.5 * math.sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2])
+
+
+def _cull_to_sphere(S, qS, self_idx, R):
+    """The near set of Sec. 2.2 read literally: the images whose position
+    lies strictly inside the auxiliary sphere |y| < R (box-centred).  The
+    test is |y|^2 = (y_x^2 + y_y^2) + y_z^2 < R^2 in FP64 on the image
+    positions as built (position + shift; z reflected, then shifted).  The
+    candidates are the cell/layer stencil, which covers the sphere whenever
+    R lies in the admissible range checked by the callers."""
+    r2 = (S[:, 0] * S[:, 0] + S[:, 1] * S[:, 1]) + S[:, 2] * S[:, 2]
+    keep = r2 < R * R
+    if not np.all(keep[self_idx]):
+        raise OracleInputError("a particle lies outside the auxiliary sphere")
+    newidx = np.cumsum(keep) - 1
+    return S[keep], qS[keep], newidx[self_idx]
 
 
 @dataclass
@@ -84,11 +104,12 @@ def _final(x, q, S, qS, self_idx, y, nrm, Q, D, targets):
     return phi_n + phi_s, E_n + E_s
 
 
-def hsma3d(pos, q, box_lo, box_len, p, K, F, lam, Fw=0, surface_rule=0, targets=None):
+def hsma3d(pos, q, box_lo, box_len, p, K, F, lam, Fw=0, surface_rule=0, targets=None, near_rule=0):
     """HSMA for the fully periodic box (tinfoil boundary at infinity).
 
     targets: optional index array of particles to evaluate (all if None);
-    the energy is returned only when all particles are evaluated."""
+    the energy is returned only when all particles are evaluated.
+    near_rule: 0 = the 27 cells, 1 = the images inside the sphere."""
     L = np.asarray(box_len, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     _check_neutral(q)
@@ -102,6 +123,10 @@ def hsma3d(pos, q, box_lo, box_len, p, K, F, lam, Fw=0, surface_rule=0, targets=
 
     # 1. near set
     S, qS, self_idx = geometry.images_3d(x, q, L)
+    if near_rule == 1:
+        S, qS, self_idx = _cull_to_sphere(S, qS, self_idx, R)
+    elif near_rule != 0:
+        raise OracleInputError("near_rule must be 0 or 1")
 
     # 2. least squares on periodicity rows at opposite face points
     xm, xp, axis = geometry.check_pairs_3d(L, K)
@@ -128,9 +153,11 @@ def hsma3d(pos, q, box_lo, box_len, p, K, F, lam, Fw=0, surface_rule=0, targets=
 
 
 def hsma2d(pos, q, box_lo, box_len, p, K, F, lam, M, gamma_up, gamma_low, nz,
-           Fw=0, surface_rule=0, targets=None):
+           Fw=0, surface_rule=0, targets=None, near_rule=0):
     """HSMA for the slab periodic in x, y with dielectric interfaces at the
-    two z faces of the box (mismatches gamma_up, gamma_low, |gamma| < 1)."""
+    two z faces of the box (mismatches gamma_up, gamma_low, |gamma| < 1).
+    near_rule: 0 = 9 cells x (2M+1) layers, 1 = the images of those inside
+    the sphere (M then only bounds the candidate layers)."""
     L = np.asarray(box_len, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     _check_neutral(q)
@@ -145,6 +172,10 @@ def hsma2d(pos, q, box_lo, box_len, p, K, F, lam, M, gamma_up, gamma_low, nz,
 
     # 1. near set with image layers
     S, qS, self_idx = geometry.images_2d(x, q, L, M, gamma_up, gamma_low)
+    if near_rule == 1:
+        S, qS, self_idx = _cull_to_sphere(S, qS, self_idx, R)
+    elif near_rule != 0:
+        raise OracleInputError("near_rule must be 0 or 1")
 
     # 2a. periodicity rows on the x and y faces
     xm, xp, axis = geometry.check_pairs_2d(L, K)
@@ -201,6 +232,6 @@ def run_workload(w, targets=None):
     import workloads
     pos, q, lo, L = workloads.make_system(w)
     if w.geometry == 0:
-        return hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets)
+        return hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets, w.near_rule)
     return hsma2d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.M, w.gamma_up, w.gamma_low, w.nz,
-                  w.Fw, w.surface_rule, targets)
+                  w.Fw, w.surface_rule, targets, w.near_rule)

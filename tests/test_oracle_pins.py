@@ -326,6 +326,51 @@ def test_hsma3d_rejects_bad_input():
         hsma.hsma3d(pos, q, lo, L, 6, 10, 200, 1.5)   # 20 rows < 48 unknowns
 
 
+def test_hsma3d_sphere_near_set_against_ewald():
+    """near_rule=1 (only the images inside the auxiliary sphere, Sec. 2.2):
+    an exact split as well, so the result converges to Ewald as p grows;
+    its far field starts at R instead of 1.5 L, so it needs a higher p than
+    the 27-cell set for the same error."""
+    pos, q, lo, L = workloads.make_system(workloads.C1)
+    xc = geometry.centre_and_wrap(pos, lo, L)
+    _, E, en = ewald.ewald3d(xc, q, L)
+    Fref = q[:, None] * E
+    errs = []
+    for p, K, F, tol_e, tol_f in ((6, 100, 200, 3e-3, 5e-3), (12, 800, 1152, 3e-5, 5e-5)):
+        r = hsma.hsma3d(pos, q, lo, L, p, K, F, 1.5, near_rule=1)
+        de = abs(r.energy - en) / abs(en)
+        df = np.sqrt(((r.force - Fref) ** 2).sum() / (Fref ** 2).sum())
+        assert de < tol_e and df < tol_f
+        errs.append(df)
+    assert errs[1] < errs[0] / 20
+
+
+def test_sphere_near_set_is_every_image_inside():
+    """The culled stencil holds exactly the images inside the sphere: the
+    same set comes out of a 7x7x7-cell (slab: 7x7 cells, M+4 layers)
+    candidate set, so no image inside the sphere lies beyond the stencil."""
+    pos, q, lo, L = workloads.small_system(30, (6.0, 7.0, 6.5), 21)
+    x = geometry.centre_and_wrap(pos, lo, L)
+    R = hsma._radius(L, 1.5)
+    S, qS, si = hsma._cull_to_sphere(*geometry.images_3d(x, q, L), R)
+    ks = np.array([(a, b, c) for a in range(-3, 4) for b in range(-3, 4) for c in range(-3, 4)], dtype=np.float64)
+    W = (x[None, :, :] + (ks * L)[:, None, :]).reshape(-1, 3)
+    Win = W[np.linalg.norm(W, axis=1) < R]
+    assert len(Win) == len(S) and 9 * len(q) < len(S) < 27 * len(q)
+    key = lambda A: A[np.lexsort(A.T)]
+    assert np.abs(key(Win) - key(S)).max() < 1e-12
+    assert np.all(np.linalg.norm(S[si] - x, axis=1) == 0)
+    # slab
+    pos, q, lo, L = workloads.small_system(20, (20.0, 20.0, 10.0), 5, geometry=1)
+    x = geometry.centre_and_wrap(pos, lo, L, periodic=(True, True, False))
+    R = hsma._radius(L, 1.6)
+    S, qS, si = hsma._cull_to_sphere(*geometry.images_2d(x, q, L, 6, -0.5, 0.3), R)
+    W, qW, _ = geometry.images_2d(x, q, L, 10, -0.5, 0.3, inplane=3)
+    inside = np.linalg.norm(W, axis=1) < R
+    assert inside.sum() == len(S)
+    assert abs(qW[inside].sum() - qS.sum()) < 1e-12 and abs((qW[inside] ** 2).sum() - (qS ** 2).sum()) < 1e-12
+
+
 # ------------------------------------------------------------ HSMA2D
 @pytest.mark.parametrize("gam,Mref,nz", [(0.0, 0, 160), (-0.94, 560, 160), (0.5, 50, 80)])
 def test_hsma2d_against_ewald2d_image_sum(gam, Mref, nz):
@@ -342,6 +387,20 @@ def test_hsma2d_against_ewald2d_image_sum(gam, Mref, nz):
     assert np.sqrt(((r.force - Fref) ** 2).sum() / (Fref ** 2).sum()) < tol
     # in-plane net force vanishes
     assert np.abs(r.force[:, :2].sum(0)).max() < 20 * tol * np.sqrt((r.force ** 2).sum())
+
+
+@pytest.mark.parametrize("gam,Mref,tol", [(-0.94, 560, 5e-5), (0.5, 50, 3e-5)])
+def test_hsma2d_sphere_near_set_against_image_sum(gam, Mref, tol):
+    """near_rule=1 for the slab: image layers beyond the sphere move into
+    the fitted far field; p = 12 reaches the image-sum reference (ions kept
+    2 from the walls so that nz = 40 resolves them)."""
+    pos, q, lo, L = workloads.small_system(12, (20.0, 20.0, 10.0), 7, geometry=1, z_margin=2.0)
+    x = geometry.centre_and_wrap(pos, lo, L, periodic=(True, True, False))
+    _, E, en = ewald.slab_reference(x, q, L, gam, gam, Mref)
+    Fref = q[:, None] * E
+    r = hsma.hsma2d(pos, q, lo, L, 12, 800, 1152, 1.6, 10, gam, gam, 40, near_rule=1)
+    assert abs(r.energy - en) < tol * abs(en)
+    assert np.sqrt(((r.force - Fref) ** 2).sum() / (Fref ** 2).sum()) < tol
 
 
 def test_hsma2d_mirror_symmetry():
