@@ -73,6 +73,14 @@ typedef struct hsma_params {
   int Fw;              /* lattice generator of the surface rule (0 = auto)   */
   int surface_rule;    /* 0: periodised rank-1 (Fibonacci) lattice;
                           1: Gauss-Legendre x trapezoid (F = 2 n^2)          */
+  int near_rule;       /* near set of Sec. 2.2.  0: the cell stencil (3D: 27
+                          cells; 2D: 9 cells x (2M+1) image layers).
+                          1: only the images of that stencil strictly inside
+                          the sphere, |y - box centre| < R (FP64 test on the
+                          image position); the stencil covers the sphere for
+                          every admissible R.  Rule 1 sums about a third of
+                          the pairs (3D, lambda 1.5) but its far field starts
+                          at R, so it needs a higher p for the same error   */
   int M;               /* 2D: image layers above and below                    */
   double gamma_up;     /* 2D: (eps_c - eps_up)/(eps_c + eps_up), |gamma| < 1  */
   double gamma_low;    /* 2D: (eps_c - eps_low)/(eps_c + eps_low)             */
@@ -83,7 +91,7 @@ typedef struct hsma_params {
 typedef struct hsma_plan hsma_plan;
 
 /* Fills *p with defaults: 3D, FP32C, lambda 1.5, p 10, K 2(p+1)^2, F 800,
- * Fw 0, rule 0, M 10, gammas 0, nz 80, coulomb_k 1.                        */
+ * Fw 0, surface rule 0, near rule 0, M 10, gammas 0, nz 80, coulomb_k 1.   */
 void hsma_params_default(hsma_params* p);
 
 /* Builds the per-geometry plan: check points, sphere quadrature, harmonic

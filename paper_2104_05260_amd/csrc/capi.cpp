@@ -85,6 +85,7 @@ void hsma_params_default(hsma_params* p) {
   p->F = 800;
   p->Fw = 0;
   p->surface_rule = 0;
+  p->near_rule = 0;
   p->M = 10;
   p->gamma_up = 0.0;
   p->gamma_low = 0.0;

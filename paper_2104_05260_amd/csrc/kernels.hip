@@ -1,7 +1,7 @@
 // gfx950 kernels of the HSMA hot path and the per-step launch sequence.
 //
 // Per step (Sec. 2.2 of the paper, in this order):
-//   ingest   wrap into the centred box, validate, spatial (Morton) keys
+//   ingest   wrap into the centred box, validate, Hilbert-curve keys
 //   sort     stable LSD radix sort of the keys (spatially compact tiles)
 //   tiles    64-particle source tiles: centre, half extent, offsets
 //   check    near sums at the check targets (telescoped face-pair sets,
@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 #include "device.h"
 
@@ -25,7 +26,17 @@ namespace hsma {
 
 // ----------------------------------------------------------------- helpers
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+// FP64 1/sqrt: the hardware estimate (about 2^-23 relative error) refined
+// by two Newton steps y <- y + y (1 - x y^2) / 2, each squaring the
+// relative error, so the result is within a few units of rounding.  A
+// short dependent chain next to sqrt followed by an IEEE division.
+__device__ __forceinline__ double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double r = __fma_rn(-(x * y), y, 1.0);
+  y = __fma_rn(0.5 * y, r, y);
+  r = __fma_rn(-(x * y), y, 1.0);
+  return __fma_rn(0.5 * y, r, y);
+}
 
 // Knuth's error-free sum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
@@ -88,13 +99,15 @@ uint32_t hilbert_key_host(uint32_t x, uint32_t y, uint32_t z) { return hilbert_k
 struct StepParams {
   double3 lo, L, hbox;
   double rc2;
+  double R2;  // squared sphere radius (sphere near set)
 };
 
-__global__ void k_set_params(StepParams* sp, double3 lo, double3 L, double3 hbox, double rc2) {
+__global__ void k_set_params(StepParams* sp, double3 lo, double3 L, double3 hbox, double rc2, double R2) {
   sp->lo = lo;
   sp->L = L;
   sp->hbox = hbox;
   sp->rc2 = rc2;
+  sp->R2 = R2;
 }
 
 // ----------------------------------------------------------------- ingest
@@ -150,32 +163,42 @@ __global__ __launch_bounds__(256) void k_ingest(int n, const double* __restrict_
 }
 
 // Fixed-order reduction of the ingest partials into the device status word.
-__global__ __launch_bounds__(256) void k_validate(int nblk, const double* __restrict__ red, int* __restrict__ status) {
-  __shared__ double s0[256], s1[256], s2[256];
-  double a = 0, b = 0, c = 0;
-  for (int i = threadIdx.x; i < nblk; i += 256) {
-    a += red[3 * i];
-    b += red[3 * i + 1];
-    c += red[3 * i + 2];
+// Called by every thread of a block of at least 256 threads; threads from
+// 256 on only take part in the barriers.
+__device__ void validate_block(int nblk, const double* __restrict__ red, int* __restrict__ status, double* s0,
+                               double* s1, double* s2) {
+  const int t = threadIdx.x;
+  if (t < 256) {
+    double a = 0, b = 0, c = 0;
+    for (int i = t; i < nblk; i += 256) {
+      a += red[3 * i];
+      b += red[3 * i + 1];
+      c += red[3 * i + 2];
+    }
+    s0[t] = a;
+    s1[t] = b;
+    s2[t] = c;
   }
-  s0[threadIdx.x] = a;
-  s1[threadIdx.x] = b;
-  s2[threadIdx.x] = c;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      s0[threadIdx.x] += s0[threadIdx.x + o];
-      s1[threadIdx.x] += s1[threadIdx.x + o];
-      s2[threadIdx.x] += s2[threadIdx.x + o];
+    if (t < o) {
+      s0[t] += s0[t + o];
+      s1[t] += s1[t + o];
+      s2[t] += s2[t + o];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     int st = HSMA_OK;
     if (s2[0] > 0) st = HSMA_ERR_OUT_OF_DOMAIN;
     else if (!(fabs(s0[0]) <= 1e-12 * s1[0])) st = HSMA_ERR_NOT_NEUTRAL;
     status[0] = st;
   }
+}
+
+__global__ __launch_bounds__(256) void k_validate(int nblk, const double* __restrict__ red, int* __restrict__ status) {
+  __shared__ double s0[256], s1[256], s2[256];
+  validate_block(nblk, red, status, s0, s1, s2);
 }
 
 // ----------------------------------------------------------------- radix sort
@@ -270,28 +293,25 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
 // carry zero charge and a far-away offset so they contribute exactly 0.
 constexpr float kFar = 1.0e15f;
 
-__global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ order, const double4* __restrict__ pos,
-                                              double4* __restrict__ pos64, float4* __restrict__ src32,
-                                              double4* __restrict__ src64, double4* __restrict__ tile_c,
-                                              float4* __restrict__ tile_h, int* __restrict__ perm) {
-  const int s = blockIdx.x * kTile + threadIdx.x;
+// Tile t built by one wave; o is the input index of sorted slot t*64+lane
+// (ignored past n).
+__device__ __forceinline__ void build_tile(int t, int n, int o, const double4* __restrict__ pos,
+                                           double4* __restrict__ pos64, float4* __restrict__ src32,
+                                           double4* __restrict__ src64, double4* __restrict__ tile_c,
+                                           float4* __restrict__ tile_h, int* __restrict__ perm) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int s = t * kTile + lane;
   const bool ok = s < n;
-  double4 p = make_double4(0, 0, 0, 0);
-  int o = 0;
-  if (ok) {
-    o = order[s];
-    p = pos[o];
-  }
+  const double4 p = ok ? pos[o] : make_double4(0, 0, 0, 0);
   const double mnx = wave_min(ok ? p.x : INFINITY), mxx = wave_max(ok ? p.x : -INFINITY);
   const double mny = wave_min(ok ? p.y : INFINITY), mxy = wave_max(ok ? p.y : -INFINITY);
   const double mnz = wave_min(ok ? p.z : INFINITY), mxz = wave_max(ok ? p.z : -INFINITY);
   const double cx = 0.5 * (mnx + mxx), cy = 0.5 * (mny + mxy), cz = 0.5 * (mnz + mxz);
-  if (threadIdx.x == 0) {
-    tile_c[blockIdx.x] = make_double4(cx, cy, cz, 0.0);
+  if (lane == 0) {
+    tile_c[t] = make_double4(cx, cy, cz, 0.0);
     // half extents rounded up so that the bound stays conservative
-    tile_h[blockIdx.x] = make_float4((float)(0.5 * (mxx - mnx)) * 1.0001f + 1e-30f,
-                                     (float)(0.5 * (mxy - mny)) * 1.0001f + 1e-30f,
-                                     (float)(0.5 * (mxz - mnz)) * 1.0001f + 1e-30f, 0.f);
+    tile_h[t] = make_float4((float)(0.5 * (mxx - mnx)) * 1.0001f + 1e-30f, (float)(0.5 * (mxy - mny)) * 1.0001f + 1e-30f,
+                            (float)(0.5 * (mxz - mnz)) * 1.0001f + 1e-30f, 0.f);
   }
   pos64[s] = p;
   if (ok) {
@@ -303,6 +323,82 @@ __global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ ord
     src64[s] = make_double4(kFar, kFar, kFar, 0.0);
     perm[s] = -1;
   }
+}
+
+__global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ order, const double4* __restrict__ pos,
+                                              double4* __restrict__ pos64, float4* __restrict__ src32,
+                                              double4* __restrict__ src64, double4* __restrict__ tile_c,
+                                              float4* __restrict__ tile_h, int* __restrict__ perm) {
+  const int s = blockIdx.x * kTile + threadIdx.x;
+  build_tile(blockIdx.x, n, s < n ? order[s] : 0, pos, pos64, src32, src64, tile_c, tile_h, perm);
+}
+
+// Small systems (n <= kSmallSort): validation, the key sort and the tiles
+// in one block.  The sort is a bitonic network in LDS over unique 64-bit
+// (key, input index) words, so its order equals the stable radix sort's.
+constexpr int kSmallSort = 4096;
+constexpr int kSmallThreads = 1024;
+
+__global__ __launch_bounds__(kSmallThreads) void k_small_prep(int n, int nblk, const double* __restrict__ red,
+                                                              int* __restrict__ status, const uint32_t* __restrict__ key,
+                                                              const double4* __restrict__ pos,
+                                                              double4* __restrict__ pos64, float4* __restrict__ src32,
+                                                              double4* __restrict__ src64, double4* __restrict__ tile_c,
+                                                              float4* __restrict__ tile_h, int* __restrict__ perm) {
+  __shared__ unsigned long long sk[kSmallSort];
+  __shared__ double s0[256], s1[256], s2[256];
+  validate_block(nblk, red, status, s0, s1, s2);
+  int m = kTile;
+  while (m < n) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += kSmallThreads)
+    sk[i] = i < n ? (((unsigned long long)key[i] << 32) | (unsigned)i) : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < m; i += kSmallThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const unsigned long long a = sk[i], b = sk[l];
+          if ((a > b) == ((i & k) == 0)) {
+            sk[i] = b;
+            sk[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int ntiles = (n + kTile - 1) / kTile;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int t = wave; t < ntiles; t += kSmallThreads / kWave) {
+    const int s = t * kTile + lane;
+    build_tile(t, n, s < n ? (int)(unsigned)(sk[s] & 0xffffffffull) : 0, pos, pos64, src32, src64, tile_c, tile_h,
+               perm);
+  }
+}
+
+// ----------------------------------------------------------------- sphere near set
+// Sphere near set: bit l of cull[d * ntiles + t] says whether the image of
+// sorted source t*64+l under image entry d lies strictly inside the sphere,
+// |y|^2 = (y_x^2 + y_y^2) + y_z^2 < R^2 in FP64 with explicitly rounded
+// operations (image position: x + s_x, y + s_y, sigma z + s_z).  Padding
+// slots read as inside (they carry no charge).  One wave per (tile, entry).
+__global__ __launch_bounds__(64) void k_cull(int n, int ntiles, const double4* __restrict__ pos64,
+                                             const Desc* __restrict__ desc, const StepParams* __restrict__ sp,
+                                             unsigned long long* __restrict__ cull) {
+  const int t = blockIdx.x, d = blockIdx.y;
+  const int s = t * kTile + threadIdx.x;
+  bool in = true;
+  if (s < n) {
+    const double4 p = pos64[s];
+    const Desc ds = desc[d];
+    const double yx = __dadd_rn(p.x, ds.sx), yy = __dadd_rn(p.y, ds.sy);
+    const double yz = __dadd_rn(__dmul_rn(ds.sigma, p.z), ds.sz);
+    const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(yx, yx), __dmul_rn(yy, yy)), __dmul_rn(yz, yz));
+    in = r2 < sp->R2;
+  }
+  const unsigned long long m = __ballot(in);
+  if (threadIdx.x == 0) cull[(long)d * ntiles + t] = m;
 }
 
 // ----------------------------------------------------------------- pair sums
@@ -355,6 +451,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                                              const float4* __restrict__ tile_h,
                                              const typename SrcT<Real>::T* __restrict__ src,
                                              const double4* __restrict__ pos64, const StepParams* __restrict__ sp,
+                                             const unsigned long long* __restrict__ cull,
                                              Real* __restrict__ part, long comp_stride, long slot_stride) {
   typedef typename SrcT<Real>::T S;
   Work w;
@@ -362,8 +459,12 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   if constexpr (PARTICLES) {
     int gi;
     if constexpr (NEAR) {
-      gi = blockIdx.x;
-      w = Work{gi, 0, ps.F, ps.nch};
+      // near work split over ps.nnear waves per group (small systems have
+      // few groups); slots nch .. nch + nnear - 1
+      const int c = blockIdx.x / ps.ngroups;
+      gi = blockIdx.x - c * ps.ngroups;
+      const int f0 = c * ps.near_chunk;
+      w = Work{gi, f0, min(ps.F, f0 + ps.near_chunk), ps.nch + c};
     } else {
       const int c = blockIdx.x / ps.ngroups;
       gi = blockIdx.x - c * ps.ngroups;
@@ -430,8 +531,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   const int tbase = g.first + lane;  // sorted index of this lane's first target
 
   // One (image, tile) pair: sum its 64 sources into the accumulators.
+  // m: sphere near set mask of the tile's sources (all ones for the cell
+  // stencil); cleared bits contribute nothing.
   auto do_tile = [&](const Desc& ds, const bool own, const int tile, const double dlx, const double dly,
-                     const double dlz) {
+                     const double dlz, const unsigned long long m) {
     const Real sg = (Real)ds.sigma;
     const Real sc = (Real)ds.scale;
     Real ux[kTPL], uy[kTPL], uz[kTPL];
@@ -453,12 +556,13 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
 #pragma unroll
         for (int j = 0; j < kTPL; ++j) {
           const bool self = si == (long)(tbase + j * kWave);
+          const bool drop = self || !((m >> k) & 1ull);
           const Real dx = ux[j] - (Real)v.x;
           const Real dy = uy[j] - (Real)v.y;
           const Real dz = uz[j] - (Real)v.z;
           const Real r2 = self ? (Real)1 : dx * dx + dy * dy + dz * dz;
           const Real ri = rsq(r2);
-          const Real a = (self ? (Real)0 : (Real)v.w) * ri;
+          const Real a = (drop ? (Real)0 : (Real)v.w) * ri;
           pp[j] += a;
           const Real b = a * (ri * ri);
           qx[j] += b * dx;
@@ -467,24 +571,32 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
         }
       }
     } else if constexpr (!NEAR) {
+      // the plain loop; a tile cut by the sphere runs the same loop with
+      // the charges of the sources outside it set to zero
+      auto far_loop = [&](auto masked) {
 #pragma unroll HSMA_FAR_UNROLL
-      for (int k = 0; k < kTile; ++k) {
-        const S v = s[k];
+        for (int k = 0; k < kTile; ++k) {
+          const S v = s[k];
+          Real qv = (Real)v.w;
+          if constexpr (decltype(masked)::value) qv = ((m >> k) & 1ull) ? qv : (Real)0;
 #pragma unroll
-        for (int j = 0; j < kTPL; ++j) {
-          const Real dx = ux[j] - (Real)v.x;
-          const Real dy = uy[j] - (Real)v.y;
-          const Real dz = uz[j] - (Real)v.z;
-          const Real r2 = dx * dx + dy * dy + dz * dz;
-          const Real ri = rsq(r2);
-          const Real a = (Real)v.w * ri;
-          pp[j] += a;
-          const Real b = a * (ri * ri);
-          qx[j] += b * dx;
-          qy[j] += b * dy;
-          qz[j] += b * dz;
+          for (int j = 0; j < kTPL; ++j) {
+            const Real dx = ux[j] - (Real)v.x;
+            const Real dy = uy[j] - (Real)v.y;
+            const Real dz = uz[j] - (Real)v.z;
+            const Real r2 = dx * dx + dy * dy + dz * dz;
+            const Real ri = rsq(r2);
+            const Real a = qv * ri;
+            pp[j] += a;
+            const Real b = a * (ri * ri);
+            qx[j] += b * dx;
+            qy[j] += b * dy;
+            qz[j] += b * dz;
+          }
         }
-      }
+      };
+      if (m == ~0ull) far_loop(std::false_type{});
+      else far_loop(std::true_type{});
     } else {
       for (int k = 0; k < kTile; ++k) {
         const S v = s[k];
@@ -494,7 +606,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           Real dy = uy[j] - (Real)v.y;
           Real dz = uz[j] - (Real)v.z;
           Real r2 = dx * dx + dy * dy + dz * dz;
-          Real qq = (Real)v.w;
+          Real qq = ((m >> k) & 1ull) ? (Real)v.w : (Real)0;
           const long si = (long)tile * kTile + k;
           if (PARTICLES && own && si == (long)(tbase + j * kWave)) {
             // the target itself or one of its own images: summed in FP64 by
@@ -570,6 +682,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           const double dlz = shifted_dz(ds, cs.z, cgz);
           near = gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
                          __dadd_rn(hgz, (double)hs.z)) < rc2;
+          if (cull && near) near = cull[(long)di * ntiles + tile] != 0ull;
         }
         unsigned long long m = __ballot(near);
         while (m) {
@@ -580,11 +693,16 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
           const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
           const double dlz = shifted_dz(ds, cs.z, cgz);
-          do_tile(ds, nt >= own0 && nt <= own1, nt, dlx, dly, dlz);
+          do_tile(ds, nt >= own0 && nt <= own1, nt, dlx, dly, dlz, cull ? cull[(long)di * ntiles + nt] : ~0ull);
         }
       }
     } else {
       for (int tile = t0; tile < t1; ++tile) {
+        unsigned long long cm = ~0ull;
+        if (cull) {
+          cm = cull[(long)di * ntiles + tile];
+          if (cm == 0ull) continue;  // every source of this image outside the sphere
+        }
         const double4 cs = tile_c[tile];
         const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
         const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
@@ -595,7 +713,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                       __dadd_rn(hgz, (double)hs.z)) < rc2)
             continue;  // summed by the near pass
         }
-        do_tile(ds, tile >= own0 && tile <= own1, tile, dlx, dly, dlz);
+        do_tile(ds, tile >= own0 && tile <= own1, tile, dlx, dly, dlz, cm);
       }
     }
   }
@@ -614,21 +732,29 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
 // Sphere sources: charge Q_k and double-layer strength D_k at y_k, normal
 // n_k.  phi += Q/|d| - D (n.d)/|d|^3,  E += Q d/|d|^3 + D (n/|d|^3 - 3 (n.d) d/|d|^5).
 // Records: surf[2k] = (y, Q), surf[2k+1] = (n, D), box-centred coordinates.
-// Grid: (target group, chunk of kSphereChunk sources); slot = slot0 + chunk.
+// Grid: (target group, chunk of `chunk` sources); slot = slot0 + chunk index.
 // Always FP64: the Green representation of the harmonic part cancels
 // strongly inside the sphere (u on the sphere exceeds u in the box by about
 // lambda^p), so FP32 rounding of Q_k, D_k and y_k would be amplified into a
 // smooth error field; these sums are N x F pairs, a few per mille of the
 // near-set work.  FP32 partials store the potential as a (hi, lo) pair.
-constexpr int kSphereChunk = 256;
+constexpr int kSphereChunkMin = 16, kSphereChunkMax = 256;
+
+// Sphere sources per wave: enough waves (about 1024) to keep small systems
+// from running on a handful of long waves, at most kSphereChunkMax.
+static int sphere_chunk(int F, int ngroups) {
+  const long long want = ((long long)F * ngroups + 1023) / 1024;
+  const long long c = (want + kSphereChunkMin - 1) / kSphereChunkMin * kSphereChunkMin;
+  return (int)std::min<long long>(kSphereChunkMax, std::max<long long>(kSphereChunkMin, c));
+}
 
 template <typename Real>
 __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ tgt, int n,
-                                                    const double4* __restrict__ surf, int F,
+                                                    const double4* __restrict__ surf, int F, int chunk,
                                                     Real* __restrict__ part, long comp_stride, int slot0) {
   const int lane = threadIdx.x;
   const int first = blockIdx.x * kGroup;
-  const int kb = blockIdx.y * kSphereChunk, ke = min(F, kb + kSphereChunk);
+  const int kb = blockIdx.y * chunk, ke = min(F, kb + chunk);
   double tx[kTPL], ty[kTPL], tz[kTPL];
   double ph[kTPL], ex[kTPL], ey[kTPL], ez[kTPL];
 #pragma unroll
@@ -646,7 +772,7 @@ __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ 
     for (int j = 0; j < kTPL; ++j) {
       const double dx = tx[j] - a0.x, dy = ty[j] - a0.y, dz = tz[j] - a0.z;
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double ri = 1.0 / sqrt(r2);
+      const double ri = rsq(r2);
       const double ri2 = ri * ri;
       const double ri3 = ri * ri2;
       const double a = a0.w * ri;
@@ -771,6 +897,7 @@ template <typename Real>
 __global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* __restrict__ part, long comp_stride,
                                                   const double4* __restrict__ pos64, const int* __restrict__ perm,
                                                   const Desc* __restrict__ desc, int ndesc,
+                                                  const unsigned long long* __restrict__ cull, int ntiles,
                                                   double kc, const int* __restrict__ status, double* __restrict__ pot,
                                                   double* __restrict__ force, double* __restrict__ epart) {
   __shared__ double s[256];
@@ -810,9 +937,10 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* 
     for (int d = 0; d < ndesc; ++d) {
       const Desc ds = desc[d];
       if (ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.0) continue;  // the self pair
+      if (cull && !((cull[(long)d * ntiles + t / kTile] >> (t % kTile)) & 1ull)) continue;  // outside the sphere
       const double dx = -ds.sx, dy = -ds.sy, dz = p.z - (ds.sigma * p.z + ds.sz);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double ri = 1.0 / sqrt(r2);
+      const double ri = rsq(r2);
       const double a = ds.scale * ri;
       sphi += a;
       const double b = a * ri * ri;
@@ -963,7 +1091,7 @@ hsma_status DevicePlan::init(std::string& err) {
 
 void DevicePlan::free_arena() {
   void* ps[] = {d_key[0], d_key[1], d_val[0], d_val[1], d_hist, d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
-                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched};
+                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched, d_cull};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   d_key[0] = d_key[1] = nullptr;
@@ -978,6 +1106,7 @@ void DevicePlan::free_arena() {
   d_red = d_epart = nullptr;
   d_part = d_cpart = nullptr;
   d_csched = nullptr;
+  d_cull = nullptr;
   if (stage_ev) (void)hipEventSynchronize(stage_ev);  // an upload may still read the staging
   if (h_stage) (void)hipHostFree(h_stage);
   h_stage = nullptr;
@@ -1004,7 +1133,8 @@ DevicePlan::~DevicePlan() {
 }
 
 // Particle schedule for n particles: chunks sized so that a launch has
-// about `target` waves (and at least 8 tiles per chunk).
+// about `target` waves (and at least 2 tiles per chunk: small systems get
+// many short waves rather than a few long ones).
 static PartSched part_schedule(int64_t n, int ndesc, int target) {
   PartSched ps;
   ps.n = (int)n;
@@ -1013,9 +1143,15 @@ static PartSched part_schedule(int64_t n, int ndesc, int target) {
   ps.ndesc = ndesc;
   ps.F = ndesc * ntiles;
   long long want = std::max<long long>(1, (target + (long long)ps.ngroups - 1) / ps.ngroups);
-  want = std::min<long long>(want, std::max<long long>(1, ps.F / 8));
+  want = std::min<long long>(want, std::max<long long>(1, ps.F / 2));
   ps.chunk = (int)((ps.F + want - 1) / want);
   ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
+  // near pass: one wave per group, or up to kMaxNearSplit waves per group
+  // when there are fewer groups than about 2048
+  const long long nw = std::min<long long>({(long long)kMaxNearSplit, (long long)ps.F,
+                                            std::max<long long>(1, (2048 + ps.ngroups - 1) / ps.ngroups)});
+  ps.near_chunk = (int)((ps.F + nw - 1) / nw);
+  ps.nnear = (ps.F + ps.near_chunk - 1) / ps.near_chunk;
   return ps;
 }
 
@@ -1030,7 +1166,7 @@ static void check_schedule(const std::vector<Group>& groups, int ntiles, int tar
   nslots = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const long long F = (long long)groups[gi].ndesc * ntiles;
-    const long long want = std::max<long long>(1, std::min<long long>(std::max<long long>(1, F / 8),
+    const long long want = std::max<long long>(1, std::min<long long>(std::max<long long>(1, F / 2),
         (long long)((double)target * F / std::max<long long>(1, total) + 0.5)));
     const long long chunk = (F + want - 1) / want;
     const int nch = (int)((F + chunk - 1) / chunk);
@@ -1046,11 +1182,14 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
                                  size_t& ncwork) const {
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
   const int64_t ngroups = (n + kGroup - 1) / kGroup;
-  const int nsc = (host.prm.F + kSphereChunk - 1) / kSphereChunk;
+  // ngroups x sphere chunks <= 1024 + ngroups (F / kSphereChunkMax + 2) for
+  // every size (see sphere_chunk)
+  const size_t sph = 1024 + (size_t)ngroups * ((size_t)host.prm.F / kSphereChunkMax + 2);
   const size_t ncg = host.check_groups.size();
-  part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + (size_t)ngroups * (2 + nsc));
-  cpart_bytes = rb * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
-  nwork = (size_t)part_target + 2 * (size_t)ngroups + 2;
+  part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + (2 + kMaxNearSplit) * (size_t)ngroups + sph);
+  const size_t rbc = host.prm.near_rule == 1 ? sizeof(double) : rb;  // check sums' precision
+  cpart_bytes = rbc * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
+  nwork = (size_t)part_target + (2 + kMaxNearSplit) * (size_t)ngroups + 2;
   ncwork = (size_t)check_target_max + 2 * ncg + 2;
 }
 
@@ -1087,6 +1226,8 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   HIPCHK(hipMalloc(&d_part, part_bytes));
   HIPCHK(hipMalloc(&d_cpart, cpart_bytes));
   HIPCHK(hipMalloc((void**)&d_csched, sizeof(CheckSched) * ncg));
+  const size_t ncull = host.prm.near_rule == 1 ? host.desc_particles.size() * (size_t)cnt : 0;
+  if (ncull) HIPCHK(hipMalloc((void**)&d_cull, sizeof(unsigned long long) * ncull));
   HIPCHK(hipHostMalloc(&h_stage, sizeof(CheckSched) * ncg + 64));
   if (!stage_ev) HIPCHK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
   stage_bytes = sizeof(CheckSched) * ncg + 64;
@@ -1097,7 +1238,8 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   cwork_cap = ncwork;
   arena_bytes = sizeof(uint32_t) * cn * 2 + sizeof(int) * cn * 2 + sizeof(uint32_t) * 256 * crs +
                 sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
-                sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(CheckSched) * ncg;
+                sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(CheckSched) * ncg +
+                sizeof(unsigned long long) * ncull;
   cur_n = -1;
   return HSMA_OK;
 }
@@ -1118,11 +1260,13 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   std::vector<CheckSched> cs;
   int ncfar = 0, ncslots = 0;
   check_schedule(host.check_groups, ntiles, ctarget, cs, ncfar, ncslots);
-  const int nsc = (host.prm.F + kSphereChunk - 1) / kSphereChunk;
+  const int sch = sphere_chunk(host.prm.F, ps.ngroups);
+  const int nsc = (host.prm.F + sch - 1) / sch;
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
   const long comp = (long)ps.ngroups * kGroup;
-  if (rb * 5 * (size_t)comp * (ps.nch + 1 + nsc) > part_cap || rb * 5 * (size_t)kGroup * ncslots > cpart_cap ||
-      (size_t)ps.nch * ps.ngroups + ps.ngroups > work_cap || (size_t)ncfar + cs.size() > cwork_cap) {
+  const size_t rbc = host.prm.near_rule == 1 ? sizeof(double) : rb;
+  if (rb * 5 * (size_t)comp * (ps.nch + ps.nnear + nsc) > part_cap || rbc * 5 * (size_t)kGroup * ncslots > cpart_cap ||
+      (size_t)(ps.nch + ps.nnear) * ps.ngroups > work_cap || (size_t)ncfar + cs.size() > cwork_cap) {
     err = "internal error: work decomposition exceeds the reserved arena";
     return HSMA_ERR_DEVICE;
   }
@@ -1141,6 +1285,7 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   ncwork_ = ncfar;
   nchunks_ = ps.nch;
   nsphere_ = nsc;
+  sph_chunk_ = sch;
   nrsblk_ = (int)((n + kRsBlock - 1) / kRsBlock);
   return HSMA_OK;
 }
@@ -1169,67 +1314,92 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   if ((s = record(st, kStStep, 0, err)) != HSMA_OK) return s;
   hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(256), 0, st, n, d_xyz, d_q, (const StepParams*)d_sp, slab, d_pos_w, d_key[0],
                      d_val[0], d_red);
-  hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, nblk, (const double*)d_red, d_status);
-  // radix sort: 4 passes of 8 bits over the 30-bit keys (result back in buffer 0)
-  for (int pass = 0; pass < 4; ++pass) {
-    const int sh = 8 * pass;
-    const int a = pass & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_rs_hist, dim3(nrsblk_), dim3(256), 0, st, (const uint32_t*)d_key[a], n, sh, d_hist, nrsblk_);
-    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, d_hist, 256 * nrsblk_);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nrsblk_), dim3(256), 0, st, (const uint32_t*)d_key[a],
-                       (const int*)d_val[a], d_key[b], d_val[b], n, sh, (const uint32_t*)d_hist, nrsblk_);
+  if (n <= kSmallSort) {
+    hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, n, nblk, (const double*)d_red, d_status,
+                       (const uint32_t*)d_key[0], (const double4*)d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
+                       d_tile_h, d_perm);
+  } else {
+    hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, nblk, (const double*)d_red, d_status);
+    // radix sort: 4 passes of 8 bits over the 30-bit keys (result back in buffer 0)
+    for (int pass = 0; pass < 4; ++pass) {
+      const int sh = 8 * pass;
+      const int a = pass & 1, b = a ^ 1;
+      hipLaunchKernelGGL(k_rs_hist, dim3(nrsblk_), dim3(256), 0, st, (const uint32_t*)d_key[a], n, sh, d_hist,
+                         nrsblk_);
+      hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, d_hist, 256 * nrsblk_);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(nrsblk_), dim3(256), 0, st, (const uint32_t*)d_key[a],
+                         (const int*)d_val[a], d_key[b], d_val[b], n, sh, (const uint32_t*)d_hist, nrsblk_);
+    }
+    hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
+                       d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
   }
-  hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
-                     d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
+  const unsigned long long* cullp = nullptr;
+  if (host.prm.near_rule == 1) {
+    hipLaunchKernelGGL(k_cull, dim3(ntiles_, (int)host.desc_particles.size()), dim3(64), 0, st, n, ntiles_,
+                       (const double4*)d_pos64, (const Desc*)d_desc_part, (const StepParams*)d_sp, d_cull);
+    cullp = d_cull;
+  }
   const int ncheck = (int)host.check_axis.size();
   const int ncg = (int)host.check_groups.size();
   const long ccomp = kGroup, cslot = 5L * kGroup;
   const long comp = (long)ngroups_ * kGroup;
   const long slot = 5L * comp;
   const int F = host.prm.F;
-#define HSMA_SUMS(Real, S, SRC, SURF)                                                                               \
+  // check sums: FP64 in the FP64 path, and also with the sphere near set,
+  // whose face rows are differences Phi_B(x+) - Phi_B(x-) of two full sums
+  // (a source near x- has its periodic copy near x+; the two large terms
+  // cancel exactly, their FP32 rounding would not)
+#define HSMA_CHECKS(RealC, SC, SRCC)                                                                                \
   do {                                                                                                              \
     if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;                                                    \
-    hipLaunchKernelGGL((k_pair<Real, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,   \
+    hipLaunchKernelGGL((k_pair<RealC, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,  \
                        (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
                        (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_cpart, ccomp,     \
-                       cslot);                                                                                      \
-    hipLaunchKernelGGL((k_pair<Real, true, false>), dim3(ncg), dim3(64), 0, st, (const double4*)d_check_pos,        \
+                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (RealC*)d_cpart,   \
+                       ccomp, cslot);                                                                               \
+    hipLaunchKernelGGL((k_pair<RealC, true, false>), dim3(ncg), dim3(64), 0, st, (const double4*)d_check_pos,       \
                        (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
                        (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_cpart, ccomp,     \
-                       cslot);                                                                                      \
+                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (RealC*)d_cpart,   \
+                       ccomp, cslot);                                                                               \
     if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;                                                    \
-    hipLaunchKernelGGL(k_reduce_check<Real>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,      \
-                       (const CheckSched*)d_csched, (const int*)d_check_axis, (const Real*)d_cpart, d_v);          \
-    hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw,                   \
-                       (const double*)d_v, d_A);                                                                    \
-    hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,     \
-                       (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,     \
-                       d_surf32, d_surf64, d_qd);                                                                   \
+    hipLaunchKernelGGL(k_reduce_check<RealC>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,     \
+                       (const CheckSched*)d_csched, (const int*)d_check_axis, (const RealC*)d_cpart, d_v);         \
+  } while (0)
+#define HSMA_PARTICLES(Real, S, SRC)                                                                                \
+  do {                                                                                                              \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
                        (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_part, comp, slot); \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (Real*)d_part, comp, \
+                       slot);                                                                                       \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
-    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
-                       (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_, (const Desc*)d_desc_part,     \
-                       ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, (const S*)SRC,                   \
-                       (const double4*)d_pos64, (const StepParams*)d_sp, (Real*)d_part, comp, slot);                \
+    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, st,          \
+                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
+                       (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (Real*)d_part, comp, \
+                       slot);                                                                                       \
     if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;                                                   \
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
-                       (const double4*)d_surf64, F, (Real*)d_part, comp, nchunks_ + 1);                             \
+                       (const double4*)d_surf64, F, sph_chunk_, (Real*)d_part, comp, nchunks_ + psched_.nnear);     \
     if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;                                                   \
-    hipLaunchKernelGGL(k_finalize<Real>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + 1 + nsphere_,                 \
+    hipLaunchKernelGGL(k_finalize<Real>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + psched_.nnear + nsphere_,     \
                        (const Real*)d_part, comp, (const double4*)d_pos64, (const int*)d_perm,                     \
-                       (const Desc*)d_desc_part, (int)host.desc_particles.size(), host.prm.coulomb_k,               \
-                       (const int*)d_status, d_pot, d_force, d_epart);                                              \
+                       (const Desc*)d_desc_part, (int)host.desc_particles.size(), cullp, ntiles_,                   \
+                       host.prm.coulomb_k, (const int*)d_status, d_pot, d_force, d_epart);                          \
   } while (0)
-  if (fp64) HSMA_SUMS(double, double4, d_src64, d_surf64);
-  else HSMA_SUMS(float, float4, d_src32, d_surf32);
-#undef HSMA_SUMS
+  if (fp64 || host.prm.near_rule == 1) HSMA_CHECKS(double, double4, d_src64);
+  else HSMA_CHECKS(float, float4, d_src32);
+  hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw, (const double*)d_v,
+                     d_A);
+  hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
+                     (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf, d_surf32,
+                     d_surf64, d_qd);
+  if (fp64) HSMA_PARTICLES(double, double4, d_src64);
+  else HSMA_PARTICLES(float, float4, d_src32);
+#undef HSMA_CHECKS
+#undef HSMA_PARTICLES
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nblk, (const double*)d_epart,
                      d_energy ? d_energy : d_energy_scratch);
   HIPCHK(hipGetLastError());
@@ -1256,8 +1426,18 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   const double vol = host.L[0] * host.L[1] * host.L[2];
   const double ext = std::cbrt(kTile * vol / std::max(1, n));
   const double rc = fp64 ? 1e-9 * ext : close_factor * ext;
-  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, st, (StepParams*)d_sp, lo, L, hbox, rc * rc);
-  HIPCHK(hipGetLastError());
+  // the step-parameter block is rewritten only when it changes (same
+  // stream order as the kernels that read it)
+  // sphere radius of the current box, R = lambda |L| / 2 with the diagonal
+  // summed left to right (the sphere near set is decided on exactly this R)
+  const double R = host.prm.lambda * 0.5 * std::sqrt(host.L[0] * host.L[0] + host.L[1] * host.L[1] + host.L[2] * host.L[2]);
+  const double spv[11] = {lo.x, lo.y, lo.z, L.x, L.y, L.z, hbox.x, hbox.y, hbox.z, rc * rc, R * R};
+  if (!sp_valid || std::memcmp(spv, sp_host, sizeof(spv)) != 0) {
+    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, st, (StepParams*)d_sp, lo, L, hbox, rc * rc, R * R);
+    HIPCHK(hipGetLastError());
+    std::memcpy(sp_host, spv, sizeof(spv));
+    sp_valid = true;
+  }
   // Graph replay: a step depends only on (n, buffers, stream) once the box
   // scalars live in d_sp.  It is captured on the second consecutive call
   // with the same key and replayed afterwards.

@@ -373,9 +373,9 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     return HSMA_ERR_INVALID_ARG;
   }
   if (prm.p < 1 || prm.p > 24 || prm.K < 1 || prm.F < 4 || prm.F > 1000000 ||
-      (prm.surface_rule != 0 && prm.surface_rule != 1) ||
+      (prm.surface_rule != 0 && prm.surface_rule != 1) || (prm.near_rule != 0 && prm.near_rule != 1) ||
       (prm.precision != HSMA_FP64 && prm.precision != HSMA_FP32C) || !(prm.lambda > 0)) {
-    msg = "invalid method parameter (p in 1..24, K >= 1, F >= 4, rule 0/1, precision, lambda > 0)";
+    msg = "invalid method parameter (p in 1..24, K >= 1, F >= 4, surface/near rule 0/1, precision, lambda > 0)";
     return HSMA_ERR_INVALID_ARG;
   }
   if (prm.surface_rule == 1) {
@@ -450,6 +450,24 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
         }
   }
 
+  if (prm.near_rule == 1) {
+    // sphere near set: drop the image cells that cannot reach into the
+    // sphere (nearest point of [s - L/2, s + L/2] at least R from the
+    // centre, with a margin against rounding); the kernels test the rest
+    // source by source
+    std::vector<Desc> kept;
+    for (const Desc& d : P.desc_particles) {
+      const double sh[3] = {d.sx, d.sy, d.sz};
+      double m2 = 0;
+      for (int c = 0; c < 3; ++c) {
+        const double g = std::max(0.0, std::fabs(sh[c]) - 0.5 * L[c]);
+        m2 += g * g;
+      }
+      if (m2 <= R * R * (1 + 1e-9)) kept.push_back(d);
+    }
+    P.desc_particles.swap(kept);
+  }
+
   // ---- check targets and fitting rows
   const int K = prm.K;
   std::vector<double> xm;
@@ -480,6 +498,44 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
       M[size_t(K + t) * nb + j] = L[d] / R * (bg2[3 * j + d] - bg[3 * j + d]);
     }
   }
+  // Face-pair check targets, grouped by axis, and their columns of Praw
+  // (A = Praw v, v = raw potential and field component at every target).
+  // Stencil rule: one target x- per pair, summed over the telescoped sets
+  // (cells at k_d = -2 minus cells at k_d = +1 give Phi_B(x+) - Phi_B(x-)
+  // at x-).  Sphere rule: the set B is no union of cells, so both x- and
+  // x+ = x- + L_d e_d are targets over the near set and the row difference
+  // is taken in Praw (+ for x+, - for x-).
+  // Rows: Y_val = -(Phi+ - Phi-);  Y_der = -L_d d_d(Phi+ - Phi-) = L_d (E_d+ - E_d-).
+  const bool sphere_near = prm.near_rule == 1;
+  const int nface = sphere_near ? 2 * K : K;
+  auto face_targets = [&](const std::vector<double>& Pinv, int ncheck, int& tcount) {
+    for (int side = sphere_near ? 0 : 1; side < 2; ++side) {
+      const double sgn = sphere_near ? (side == 0 ? -1.0 : 1.0) : 1.0;
+      for (int d = 0; d < naxes; ++d) {
+        std::vector<int> ts;
+        for (int t = 0; t < K; ++t)
+          if (pax[t] == d) ts.push_back(t);
+        const std::vector<Desc>& set = sphere_near ? P.desc_particles : axis_tables[d];
+        for (size_t g0 = 0; g0 < ts.size(); g0 += kGroup) {
+          Group grp{tcount, (int)std::min<size_t>(kGroup, ts.size() - g0), (int)P.desc_check.size(),
+                    (int)set.size()};
+          for (int i = 0; i < grp.count; ++i) {
+            const int t = ts[g0 + i];
+            for (int c = 0; c < 3; ++c)
+              P.check_pos.push_back(xm[3 * t + c] + (sphere_near && side == 1 && c == d ? L[d] : 0.0));
+            P.check_axis.push_back(d);
+            for (int j = 0; j < nb; ++j) {
+              P.Praw[size_t(j) * 2 * ncheck + 2 * tcount] += -sgn * Pinv[size_t(j) * P.nrows + t];
+              P.Praw[size_t(j) * 2 * ncheck + 2 * tcount + 1] += sgn * L[d] * Pinv[size_t(j) * P.nrows + K + t];
+            }
+            ++tcount;
+          }
+          P.check_groups.push_back(grp);
+          P.desc_check.insert(P.desc_check.end(), set.begin(), set.end());
+        }
+      }
+    }
+  };
   std::vector<std::vector<double>> Tb;  // per interface: T applied to basis columns
   if (slab) {
     DtN T(nz, L[0], L[1]);
@@ -522,31 +578,10 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
       return HSMA_ERR_RANK;
     }
     // ---- targets: face pairs grouped by axis, then the two interface grids
-    const int ncheck = K + 2 * ngrid;
+    const int ncheck = nface + 2 * ngrid;
     P.Praw.assign(size_t(nb) * 2 * ncheck, 0.0);
     int tcount = 0;
-    for (int d = 0; d < naxes; ++d) {
-      std::vector<int> ts;
-      for (int t = 0; t < K; ++t)
-        if (pax[t] == d) ts.push_back(t);
-      for (size_t g0 = 0; g0 < ts.size(); g0 += kGroup) {
-        Group grp{tcount, (int)std::min<size_t>(kGroup, ts.size() - g0), (int)P.desc_check.size(),
-                  (int)axis_tables[d].size()};
-        for (int i = 0; i < grp.count; ++i) {
-          const int t = ts[g0 + i];
-          for (int c = 0; c < 3; ++c) P.check_pos.push_back(xm[3 * t + c]);
-          P.check_axis.push_back(d);
-          // Y_val = -(dPhi) = -v[2s];  Y_der = -L_d d_d(dPhi) = +L_d dE_d = L_d v[2s+1]
-          for (int j = 0; j < nb; ++j) {
-            P.Praw[size_t(j) * 2 * ncheck + 2 * tcount] += -Pinv[size_t(j) * P.nrows + t];
-            P.Praw[size_t(j) * 2 * ncheck + 2 * tcount + 1] += L[d] * Pinv[size_t(j) * P.nrows + K + t];
-          }
-          ++tcount;
-        }
-        P.check_groups.push_back(grp);
-        P.desc_check.insert(P.desc_check.end(), axis_tables[d].begin(), axis_tables[d].end());
-      }
-    }
+    face_targets(Pinv, ncheck, tcount);
     for (int s = 0; s < 2; ++s) {
       const double gam = s == 0 ? prm.gamma_up : prm.gamma_low;
       const double sgn = s == 0 ? 1.0 : -1.0;
@@ -591,30 +626,10 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
       msg = "least-squares matrix is rank deficient";
       return HSMA_ERR_RANK;
     }
-    const int ncheck = K;
+    const int ncheck = nface;
     P.Praw.assign(size_t(nb) * 2 * ncheck, 0.0);
     int tcount = 0;
-    for (int d = 0; d < 3; ++d) {
-      std::vector<int> ts;
-      for (int t = 0; t < K; ++t)
-        if (pax[t] == d) ts.push_back(t);
-      for (size_t g0 = 0; g0 < ts.size(); g0 += kGroup) {
-        Group grp{tcount, (int)std::min<size_t>(kGroup, ts.size() - g0), (int)P.desc_check.size(),
-                  (int)axis_tables[d].size()};
-        for (int i = 0; i < grp.count; ++i) {
-          const int t = ts[g0 + i];
-          for (int c = 0; c < 3; ++c) P.check_pos.push_back(xm[3 * t + c]);
-          P.check_axis.push_back(d);
-          for (int j = 0; j < nb; ++j) {
-            P.Praw[size_t(j) * 2 * ncheck + 2 * tcount] += -Pinv[size_t(j) * P.nrows + t];
-            P.Praw[size_t(j) * 2 * ncheck + 2 * tcount + 1] += L[d] * Pinv[size_t(j) * P.nrows + K + t];
-          }
-          ++tcount;
-        }
-        P.check_groups.push_back(grp);
-        P.desc_check.insert(P.desc_check.end(), axis_tables[d].begin(), axis_tables[d].end());
-      }
-    }
+    face_targets(Pinv, ncheck, tcount);
   }
 
   // ---- sphere quadrature and the maps A -> (Q, D)

@@ -36,7 +36,8 @@ class _CParams(ctypes.Structure):
     _fields_ = [
         ("geometry", ctypes.c_int), ("precision", ctypes.c_int), ("lambda_", ctypes.c_double),
         ("p", ctypes.c_int), ("K", ctypes.c_int), ("F", ctypes.c_int), ("Fw", ctypes.c_int),
-        ("surface_rule", ctypes.c_int), ("M", ctypes.c_int), ("gamma_up", ctypes.c_double),
+        ("surface_rule", ctypes.c_int), ("near_rule", ctypes.c_int), ("M", ctypes.c_int),
+        ("gamma_up", ctypes.c_double),
         ("gamma_low", ctypes.c_double), ("nz", ctypes.c_int), ("coulomb_k", ctypes.c_double),
     ]
 
@@ -80,6 +81,7 @@ class Params:
     F: int = 800
     Fw: int = 0
     surface_rule: int = 0
+    near_rule: int = 0
     M: int = 10
     gamma_up: float = 0.0
     gamma_low: float = 0.0
@@ -89,12 +91,13 @@ class Params:
     @staticmethod
     def from_workload(w, precision: Optional[int] = None) -> "Params":
         return Params(geometry=w.geometry, precision=w.precision if precision is None else precision,
-                      lam=w.lam, p=w.p, K=w.K, F=w.F, Fw=w.Fw, surface_rule=w.surface_rule, M=w.M,
-                      gamma_up=w.gamma_up, gamma_low=w.gamma_low, nz=w.nz)
+                      lam=w.lam, p=w.p, K=w.K, F=w.F, Fw=w.Fw, surface_rule=w.surface_rule,
+                      near_rule=w.near_rule, M=w.M, gamma_up=w.gamma_up, gamma_low=w.gamma_low, nz=w.nz)
 
     def _c(self) -> _CParams:
         return _CParams(self.geometry, self.precision, self.lam, self.p, self.K, self.F, self.Fw,
-                        self.surface_rule, self.M, self.gamma_up, self.gamma_low, self.nz, self.coulomb_k)
+                        self.surface_rule, self.near_rule, self.M, self.gamma_up, self.gamma_low, self.nz,
+                        self.coulomb_k)
 
 
 _lib = None

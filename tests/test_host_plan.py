@@ -215,6 +215,74 @@ def test_plan_2d_reproduces_oracle_fit():
     assert want == got
 
 
+def _raw_check_values(cpos, cax, cd):
+    """Oracle potential and field component at every product check target:
+    face targets match an oracle x- or x+ point of the same axis, interface
+    targets a grid point."""
+    v = np.empty(2 * len(cpos))
+    for t, c in enumerate(cpos):
+        a = cax[t]
+        found = False
+        for pts, phi, E in ((cd["xm"], cd["phi_m"], cd["E_m"]), (cd["xp"], cd["phi_p"], cd["E_p"])):
+            if a == 2 and "top" in cd:
+                break
+            d = np.abs(pts - c).sum(1) + 1e3 * (cd["axis"] != a)
+            i = int(np.argmin(d))
+            if d[i] < 1e-12:
+                v[2 * t], v[2 * t + 1] = phi[i], E[i, a]
+                found = True
+                break
+        if not found:
+            side = cd["top"] if c[2] > 0 else cd["bottom"]
+            i = int(np.argmin(np.abs(side["points"] - c).sum(1)))
+            assert np.abs(side["points"][i] - c).max() < 1e-12
+            v[2 * t], v[2 * t + 1] = side["phi"][i], side["E"][i, 2]
+    return v
+
+
+def test_plan_sphere_near_set_reproduces_oracle_fit():
+    """near_rule=1: both x- and x+ are check targets over the culled set and
+    Praw takes the row differences; fed the oracle's values at those points
+    the library's plan gives the oracle's harmonic function (3D and slab).
+    The slab image table keeps exactly the cells and layers that reach into
+    the sphere."""
+    lib_or_skip()
+    w = workloads.C1
+    pos, q, lo, L = workloads.make_system(w)
+    r = ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, near_rule=1)
+    hp = hs.HostPlan(hs.Params(p=w.p, K=w.K, F=w.F, lam=w.lam, near_rule=1, precision=0), lo, L)
+    cpos = hp.get("check_pos").reshape(-1, 3)
+    cax = hp.get("check_axis").astype(int)
+    assert len(cpos) == 2 * w.K
+    A = _product_A(hp, _raw_check_values(cpos, cax, r.check_data))
+    pts = np.random.default_rng(2).uniform(-0.5, 0.5, (40, 3)) * L
+    u_or = obasis.values(pts, r.R, w.p) @ r.A
+    assert np.abs(u_or - _u_product(A, r.R, w.p, pts)).max() < 1e-10 * np.abs(u_or).max()
+    assert hp.get("desc_particles").reshape(-1, 5).shape[0] == 27
+    # slab
+    pos, q, lo, L = workloads.small_system(10, (20.0, 20.0, 10.0), 5, geometry=1)
+    p, K, F, lam, M, gu, gl, nz = 6, 100, 200, 1.6, 6, -0.6, 0.3, 24
+    r = ohsma.hsma2d(pos, q, lo, L, p, K, F, lam, M, gu, gl, nz, near_rule=1)
+    hp = hs.HostPlan(hs.Params(geometry=1, p=p, K=K, F=F, lam=lam, M=M, gamma_up=gu, gamma_low=gl, nz=nz,
+                               near_rule=1, precision=0), lo, L)
+    cpos = hp.get("check_pos").reshape(-1, 3)
+    cax = hp.get("check_axis").astype(int)
+    assert len(cpos) == 2 * K + 2 * nz * nz
+    A = _product_A(hp, _raw_check_values(cpos, cax, r.check_data))
+    pts = np.random.default_rng(3).uniform(-0.5, 0.5, (40, 3)) * L
+    u_or = obasis.values(pts, r.R, p) @ r.A
+    assert np.abs(u_or - _u_product(A, r.R, p, pts)).max() < 1e-9 * np.abs(u_or).max()
+    d = hp.get("desc_particles").reshape(-1, 5)
+    R = ohsma._radius(L, lam)
+    want = 0
+    for a in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            for l in range(-M, M + 1):
+                gap = np.maximum(0, np.abs(np.array([a * L[0], b * L[1], l * L[2]])) - L / 2)
+                want += (gap ** 2).sum() < R * R
+    assert d.shape[0] == want < 9 * (2 * M + 1)
+
+
 def test_sort_key_is_a_hilbert_curve():
     """Cells in key order form a face-adjacent walk through the grid (the
     property that keeps sorted tiles compact); keys are a bijection."""
