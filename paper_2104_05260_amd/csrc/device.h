@@ -74,6 +74,8 @@ struct DevicePlan {
   void* d_cpart = nullptr;
   CheckSched* d_csched = nullptr;
   unsigned long long* d_cull = nullptr;  // sphere near set: ndesc x ntiles source masks
+  unsigned* d_clist = nullptr;           // sphere near set: non-empty (entry, tile) pairs
+  int* d_ccount = nullptr;
   hipEvent_t stage_ev = nullptr;
   PartSched psched_{};
   int ntiles_ = 0, ngroups_ = 0, ncwork_ = 0, nchunks_ = 0, nsphere_ = 0, sph_chunk_ = 0,
@@ -117,7 +119,7 @@ struct DevicePlan {
 
   // step-parameter block and graph replay
   void* d_sp = nullptr;
-  double sp_host[11] = {0};     // last values written to d_sp
+  double sp_host[12] = {0};     // last values written to d_sp
   bool sp_valid = false;
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;

@@ -98,15 +98,18 @@ uint32_t hilbert_key_host(uint32_t x, uint32_t y, uint32_t z) { return hilbert_k
 // kernels so that a captured step graph does not depend on the box.
 struct StepParams {
   double3 lo, L, hbox;
-  double rc2;
-  double R2;  // squared sphere radius (sphere near set)
+  double rc2;   // close-pair radius^2 of the particle sums
+  double rc2c;  // the same for the check sums (< 0: every tile goes through the far kernel)
+  double R2;    // squared sphere radius (sphere near set)
 };
 
-__global__ void k_set_params(StepParams* sp, double3 lo, double3 L, double3 hbox, double rc2, double R2) {
+__global__ void k_set_params(StepParams* sp, double3 lo, double3 L, double3 hbox, double rc2, double rc2c,
+                             double R2) {
   sp->lo = lo;
   sp->L = L;
   sp->hbox = hbox;
   sp->rc2 = rc2;
+  sp->rc2c = rc2c;
   sp->R2 = R2;
 }
 
@@ -401,6 +404,44 @@ __global__ __launch_bounds__(64) void k_cull(int n, int ntiles, const double4* _
   if (threadIdx.x == 0) cull[(long)d * ntiles + t] = m;
 }
 
+// The (image entry, tile) pairs with at least one source inside the sphere,
+// in entry-major order, packed as d << kTileBits | t; count in *count.  One
+// block: each thread counts a contiguous run of entries, a block scan gives
+// the offsets, the runs are written in order.
+constexpr int kTileBits = 20;
+constexpr int kCompactThreads = 1024;
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(int nent, int ntiles,
+                                                             const unsigned long long* __restrict__ cull,
+                                                             unsigned* __restrict__ list, int* __restrict__ count) {
+  __shared__ int sc[kCompactThreads];
+  const int per = (nent + kCompactThreads - 1) / kCompactThreads;
+  const int b = threadIdx.x * per, e = min(nent, b + per);
+  int c = 0;
+  for (int i = b; i < e; ++i) c += cull[i] != 0ull;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 1; o < kCompactThreads; o <<= 1) {
+    const int v = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+    __syncthreads();
+    sc[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int w = sc[threadIdx.x] - c;
+  for (int i = b; i < e; ++i)
+    if (cull[i] != 0ull) list[w++] = ((unsigned)(i / ntiles) << kTileBits) | (unsigned)(i % ntiles);
+  if (threadIdx.x == kCompactThreads - 1) *count = sc[threadIdx.x];
+}
+
+// Sphere near set view passed to the pair kernels (all null for the cell
+// stencil): source masks per (entry, tile), the compacted non-empty pairs
+// and their number.
+struct CullView {
+  const unsigned long long* mask;
+  const unsigned* list;
+  const int* count;
+};
+
 // ----------------------------------------------------------------- pair sums
 // One wave per work item: a group of up to 64*kTPL targets against a
 // contiguous range of (image entry, source tile) pairs.  Sources are read
@@ -451,11 +492,12 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                                              const float4* __restrict__ tile_h,
                                              const typename SrcT<Real>::T* __restrict__ src,
                                              const double4* __restrict__ pos64, const StepParams* __restrict__ sp,
-                                             const unsigned long long* __restrict__ cull,
+                                             CullView cv,
                                              Real* __restrict__ part, long comp_stride, long slot_stride) {
   typedef typename SrcT<Real>::T S;
   Work w;
   Group g;
+  int part_i = 0, nparts = 1;  // this wave's share of the group's range
   if constexpr (PARTICLES) {
     int gi;
     if constexpr (NEAR) {
@@ -465,11 +507,15 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       gi = blockIdx.x - c * ps.ngroups;
       const int f0 = c * ps.near_chunk;
       w = Work{gi, f0, min(ps.F, f0 + ps.near_chunk), ps.nch + c};
+      part_i = c;
+      nparts = ps.nnear;
     } else {
       const int c = blockIdx.x / ps.ngroups;
       gi = blockIdx.x - c * ps.ngroups;
       const int f0 = c * ps.chunk;
       w = Work{gi, f0, min(ps.F, f0 + ps.chunk), c};
+      part_i = c;
+      nparts = ps.nch;
     }
     g = Group{gi * kGroup, min(kGroup, ps.n - gi * kGroup), 0, ps.ndesc};
   } else {
@@ -495,10 +541,12 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       const int c = blockIdx.x - cs.first_work;
       const int f0 = c * cs.chunk;
       w = Work{gi, f0, min(F, f0 + cs.chunk), cs.slot0 + c};
+      part_i = c;
+      nparts = cs.nch;
     }
   }
   const double3 hbox = sp->hbox;
-  const double rc2 = sp->rc2;
+  const double rc2 = PARTICLES ? sp->rc2 : sp->rc2c;
   const int lane = threadIdx.x;
   bool valid[kTPL];
   Real ox[kTPL], oy[kTPL], oz[kTPL];
@@ -656,7 +704,72 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   const int own0 = PARTICLES ? g.first / kTile : 0;
   const int own1 = PARTICLES ? (g.first + g.count - 1) / kTile : -1;
 
-  int f = w.f0;
+  const unsigned long long* __restrict__ cull = cv.mask;
+  if (cv.list) {
+    // sphere near set: the wave takes its share of the compacted non-empty
+    // (entry, tile) pairs (the same share of the same list for every group)
+    const int C = *cv.count;
+    const int per = (C + nparts - 1) / nparts;
+    const int f0 = min(C, part_i * per), f1 = min(C, f0 + per);
+    const unsigned tmask = (1u << kTileBits) - 1u;
+    if constexpr (NEAR) {
+      for (int fb = f0; fb < f1; fb += kWave) {
+        const int fl = fb + lane;
+        bool near = false;
+        if (fl < f1) {
+          const unsigned e = cv.list[fl];
+          const int tile = (int)(e & tmask);
+          const Desc dsl = desc[g.desc_off + (int)(e >> kTileBits)];
+          const double4 cs = tile_c[tile];
+          const float4 hs = tile_h[tile];
+          const double dlx = __dsub_rn(__dadd_rn(cs.x, dsl.sx), cgx);
+          const double dly = __dsub_rn(__dadd_rn(cs.y, dsl.sy), cgy);
+          const double dlz = shifted_dz(dsl, cs.z, cgz);
+          near = gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+                         __dadd_rn(hgz, (double)hs.z)) < rc2;
+        }
+        unsigned long long m = __ballot(near);
+        while (m) {
+          const int l = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const unsigned e = cv.list[fb + l];
+          const int di = (int)(e >> kTileBits), nt = (int)(e & tmask);
+          const Desc ds = desc[g.desc_off + di];
+          const double4 cs = tile_c[nt];
+          const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+          const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+          const double dlz = shifted_dz(ds, cs.z, cgz);
+          do_tile(ds, nt >= own0 && nt <= own1, nt, dlx, dly, dlz, cull[(long)di * ntiles + nt]);
+        }
+      }
+    } else {
+      int cur = -1;
+      Desc ds{};
+      bool img_far = false;
+      for (int f = f0; f < f1; ++f) {
+        const unsigned e = cv.list[f];
+        const int di = (int)(e >> kTileBits), tile = (int)(e & tmask);
+        if (di != cur) {
+          cur = di;
+          ds = desc[g.desc_off + di];
+          img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
+                            __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
+        }
+        const double4 cs = tile_c[tile];
+        const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+        const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+        const double dlz = shifted_dz(ds, cs.z, cgz);
+        if (!img_far) {
+          const float4 hs = tile_h[tile];
+          if (gap2_of(dlx, dly, dlz, __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+                      __dadd_rn(hgz, (double)hs.z)) < rc2)
+            continue;  // summed by the near pass
+        }
+        do_tile(ds, tile >= own0 && tile <= own1, tile, dlx, dly, dlz, cull[(long)di * ntiles + tile]);
+      }
+    }
+  }
+  int f = cv.list ? w.f1 : w.f0;  // the cell stencil walks [f0, f1) of the entry-major range
   while (f < w.f1) {
     const int di = f / ntiles;
     const int t0 = f - di * ntiles;
@@ -1091,7 +1204,7 @@ hsma_status DevicePlan::init(std::string& err) {
 
 void DevicePlan::free_arena() {
   void* ps[] = {d_key[0], d_key[1], d_val[0], d_val[1], d_hist, d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
-                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched, d_cull};
+                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched, d_cull, d_clist, d_ccount};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   d_key[0] = d_key[1] = nullptr;
@@ -1107,6 +1220,8 @@ void DevicePlan::free_arena() {
   d_part = d_cpart = nullptr;
   d_csched = nullptr;
   d_cull = nullptr;
+  d_clist = nullptr;
+  d_ccount = nullptr;
   if (stage_ev) (void)hipEventSynchronize(stage_ev);  // an upload may still read the staging
   if (h_stage) (void)hipHostFree(h_stage);
   h_stage = nullptr;
@@ -1227,7 +1342,11 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   HIPCHK(hipMalloc(&d_cpart, cpart_bytes));
   HIPCHK(hipMalloc((void**)&d_csched, sizeof(CheckSched) * ncg));
   const size_t ncull = host.prm.near_rule == 1 ? host.desc_particles.size() * (size_t)cnt : 0;
-  if (ncull) HIPCHK(hipMalloc((void**)&d_cull, sizeof(unsigned long long) * ncull));
+  if (ncull) {
+    HIPCHK(hipMalloc((void**)&d_cull, sizeof(unsigned long long) * ncull));
+    HIPCHK(hipMalloc((void**)&d_clist, sizeof(unsigned) * ncull));
+    HIPCHK(hipMalloc((void**)&d_ccount, sizeof(int)));
+  }
   HIPCHK(hipHostMalloc(&h_stage, sizeof(CheckSched) * ncg + 64));
   if (!stage_ev) HIPCHK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
   stage_bytes = sizeof(CheckSched) * ncg + 64;
@@ -1239,7 +1358,7 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   arena_bytes = sizeof(uint32_t) * cn * 2 + sizeof(int) * cn * 2 + sizeof(uint32_t) * 256 * crs +
                 sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
                 sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(CheckSched) * ncg +
-                sizeof(unsigned long long) * ncull;
+                (sizeof(unsigned long long) + sizeof(unsigned)) * ncull;
   cur_n = -1;
   return HSMA_OK;
 }
@@ -1334,10 +1453,15 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                        d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
   }
   const unsigned long long* cullp = nullptr;
+  CullView cv{nullptr, nullptr, nullptr};
   if (host.prm.near_rule == 1) {
-    hipLaunchKernelGGL(k_cull, dim3(ntiles_, (int)host.desc_particles.size()), dim3(64), 0, st, n, ntiles_,
-                       (const double4*)d_pos64, (const Desc*)d_desc_part, (const StepParams*)d_sp, d_cull);
+    const int nd = (int)host.desc_particles.size();
+    hipLaunchKernelGGL(k_cull, dim3(ntiles_, nd), dim3(64), 0, st, n, ntiles_, (const double4*)d_pos64,
+                       (const Desc*)d_desc_part, (const StepParams*)d_sp, d_cull);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, nd * ntiles_, ntiles_,
+                       (const unsigned long long*)d_cull, d_clist, d_ccount);
     cullp = d_cull;
+    cv = CullView{d_cull, d_clist, d_ccount};
   }
   const int ncheck = (int)host.check_axis.size();
   const int ncg = (int)host.check_groups.size();
@@ -1355,12 +1479,12 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     hipLaunchKernelGGL((k_pair<RealC, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,  \
                        (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
                        (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
-                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (RealC*)d_cpart,   \
+                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (RealC*)d_cpart,   \
                        ccomp, cslot);                                                                               \
     hipLaunchKernelGGL((k_pair<RealC, true, false>), dim3(ncg), dim3(64), 0, st, (const double4*)d_check_pos,       \
                        (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
                        (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
-                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (RealC*)d_cpart,   \
+                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (RealC*)d_cpart,   \
                        ccomp, cslot);                                                                               \
     if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;                                                    \
     hipLaunchKernelGGL(k_reduce_check<RealC>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,     \
@@ -1372,13 +1496,13 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
                        (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (Real*)d_part, comp, \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
                        slot);                                                                                       \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, st,          \
                        (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cullp, (Real*)d_part, comp, \
+                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
                        slot);                                                                                       \
     if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;                                                   \
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
@@ -1414,6 +1538,10 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
     err = "too many particles for one call";
     return HSMA_ERR_INVALID_ARG;
   }
+  if (host.prm.near_rule == 1 && (n64 + kTile - 1) / kTile > (int64_t)1 << kTileBits) {
+    err = "too many particles for the sphere near set (at most 2^26)";
+    return HSMA_ERR_INVALID_ARG;
+  }
   hsma_status s = prepare(n64, st, err);
   if (s != HSMA_OK) return s;
   const int n = (int)n64;
@@ -1431,9 +1559,14 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   // sphere radius of the current box, R = lambda |L| / 2 with the diagonal
   // summed left to right (the sphere near set is decided on exactly this R)
   const double R = host.prm.lambda * 0.5 * std::sqrt(host.L[0] * host.L[0] + host.L[1] * host.L[1] + host.L[2] * host.L[2]);
-  const double spv[11] = {lo.x, lo.y, lo.z, L.x, L.y, L.z, hbox.x, hbox.y, hbox.z, rc * rc, R * R};
+  // FP64 check sums need neither close-pair corrections nor self exclusion:
+  // all their tiles go through the far kernel (a face check group spans a
+  // whole face, so its box overlaps many tiles)
+  const bool fp64_checks = fp64 || host.prm.near_rule == 1;
+  const double rc2c = fp64_checks ? -1.0 : rc * rc;
+  const double spv[12] = {lo.x, lo.y, lo.z, L.x, L.y, L.z, hbox.x, hbox.y, hbox.z, rc * rc, rc2c, R * R};
   if (!sp_valid || std::memcmp(spv, sp_host, sizeof(spv)) != 0) {
-    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, st, (StepParams*)d_sp, lo, L, hbox, rc * rc, R * R);
+    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, st, (StepParams*)d_sp, lo, L, hbox, rc * rc, rc2c, R * R);
     HIPCHK(hipGetLastError());
     std::memcpy(sp_host, spv, sizeof(spv));
     sp_valid = true;
