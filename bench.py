@@ -9,6 +9,11 @@ near-set and sphere sums, forces and energy.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 
+For profiling the other workloads the same timed loop runs on any named
+configuration, optionally with the sphere near set and other p, K, F:
+
+  python bench.py --workload c3_hsma2d_n20000_slab [--near-rule 1 --p 14 --K 450 --F 1152]
+
 Besides the throughput it reports the dominant kernel's roofline position
 (FP32 VALU bound; algorithmic 20 flop per near pair over its HIP-event
 duration), the error against the FP64 GPU path and that path's speed, and
@@ -62,10 +67,10 @@ def cpu_baseline(w, pos, q, lo, L, sample_n=256):
     from oracle import hsma as ohsma
     rng = np.random.default_rng(11)
     t0 = time.perf_counter()
-    ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets=np.arange(1))
+    ohsma.run_workload(w, targets=np.arange(1))
     t1 = time.perf_counter()
     sample = rng.choice(w.n, sample_n, replace=False)
-    ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets=sample)
+    ohsma.run_workload(w, targets=sample)
     t2 = time.perf_counter()
     fixed = t1 - t0
     per_particle = max((t2 - t1) - fixed, 1e-9) / (sample_n - 1)
@@ -139,21 +144,6 @@ def serving_bench(hs, workloads, n_systems=256, slots=8, loads=(0.5, 0.8, 0.95),
     return out
 
 
-def sphere_near_pairs(pos, lo, L, R):
-    """Pairs summed with the sphere near set: every particle against every
-    image (of the 27 cells) strictly inside the sphere, minus the self pairs."""
-    import numpy as np
-    x = pos - (lo + 0.5 * L)
-    x -= L * np.floor(x / L + 0.5)
-    inside = 0
-    for a in (-1, 0, 1):
-        for b in (-1, 0, 1):
-            for c in (-1, 0, 1):
-                y = x + np.array([a, b, c]) * L
-                inside += int((((y[:, 0] * y[:, 0] + y[:, 1] * y[:, 1]) + y[:, 2] * y[:, 2]) < R * R).sum())
-    return len(x) * inside - len(x)
-
-
 def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells, f64_cells, steps=10):
     """The same system with the sphere near set (images inside the sphere
     only, Sec. 2.2) at parameters that reach the same 1e-5 force bar:
@@ -174,11 +164,11 @@ def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells,
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
-    R = plan.info()["radius"]
+    pairs = plan.info()["near_pairs"]
     plan.close()
     out = {"near_rule": 1, "p": ws.p, "K": ws.K, "F": ws.F, "lambda": ws.lam, "precision": "fp32-compensated",
            "ms_per_step": ms, "particle_steps_per_s": w.n / (ms * 1e-3), "speedup_vs_27_cells": ms_cells / ms,
-           "near_pairs": sphere_near_pairs(pos, lo, L, R)}
+           "near_pairs": pairs, "near_pairs_27_cells": 27 * w.n * w.n - w.n}
     if f64_cells is not None:
         fs = f.cpu().numpy()
         out["rel_rms_force_diff_vs_27_cells_fp64"] = float(np.sqrt(((fs - f64_cells) ** 2).sum() / (f64_cells ** 2).sum()))
@@ -195,6 +185,12 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix measurement")
     ap.add_argument("--no-sphere-rule", action="store_true",
                     help="skip the sphere-near-set measurement (near_rule=1 at matched accuracy)")
+    ap.add_argument("--workload", default="c2_hsma3d_n50000_fp32c",
+                    help="configuration to time (default: the 50,000-ion benchmark system)")
+    ap.add_argument("--near-rule", type=int, default=None, help="override the near set (0 cells, 1 sphere)")
+    ap.add_argument("--p", type=int, default=None, help="override the harmonic degree")
+    ap.add_argument("--K", type=int, default=None, help="override the check-point pairs")
+    ap.add_argument("--F", type=int, default=None, help="override the sphere points")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for counter runs: one 512 MiB device copy (calibration of the byte counters) "
                          "then warmup + steps of the benchmarked step, nothing else")
@@ -215,7 +211,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    w = workloads.C2
+    import dataclasses
+    w = workloads.CONFIGS[args.workload]
+    over = {k: v for k, v in (("near_rule", args.near_rule), ("p", args.p), ("K", args.K), ("F", args.F))
+            if v is not None}
+    default_run = args.workload == workloads.C2.name and not over
+    if over:
+        w = dataclasses.replace(w, **over)
+    if not default_run:
+        # a profiling run of another configuration: the timed loop only
+        args.no_fp64 = args.no_serving = args.no_sphere_rule = True
     pos, q, lo, L = workloads.make_system(w)
     dev = torch.device("cuda:0")
     x = torch.tensor(pos, device=dev)
@@ -274,8 +279,10 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "box": list(w.box), "p": w.p, "F": w.F, "K": w.K,
-                   "lambda": w.lam, "near_cells": 27, "precision": "fp32-compensated",
-                   "parallelism": "single-gpu"},
+                   "lambda": w.lam,
+                   "near_set": "images inside the sphere" if w.near_rule == 1 else
+                               ("27 cells" if w.geometry == 0 else f"9 cells x {2 * w.M + 1} layers"),
+                   "precision": "fp32-compensated", "parallelism": "single-gpu"},
         "pair_interactions_per_s": (info["near_pairs"] + info["check_pairs"] + info["surface_pairs"]) / (ms * 1e-3),
         "stage_ms": {"step": tm["step_ms"] / calls, "near": near_ms, "check": tm["check_ms"] / calls,
                      "sphere": tm["sphere_ms"] / calls},

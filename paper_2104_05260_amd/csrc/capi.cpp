@@ -249,6 +249,16 @@ hsma_status hsma_plan_get_info(const hsma_plan* plan, hsma_plan_info* info) {
   info->near_pairs = plan->dev.near_pairs;
   info->check_pairs = plan->dev.check_pairs;
   info->surface_pairs = plan->dev.sphere_pairs;
+  if (h.prm.near_rule == 1 && plan->dev.cur_n > 0) {
+    // sphere near set: the pairs actually summed, from the last step's masks
+    std::string err;
+    long long inside = 0;
+    const hsma_status st = plan->dev.sphere_sources(inside, err);
+    if (st != HSMA_OK) return fail(st, err);
+    const long long n = plan->dev.cur_n;
+    info->near_pairs = n * inside - n;
+    info->check_pairs = (long long)h.check_axis.size() * inside;
+  }
   return HSMA_OK;
 }
 

@@ -114,6 +114,9 @@ struct DevicePlan {
   double* d_unit_SQ = nullptr;
   double* d_unit_SD = nullptr;
   double* d_unit_ysurf = nullptr;
+  // sphere near set: number of source images inside the sphere in the last
+  // step (waits for that step)
+  hsma_status sphere_sources(long long& inside, std::string& err) const;
   hsma_status init_scalable(std::string& err);
   hsma_status set_box(const double lo[3], double scale, hipStream_t st, std::string& err);
 

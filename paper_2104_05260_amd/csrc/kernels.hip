@@ -1619,6 +1619,20 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
 }
 
 
+hsma_status DevicePlan::sphere_sources(long long& inside, std::string& err) const {
+  inside = 0;
+  if (!d_cull || cur_n <= 0) return HSMA_OK;
+  if (last_stream) HIPCHK(hipStreamSynchronize(last_stream));
+  else HIPCHK(hipDeviceSynchronize());
+  const size_t nd = host.desc_particles.size();
+  std::vector<unsigned long long> m(nd * (size_t)ntiles_);
+  HIPCHK(hipMemcpy(m.data(), d_cull, sizeof(unsigned long long) * m.size(), hipMemcpyDeviceToHost));
+  for (unsigned long long v : m) inside += __builtin_popcountll(v);
+  // padding slots of the last tile read as inside
+  inside -= (long long)nd * ((long long)ntiles_ * kTile - cur_n);
+  return HSMA_OK;
+}
+
 // Keeps a copy of the plan constants for the unit box so that the plan can
 // be re-targeted to any box len = s * unit_len with one kernel.
 hsma_status DevicePlan::init_scalable(std::string& err) {

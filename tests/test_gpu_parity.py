@@ -145,6 +145,25 @@ def test_sphere_near_set_slab(prec, gam):
     check(params, pos, q, lo, L, fp32=prec == 1, label=f"slab sphere near set gamma={gam}")
 
 
+def test_sphere_near_set_pair_count():
+    """Plan info reports the pairs the sphere near set actually sums: every
+    particle against every image inside the sphere, self pairs excluded
+    (counted here directly from the positions)."""
+    pos, q, lo, L = workloads.small_system(3000, (25.0, 25.0, 25.0), 8)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, near_rule=1)
+    with hs.Plan(params, lo, L) as plan:
+        plan.compute(pos, q)
+        info = plan.info()
+    x = ogeo.centre_and_wrap(pos, lo, L)
+    R = ohsma._radius(L, 1.5)
+    inside = 0
+    for k in ogeo.shifts_3d() * L:
+        y = x + k
+        inside += int((((y[:, 0] * y[:, 0] + y[:, 1] * y[:, 1]) + y[:, 2] * y[:, 2]) < R * R).sum())
+    assert info["near_pairs"] == len(q) * inside - len(q)
+    assert info["check_pairs"] == info["n_check"] * inside
+
+
 def test_deterministic_and_permutation():
     pos, q, lo, L = workloads.small_system(3000, (25.0, 25.0, 25.0), 7)
     params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5)
