@@ -76,8 +76,18 @@ def cpu_baseline(w, pos, q, lo, L, sample_n=256):
     per_particle = max((t2 - t1) - fixed, 1e-9) / (sample_n - 1)
     est_step = fixed + per_particle * w.n
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": w.n / est_step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+        "cpu_model": model, "nproc": os.cpu_count(),
         "sample": (f"FP64 oracle: fixed part (all check sums + fit + sphere sources) {fixed:.2f} s measured, "
                    f"particle sums at {sample_n} sampled particles measured and scaled to all {w.n}; "
                    f"estimated {est_step:.1f} s per step"),
@@ -249,16 +259,20 @@ def main():
         raise SystemExit("device-side validation failed")
     plan.set_timing(True)
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event between consecutive steps (no synchronisation inside the
+    # timed region): mean, median and p90 of the per-step device times
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         plan.compute_device(x, qq, en, pot, f)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall1 = time.perf_counter()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     tm = plan.timing()
     info = plan.info()
     plan.set_timing(False)
@@ -275,6 +289,8 @@ def main():
         "unit": "particle-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": float(np.median(per_step)),
+        "ms_per_step_p90": float(np.percentile(per_step, 90)),
         "wall_ms_per_step": (wall1 - wall0) * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -284,6 +300,8 @@ def main():
                                ("27 cells" if w.geometry == 0 else f"9 cells x {2 * w.M + 1} layers"),
                    "precision": "fp32-compensated", "parallelism": "single-gpu"},
         "pair_interactions_per_s": (info["near_pairs"] + info["check_pairs"] + info["surface_pairs"]) / (ms * 1e-3),
+        "pairs_per_step": {"near_set": info["near_pairs"], "check_points": info["check_pairs"],
+                           "sphere_sources": info["surface_pairs"]},
         "stage_ms": {"step": tm["step_ms"] / calls, "near": near_ms, "check": tm["check_ms"] / calls,
                      "sphere": tm["sphere_ms"] / calls},
         "roofline": {

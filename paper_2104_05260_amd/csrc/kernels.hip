@@ -340,6 +340,8 @@ __global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ ord
 // in one block.  The sort is a bitonic network in LDS over unique 64-bit
 // (key, input index) words, so its order equals the stable radix sort's.
 constexpr int kSmallSort = 4096;
+// largest system whose check chain overlaps its particle sums (side stream)
+constexpr int kOverlapMaxN = 32768;
 constexpr int kSmallThreads = 1024;
 
 __global__ __launch_bounds__(kSmallThreads) void k_small_prep(int n, int nblk, const double* __restrict__ red,
@@ -1171,6 +1173,10 @@ static hsma_status upload(T** dst, const std::vector<T>& v, std::string& err) {
 
 hsma_status DevicePlan::init(std::string& err) {
   HIPCHK(hipGetDevice(&device));
+  // side stream of the step (default priority) and its fork/join events
+  HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
   hsma_status st;
   if ((st = upload(&d_desc_part, host.desc_particles, err)) != HSMA_OK) return st;
   if ((st = upload(&d_desc_check, host.desc_check, err)) != HSMA_OK) return st;
@@ -1245,6 +1251,9 @@ DevicePlan::~DevicePlan() {
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (own_stream) (void)hipStreamDestroy(own_stream);
+  if (side) (void)hipStreamDestroy(side);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
 }
 
 // Particle schedule for n particles: chunks sized so that a launch has
@@ -1427,6 +1436,7 @@ hsma_status DevicePlan::record(hipStream_t st, int stage, int edge, std::string&
 hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz, const double* d_q,
                                      double* d_energy, double* d_pot, double* d_force, std::string& err) {
   hsma_status s = HSMA_OK;
+  const hipStream_t stream_arg = st;
   const bool fp64 = host.prm.precision == HSMA_FP64;
   const int slab = host.prm.geometry == HSMA_GEOM_2D;
   const int nblk = (n + 255) / 256;
@@ -1490,7 +1500,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     hipLaunchKernelGGL(k_reduce_check<RealC>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,     \
                        (const CheckSched*)d_csched, (const int*)d_check_axis, (const RealC*)d_cpart, d_v);         \
   } while (0)
-#define HSMA_PARTICLES(Real, S, SRC)                                                                                \
+#define HSMA_PARTICLES_NEAR(Real, S, SRC)                                                                           \
   do {                                                                                                              \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
@@ -1504,6 +1514,9 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
                        (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
                        slot);                                                                                       \
+  } while (0)
+#define HSMA_PARTICLES_SPHERE(Real)                                                                                 \
+  do {                                                                                                              \
     if ((s = record(st, kStSphere, 0, err)) != HSMA_OK) return s;                                                   \
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
                        (const double4*)d_surf64, F, sph_chunk_, (Real*)d_part, comp, nchunks_ + psched_.nnear);     \
@@ -1513,17 +1526,40 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                        (const Desc*)d_desc_part, (int)host.desc_particles.size(), cullp, ntiles_,                   \
                        host.prm.coulomb_k, (const int*)d_status, d_pot, d_force, d_epart);                          \
   } while (0)
-  if (fp64 || host.prm.near_rule == 1) HSMA_CHECKS(double, double4, d_src64);
-  else HSMA_CHECKS(float, float4, d_src32);
-  hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw, (const double*)d_v,
-                     d_A);
-  hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
-                     (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf, d_surf32,
-                     d_surf64, d_qd);
-  if (fp64) HSMA_PARTICLES(double, double4, d_src64);
-  else HSMA_PARTICLES(float, float4, d_src32);
+  // The check sums, the fit and the sphere sources depend only on the
+  // tiles, as do the near-set sums at the particles.  For systems up to
+  // kOverlapMaxN particles the first chain runs on a side stream, forked
+  // from and joined back into the call's stream (event edges, so a captured
+  // step graph holds both branches), while the particle sums run on the
+  // call's stream: the chain's small, latency-bound kernels then overlap
+  // the particle sums.  Larger systems fill the GPU with the particle sums
+  // alone; there the chain runs first on the call's stream.
+  const bool overlap = n <= kOverlapMaxN;
+  {
+    if (overlap) {
+      HIPCHK(hipEventRecord(ev_fork, st));
+      HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+    }
+    {
+      const hipStream_t st = overlap ? side : stream_arg;  // where the check chain's launches go
+      if (fp64 || host.prm.near_rule == 1) HSMA_CHECKS(double, double4, d_src64);
+      else HSMA_CHECKS(float, float4, d_src32);
+      hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw,
+                         (const double*)d_v, d_A);
+      hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
+                         (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,
+                         d_surf32, d_surf64, d_qd);
+      if (overlap) HIPCHK(hipEventRecord(ev_join, st));
+    }
+  }
+  if (fp64) HSMA_PARTICLES_NEAR(double, double4, d_src64);
+  else HSMA_PARTICLES_NEAR(float, float4, d_src32);
+  if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+  if (fp64) HSMA_PARTICLES_SPHERE(double);
+  else HSMA_PARTICLES_SPHERE(float);
 #undef HSMA_CHECKS
-#undef HSMA_PARTICLES
+#undef HSMA_PARTICLES_NEAR
+#undef HSMA_PARTICLES_SPHERE
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nblk, (const double*)d_epart,
                      d_energy ? d_energy : d_energy_scratch);
   HIPCHK(hipGetLastError());

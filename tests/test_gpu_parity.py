@@ -331,15 +331,17 @@ def test_c5_million_ions_sampled():
     assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())
 
 
-def test_step_graph_replays_match_eager():
+@pytest.mark.parametrize("near_rule", [0, 1])
+def test_step_graph_replays_match_eager(near_rule):
     """A plan in graph mode captures the step on the second identical call
     and replays it; every replay (new positions each time, eager work and
-    synchronisations in between) equals the eager result bitwise."""
+    synchronisations in between) equals the eager result bitwise.  With the
+    sphere near set the graph also holds the mask and list kernels."""
     import torch
     dev = torch.device("cuda:0")
     pos0, q, lo, L = workloads.small_system(2000, (20.0, 20.0, 20.0), 31)
     rng = np.random.default_rng(4)
-    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, near_rule=near_rule)
     stream = torch.cuda.Stream()
     with hs.Plan(params, lo, L) as eager, hs.Plan(params, lo, L) as graphed:
         graphed.set_graph(True)

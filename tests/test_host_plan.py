@@ -56,6 +56,7 @@ def test_no_device_is_reported():
     (dict(surface_rule=1, F=300), "HSMA_ERR_INVALID_ARG"),
     (dict(geometry=1, gamma_up=1.0), "HSMA_ERR_INVALID_ARG"),
     (dict(geometry=7), "HSMA_ERR_INVALID_ARG"),
+    (dict(near_rule=2), "HSMA_ERR_INVALID_ARG"),
 ])
 def test_plan_parameter_errors(bad, err):
     lib_or_skip()
