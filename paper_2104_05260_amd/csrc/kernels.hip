@@ -461,6 +461,12 @@ struct CullView {
 // vector of any pair closer than rc from the FP64 positions and drops the
 // self pair.  Both kernels classify tiles with the same FP64 arithmetic, so
 // every pair is summed exactly once.
+//
+// Sphere near set: the wave walks its share of the compacted list of
+// (image entry, tile) pairs that hold at least one source inside the
+// sphere, and the sources of a tile the sphere cuts enter with zero charge
+// (bit k of the tile's mask), so the loop is the same as for the stencil.
+//
 // Tile classification shared by the far and near kernels.  Explicitly
 // rounded operations (no FMA contraction) so that both kernels reach the
 // same decision for every (group, image, tile) and each pair is summed once.
@@ -622,10 +628,17 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       }
     } else if constexpr (!NEAR) {
       // the plain loop; a tile cut by the sphere runs the same loop with
-      // the charges of the sources outside it set to zero
+      // the charges of the sources outside it set to zero, over the
+      // blocks of HSMA_FAR_UNROLL sources between its first and last
+      // source inside (m != 0 here: empty tiles never reach this point)
       auto far_loop = [&](auto masked) {
+        int k0 = 0, k1 = kTile;
+        if constexpr (decltype(masked)::value) {
+          k0 = __builtin_ctzll(m) / HSMA_FAR_UNROLL * HSMA_FAR_UNROLL;
+          k1 = (kTile - __builtin_clzll(m) + HSMA_FAR_UNROLL - 1) / HSMA_FAR_UNROLL * HSMA_FAR_UNROLL;
+        }
 #pragma unroll HSMA_FAR_UNROLL
-        for (int k = 0; k < kTile; ++k) {
+        for (int k = k0; k < k1; ++k) {
           const S v = s[k];
           Real qv = (Real)v.w;
           if constexpr (decltype(masked)::value) qv = ((m >> k) & 1ull) ? qv : (Real)0;

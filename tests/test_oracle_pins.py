@@ -316,6 +316,27 @@ def test_hsma3d_scaling_permutation_and_lsq_optimality():
     assert abs(rt.energy - r.energy) < 1e-4 * abs(r.energy)
 
 
+def test_hsma3d_force_is_minus_energy_gradient():
+    """Finite differences of the HSMA energy against the reported forces
+    F_i = q_i E_i, within the method error (the fit is redone at every
+    displaced configuration, so agreement is at the method-error level, not
+    to rounding)."""
+    pos, q, lo, L = workloads.make_system(workloads.C1)
+    p, K, F = 8, 162, 512
+    r = hsma.hsma3d(pos, q, lo, L, p, K, F, 1.5)
+    scale = np.abs(r.force).max()
+    h = 1e-4
+    for i in (3, 41, 77):
+        for k in range(3):
+            pp = pos.copy()
+            pp[i, k] += h
+            ep = hsma.hsma3d(pp, q, lo, L, p, K, F, 1.5).energy
+            pp[i, k] -= 2 * h
+            em = hsma.hsma3d(pp, q, lo, L, p, K, F, 1.5).energy
+            fd = -(ep - em) / (2 * h)
+            assert abs(fd - r.force[i, k]) < 1e-5 * scale, (i, k, fd, r.force[i, k])  # measured 1.1e-6
+
+
 def test_hsma3d_rejects_bad_input():
     pos, q, lo, L = workloads.small_system(10, (5.0, 5.0, 5.0), 1)
     with pytest.raises(hsma.OracleInputError):
@@ -413,6 +434,19 @@ def test_hsma2d_mirror_symmetry():
     Fm = rm.force.copy()
     Fm[:, 2] *= -1
     assert np.abs(Fm - r.force).max() < 1e-3 * np.abs(r.force).max()
+
+
+def test_hsma2d_in_plane_translation():
+    """Shifting every ion in x and y (the slab is periodic there) leaves the
+    energy unchanged and moves the forces with the ions, within the method
+    error."""
+    pos, q, lo, L = workloads.small_system(10, (20.0, 20.0, 10.0), 9, geometry=1)
+    args = (6, 100, 200, 1.6, 6, -0.5, -0.5, 40)
+    r = hsma.hsma2d(pos, q, lo, L, *args, surface_rule=1)
+    shifted = pos + np.array([7.3, -12.1, 0.0])
+    rs = hsma.hsma2d(shifted, q, lo, L, *args, surface_rule=1)
+    assert abs(rs.energy - r.energy) < 1e-3 * abs(r.energy)
+    assert np.abs(rs.force - r.force).max() < 1e-3 * np.abs(r.force).max()
 
 
 def test_hsma2d_rejects_particle_outside_slab():
