@@ -80,7 +80,7 @@ struct DevicePlan {
   int* d_ccount = nullptr;
   hipEvent_t stage_ev = nullptr;
   PartSched psched_{};
-  int ntiles_ = 0, ngroups_ = 0, ncwork_ = 0, nchunks_ = 0, nsphere_ = 0, sph_chunk_ = 0,
+  int ntiles_ = 0, ngroups_ = 0, ncwork_ = 0, cwork_face_ = 0, nchunks_ = 0, nsphere_ = 0, sph_chunk_ = 0,
       nrsblk_ = 0;
 
   // host-call staging
@@ -137,6 +137,12 @@ struct DevicePlan {
   // Allocates the per-size arena for any particle count up to nmax.
   hsma_status reserve(int64_t nmax, std::string& err);
   void capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_bytes, size_t& nwork, size_t& ncwork) const;
+  // element size of the check-partial buffer: 8 bytes when any check sum
+  // runs in FP64 (FP64 path; face rows of the sphere near set), else 4.
+  // Reservation, the capacity check and the launches' slot stride all use it.
+  size_t cpart_elem() const {
+    return (host.prm.precision == HSMA_FP64 || host.prm.near_rule == 1) ? sizeof(double) : sizeof(float);
+  }
   hsma_status prepare(int64_t n, hipStream_t st, std::string& err);
   hsma_status run(hipStream_t st, int64_t n, const double* d_xyz, const double* d_q, double* d_energy,
                   double* d_pot, double* d_force, std::string& err);

@@ -75,6 +75,7 @@ struct HostPlan {
   std::vector<double> check_pos;    // ncheck * 3
   std::vector<int> check_axis;      // field component reported per target
   std::vector<Group> check_groups;
+  int face_groups = 0;              // check groups [0, face_groups) hold face-pair targets
 
   // A = Praw * v,  v[2t] = value at check target t, v[2t+1] = field
   // component check_axis[t] at t.  Row-major nb x (2*ncheck).

@@ -99,7 +99,7 @@ uint32_t hilbert_key_host(uint32_t x, uint32_t y, uint32_t z) { return hilbert_k
 struct StepParams {
   double3 lo, L, hbox;
   double rc2;   // close-pair radius^2 of the particle sums
-  double rc2c;  // the same for the check sums (< 0: every tile goes through the far kernel)
+  double rc2c;  // the same for the FP32 check sums
   double R2;    // squared sphere radius (sphere near set)
 };
 
@@ -494,7 +494,8 @@ __device__ __forceinline__ double gap2_of(double dlx, double dly, double dlz, do
 
 template <typename Real, bool NEAR, bool PARTICLES>
 __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ cgroups,
-                                             const CheckSched* __restrict__ csched, int ncg, PartSched ps,
+                                             const CheckSched* __restrict__ csched, int ncg, int cbase,
+                                             PartSched ps,
                                              const Desc* __restrict__ desc,
                                              int ntiles, const double4* __restrict__ tile_c,
                                              const float4* __restrict__ tile_h,
@@ -527,15 +528,18 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     }
     g = Group{gi * kGroup, min(kGroup, ps.n - gi * kGroup), 0, ps.ndesc};
   } else {
+    // checks: cbase offsets the launch index (a launch may cover a subset
+    // of the groups: its far waves, or its groups for the near pass)
+    const int bid = (int)blockIdx.x + cbase;
     int gi;
     if constexpr (NEAR) {
-      gi = blockIdx.x;
+      gi = bid;
     } else {
       // the check group whose far waves include this one (binary search)
       int lo = 0, hi = ncg - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (csched[mid].first_work <= (int)blockIdx.x) lo = mid;
+        if (csched[mid].first_work <= bid) lo = mid;
         else hi = mid - 1;
       }
       gi = lo;
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     if constexpr (NEAR) {
       w = Work{gi, 0, F, cs.slot0 + cs.nch};
     } else {
-      const int c = blockIdx.x - cs.first_work;
+      const int c = bid - cs.first_work;
       const int f0 = c * cs.chunk;
       w = Work{gi, f0, min(F, f0 + cs.chunk), cs.slot0 + c};
       part_i = c;
@@ -554,7 +558,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     }
   }
   const double3 hbox = sp->hbox;
-  const double rc2 = PARTICLES ? sp->rc2 : sp->rc2c;
+  // FP64 check sums need neither close-pair corrections nor self exclusion:
+  // every tile goes through the far kernel (a face check group spans a whole
+  // face, so its box overlaps many tiles)
+  const double rc2 = PARTICLES ? sp->rc2 : (sizeof(Real) == 8 ? -1.0 : sp->rc2c);
   const int lane = threadIdx.x;
   bool valid[kTPL];
   Real ox[kTPL], oy[kTPL], oz[kTPL];
@@ -935,11 +942,12 @@ __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ 
 // combined at the end (error-free for the FP32 potential).
 template <typename Real>
 __global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __restrict__ groups,
-                                                      const CheckSched* __restrict__ csched, const int* __restrict__ axis,
-                                                      const Real* __restrict__ part, double* __restrict__ v) {
+                                                      const CheckSched* __restrict__ csched, int gbase,
+                                                      const int* __restrict__ axis, const Real* __restrict__ part,
+                                                      long slot_elems, double* __restrict__ v) {
   __shared__ double sh_phi[kGroup], sh_e[kGroup];
-  const Group g = groups[blockIdx.x];
-  const CheckSched cs = csched[blockIdx.x];
+  const Group g = groups[blockIdx.x + gbase];
+  const CheckSched cs = csched[blockIdx.x + gbase];
   const int2 sr = make_int2(cs.slot0, cs.nch + 1);
   const int local = threadIdx.x % kGroup, half = threadIdx.x / kGroup;
   const bool ok = local < g.count;
@@ -949,7 +957,7 @@ __global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __rest
   if constexpr (sizeof(Real) == 4) {
     float hi = 0, lo = 0, ea = 0, ec = 0;
     for (int w = sr.x + half; w < sr.x + sr.y; w += 2) {
-      const Real* p = part + (long)w * 5 * kGroup + local;
+      const Real* p = part + (long)w * slot_elems + local;
       float sm, er;
       two_sum(hi, p[0], sm, er);
       hi = sm;
@@ -962,7 +970,7 @@ __global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __rest
     e = (double)ea + (double)ec;
   } else {
     for (int w = sr.x + half; w < sr.x + sr.y; w += 2) {
-      const Real* p = part + (long)w * 5 * kGroup + local;
+      const Real* p = part + (long)w * slot_elems + local;
       phi += p[0];
       e += p[(2 + ax) * kGroup];
     }
@@ -1324,7 +1332,7 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
   const size_t sph = 1024 + (size_t)ngroups * ((size_t)host.prm.F / kSphereChunkMax + 2);
   const size_t ncg = host.check_groups.size();
   part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + (2 + kMaxNearSplit) * (size_t)ngroups + sph);
-  const size_t rbc = host.prm.near_rule == 1 ? sizeof(double) : rb;  // check sums' precision
+  const size_t rbc = cpart_elem();
   cpart_bytes = rbc * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
   nwork = (size_t)part_target + (2 + kMaxNearSplit) * (size_t)ngroups + 2;
   ncwork = (size_t)check_target_max + 2 * ncg + 2;
@@ -1405,7 +1413,7 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   const int nsc = (host.prm.F + sch - 1) / sch;
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
   const long comp = (long)ps.ngroups * kGroup;
-  const size_t rbc = host.prm.near_rule == 1 ? sizeof(double) : rb;
+  const size_t rbc = cpart_elem();
   if (rb * 5 * (size_t)comp * (ps.nch + ps.nnear + nsc) > part_cap || rbc * 5 * (size_t)kGroup * ncslots > cpart_cap ||
       (size_t)(ps.nch + ps.nnear) * ps.ngroups > work_cap || (size_t)ncfar + cs.size() > cwork_cap) {
     err = "internal error: work decomposition exceeds the reserved arena";
@@ -1424,6 +1432,7 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   ngroups_ = ps.ngroups;
   psched_ = ps;
   ncwork_ = ncfar;
+  cwork_face_ = host.face_groups < (int)cs.size() ? cs[host.face_groups].first_work : ncfar;
   nchunks_ = ps.nch;
   nsphere_ = nsc;
   sph_chunk_ = sch;
@@ -1488,7 +1497,8 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   }
   const int ncheck = (int)host.check_axis.size();
   const int ncg = (int)host.check_groups.size();
-  const long ccomp = kGroup, cslot = 5L * kGroup;
+  const long ccomp = kGroup;
+  const size_t cpart_elem = this->cpart_elem();  // the buffer's element size, as reserved
   const long comp = (long)ngroups_ * kGroup;
   const long slot = 5L * comp;
   const int F = host.prm.F;
@@ -1496,34 +1506,42 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   // whose face rows are differences Phi_B(x+) - Phi_B(x-) of two full sums
   // (a source near x- has its periodic copy near x+; the two large terms
   // cancel exactly, their FP32 rounding would not)
-#define HSMA_CHECKS(RealC, SC, SRCC)                                                                                \
+// check sums of the groups [G0, G1) whose far waves are [W0, W1).  A partial
+// slot is 5 x kGroup elements of the buffer's element type (cpart_elem
+// bytes: 8 when any check sum is FP64, else 4); a float launch into an
+// 8-byte buffer uses the first half of each slot, so both precisions can
+// share it
+#define HSMA_CHECKS(RealC, SC, SRCC, W0, W1, G0, G1)                                                                \
   do {                                                                                                              \
-    if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;                                                    \
-    hipLaunchKernelGGL((k_pair<RealC, false, false>), dim3(ncwork_), dim3(64), 0, st, (const double4*)d_check_pos,  \
-                       (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
-                       (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
-                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (RealC*)d_cpart,   \
-                       ccomp, cslot);                                                                               \
-    hipLaunchKernelGGL((k_pair<RealC, true, false>), dim3(ncg), dim3(64), 0, st, (const double4*)d_check_pos,       \
-                       (const Group*)d_check_groups, (const CheckSched*)d_csched, ncg, psched_,                     \
-                       (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,       \
-                       (const SC*)SRCC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (RealC*)d_cpart,   \
-                       ccomp, cslot);                                                                               \
-    if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;                                                    \
-    hipLaunchKernelGGL(k_reduce_check<RealC>, dim3(ncg), dim3(2 * kGroup), 0, st, (const Group*)d_check_groups,     \
-                       (const CheckSched*)d_csched, (const int*)d_check_axis, (const RealC*)d_cpart, d_v);         \
+    const long cslot_e = 5L * kGroup * (long)(cpart_elem / sizeof(RealC));                                          \
+    if ((W1) > (W0))                                                                                                \
+      hipLaunchKernelGGL((k_pair<RealC, false, false>), dim3((W1) - (W0)), dim3(64), 0, st,                         \
+                         (const double4*)d_check_pos, (const Group*)d_check_groups, (const CheckSched*)d_csched,    \
+                         ncg, (W0), psched_, (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c,         \
+                         (const float4*)d_tile_h, (const SC*)SRCC, (const double4*)d_pos64,                         \
+                         (const StepParams*)d_sp, cv, (RealC*)d_cpart, ccomp, cslot_e);                             \
+    if ((G1) > (G0)) {                                                                                              \
+      hipLaunchKernelGGL((k_pair<RealC, true, false>), dim3((G1) - (G0)), dim3(64), 0, st,                          \
+                         (const double4*)d_check_pos, (const Group*)d_check_groups, (const CheckSched*)d_csched,    \
+                         ncg, (G0), psched_, (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c,         \
+                         (const float4*)d_tile_h, (const SC*)SRCC, (const double4*)d_pos64,                         \
+                         (const StepParams*)d_sp, cv, (RealC*)d_cpart, ccomp, cslot_e);                             \
+      hipLaunchKernelGGL(k_reduce_check<RealC>, dim3((G1) - (G0)), dim3(2 * kGroup), 0, st,                         \
+                         (const Group*)d_check_groups, (const CheckSched*)d_csched, (G0), (const int*)d_check_axis, \
+                         (const RealC*)d_cpart, cslot_e, d_v);                                                      \
+    }                                                                                                               \
   } while (0)
 #define HSMA_PARTICLES_NEAR(Real, S, SRC)                                                                           \
   do {                                                                                                              \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
-                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
+                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,      \
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
                        (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
                        slot);                                                                                       \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, st,          \
-                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, psched_,      \
+                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,      \
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
                        (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
                        slot);                                                                                       \
@@ -1555,8 +1573,19 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     }
     {
       const hipStream_t st = overlap ? side : stream_arg;  // where the check chain's launches go
-      if (fp64 || host.prm.near_rule == 1) HSMA_CHECKS(double, double4, d_src64);
-      else HSMA_CHECKS(float, float4, d_src32);
+      if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;
+      if (fp64) {
+        HSMA_CHECKS(double, double4, d_src64, 0, ncwork_, 0, ncg);
+      } else if (host.prm.near_rule == 1) {
+        // sphere near set: the face rows (differences of two full sums) in
+        // FP64, the slab's interface rows (single sums) in FP32
+        const int gf = host.face_groups;
+        HSMA_CHECKS(double, double4, d_src64, 0, cwork_face_, 0, gf);
+        HSMA_CHECKS(float, float4, d_src32, cwork_face_, ncwork_, gf, ncg);
+      } else {
+        HSMA_CHECKS(float, float4, d_src32, 0, ncwork_, 0, ncg);
+      }
+      if ((s = record(st, kStCheck, 1, err)) != HSMA_OK) return s;
       hipLaunchKernelGGL(k_lsq, dim3(host.nb), dim3(256), 0, st, 2 * ncheck, (const double*)d_Praw,
                          (const double*)d_v, d_A);
       hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
@@ -1608,11 +1637,7 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   // sphere radius of the current box, R = lambda |L| / 2 with the diagonal
   // summed left to right (the sphere near set is decided on exactly this R)
   const double R = host.prm.lambda * 0.5 * std::sqrt(host.L[0] * host.L[0] + host.L[1] * host.L[1] + host.L[2] * host.L[2]);
-  // FP64 check sums need neither close-pair corrections nor self exclusion:
-  // all their tiles go through the far kernel (a face check group spans a
-  // whole face, so its box overlaps many tiles)
-  const bool fp64_checks = fp64 || host.prm.near_rule == 1;
-  const double rc2c = fp64_checks ? -1.0 : rc * rc;
+  const double rc2c = rc * rc;
   const double spv[12] = {lo.x, lo.y, lo.z, L.x, L.y, L.z, hbox.x, hbox.y, hbox.z, rc * rc, rc2c, R * R};
   if (!sp_valid || std::memcmp(spv, sp_host, sizeof(spv)) != 0) {
     hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, st, (StepParams*)d_sp, lo, L, hbox, rc * rc, rc2c, R * R);

@@ -582,6 +582,7 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     P.Praw.assign(size_t(nb) * 2 * ncheck, 0.0);
     int tcount = 0;
     face_targets(Pinv, ncheck, tcount);
+    P.face_groups = (int)P.check_groups.size();
     for (int s = 0; s < 2; ++s) {
       const double gam = s == 0 ? prm.gamma_up : prm.gamma_low;
       const double sgn = s == 0 ? 1.0 : -1.0;
@@ -630,6 +631,7 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     P.Praw.assign(size_t(nb) * 2 * ncheck, 0.0);
     int tcount = 0;
     face_targets(Pinv, ncheck, tcount);
+    P.face_groups = (int)P.check_groups.size();
   }
 
   // ---- sphere quadrature and the maps A -> (Q, D)
