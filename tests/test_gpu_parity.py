@@ -311,6 +311,25 @@ def test_c3_slab_full_size_sampled():
     assert np.abs(f64[:, :2].sum(0)).max() <= 1e-3 * np.sqrt((f64 ** 2).sum())
 
 
+def test_c3_sphere_near_set_sampled():
+    """The 20,000-ion slab with the sphere near set at p = 14: FP64 face rows
+    and FP32 interface rows in one partial buffer (65,536 check slots),
+    both precisions against the oracle at 128 sampled ions."""
+    import dataclasses
+    w = dataclasses.replace(workloads.C3, near_rule=1, p=14, K=450, F=1152)
+    pos, q, lo, L = workloads.make_system(w)
+    sample = np.random.default_rng(8).choice(w.n, 128, replace=False)
+    note("[parity] C3 sphere near set: oracle (sampled)")
+    r = _sampled_oracle(w, hs.Params.from_workload(w), pos, q, lo, L, sample)
+    for prec in (1, 0):
+        note(f"[parity] C3 sphere near set gpu precision={prec}")
+        e, pot, f = run_gpu(hs.Params.from_workload(w, precision=prec), pos, q, lo, L)
+        dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
+        df = rel_rms(f[sample], r.force)
+        note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}")
+        assert (dp < 1e-10 and df < 1e-10) if prec == 0 else (dp < 1e-5 and df < 1e-5)
+
+
 def test_c5_million_ions_sampled():
     """999,999 ions (2:1 valence) in L = 200, p = 12, F = 1152, K = 800:
     the FP32 compensated path against the oracle at 128 sampled particles
