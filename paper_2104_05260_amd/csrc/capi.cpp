@@ -25,36 +25,6 @@ hsma_status fail(hsma_status s, const std::string& msg) {
 namespace hsma {
 hsma_status set_last_error(hsma_status s, const std::string& msg) { return fail(s, msg); }
 
-hsma_status validate_host_input(const hsma_params& prm, const double lo[3], const double L[3], int64_t n,
-                                const double* xyz, const double* q, std::string& msg) {
-  double sq = 0, sa = 0;
-  const bool slab = prm.geometry == HSMA_GEOM_2D;
-  for (int64_t i = 0; i < n; ++i) {
-    for (int c = 0; c < 3; ++c)
-      if (!std::isfinite(xyz[3 * i + c])) {
-        msg = "non-finite coordinate";
-        return HSMA_ERR_OUT_OF_DOMAIN;
-      }
-    if (!std::isfinite(q[i])) {
-      msg = "non-finite charge";
-      return HSMA_ERR_OUT_OF_DOMAIN;
-    }
-    if (slab) {
-      const double z = xyz[3 * i + 2] - lo[2];
-      if (!(z > 0.0 && z < L[2])) {
-        msg = "particle outside the slab";
-        return HSMA_ERR_OUT_OF_DOMAIN;
-      }
-    }
-    sq += q[i];
-    sa += std::fabs(q[i]);
-  }
-  if (!(std::fabs(sq) <= 1e-12 * sa)) {
-    msg = "system is not charge neutral";
-    return HSMA_ERR_NOT_NEUTRAL;
-  }
-  return HSMA_OK;
-}
 }  // namespace hsma
 
 namespace {

@@ -657,4 +657,38 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
   return HSMA_OK;
 }
 
+// Host-side input validation of the host-memory calls: finite coordinates
+// and charges, every ion strictly between the slab's interfaces, charge
+// neutrality (the constant mode A_0^0 is undetermined otherwise).
+hsma_status validate_host_input(const hsma_params& prm, const double lo[3], const double L[3], int64_t n,
+                                const double* xyz, const double* q, std::string& msg) {
+  double sq = 0, sa = 0;
+  const bool slab = prm.geometry == HSMA_GEOM_2D;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(xyz[3 * i + c])) {
+        msg = "non-finite coordinate";
+        return HSMA_ERR_OUT_OF_DOMAIN;
+      }
+    if (!std::isfinite(q[i])) {
+      msg = "non-finite charge";
+      return HSMA_ERR_OUT_OF_DOMAIN;
+    }
+    if (slab) {
+      const double z = xyz[3 * i + 2] - lo[2];
+      if (!(z > 0.0 && z < L[2])) {
+        msg = "particle outside the slab";
+        return HSMA_ERR_OUT_OF_DOMAIN;
+      }
+    }
+    sq += q[i];
+    sa += std::fabs(q[i]);
+  }
+  if (!(std::fabs(sq) <= 1e-12 * sa)) {
+    msg = "system is not charge neutral";
+    return HSMA_ERR_NOT_NEUTRAL;
+  }
+  return HSMA_OK;
+}
+
 }  // namespace hsma

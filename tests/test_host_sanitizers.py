@@ -1,0 +1,36 @@
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU).
+
+The library's host FP64 plan (plan.cpp: check points, image tables,
+pseudo-inverse, sphere maps, input validation) is compiled with g++ and the
+sanitizers together with a driver that builds plans for both geometries,
+both near sets and both surface rules, feeds invalid parameters and inputs,
+and checks the plans' structural invariants.  Device code is not involved
+(GPU sanitizers are not available for it here)."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_host_plan_under_asan_ubsan():
+    tmp = tempfile.mkdtemp(prefix="hsma_san_")
+    try:
+        exe = os.path.join(tmp, "host_plan_check")
+        cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+               "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               os.path.join(ROOT, "tests", "native", "host_plan_check.cpp"),
+               os.path.join(ROOT, "paper_2104_05260_amd", "csrc", "plan.cpp"), "-o", exe]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr[-3000:]
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+                   UBSAN_OPTIONS="print_stacktrace=1")
+        run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+        assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
+        assert "host plan checks passed" in run.stdout
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
