@@ -185,6 +185,49 @@ def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells,
     return out
 
 
+def slab_near_sets_bench(hs, workloads, steps=5):
+    """The 20,000-ion slab with both near sets: the 189-entry stencil at the
+    workload's p = 10 and the sphere near set at p = 14 (K = 450, F = 1152),
+    FP32 compensated, timed on the current stream; the sphere result's RMS
+    force difference from the stencil's FP64 result."""
+    import dataclasses
+    import numpy as np
+    import torch
+    w = workloads.C3
+    pos, q, lo, L = workloads.make_system(w)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(pos, device=dev)
+    qq = torch.tensor(q, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    pot = torch.zeros(w.n, dtype=torch.float64, device=dev)
+    f = torch.zeros((w.n, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(ww, prec, k):
+        plan = hs.Plan(hs.Params.from_workload(ww, precision=prec), lo, L)
+        plan.compute_device(x, qq, en, pot, f)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(k):
+            plan.compute_device(x, qq, en, pot, f)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pairs = plan.info()["near_pairs"]
+        plan.close()
+        return ev0.elapsed_time(ev1) / k, f.cpu().numpy(), pairs
+
+    ws = dataclasses.replace(w, p=14, K=450, F=1152, near_rule=1)
+    ms_cells, _, pairs_cells = timed(w, hs.FP32C, steps)
+    _, f64_cells, _ = timed(w, hs.FP64, 1)
+    ms_sphere, f_sphere, pairs_sphere = timed(ws, hs.FP32C, steps)
+    return {"workload": w.name, "stencil_ms_per_step": ms_cells, "sphere_ms_per_step": ms_sphere,
+            "speedup": ms_cells / ms_sphere, "stencil_near_pairs": pairs_cells, "sphere_near_pairs": pairs_sphere,
+            "sphere_p": ws.p, "sphere_K": ws.K, "sphere_F": ws.F,
+            "rel_rms_force_diff_vs_stencil_fp64": float(np.sqrt(((f_sphere - f64_cells) ** 2).sum()
+                                                                / (f64_cells ** 2).sum()))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,8 +249,8 @@ def main():
                          "then warmup + steps of the benchmarked step, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method would shard by target ranges; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the method would shard by target ranges). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: one process per run; WORLD_SIZE > 1 is not supported", file=sys.stderr)
@@ -336,6 +379,7 @@ def main():
     if not args.no_sphere_rule:
         out["sphere_near_set"] = sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
                                                    None if args.no_fp64 else f64)
+        out["sphere_near_set_slab"] = slab_near_sets_bench(hs, workloads)
     if not args.no_serving:
         out["serving"] = serving_bench(hs, workloads)
     if not args.no_cpu_baseline:
