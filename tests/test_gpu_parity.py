@@ -105,6 +105,33 @@ def test_ragged_sizes_3d(n, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_boundary_and_wrapped_positions(prec):
+    """Ions exactly on box faces, edges and corners, and ions given one or
+    two box lengths outside the box (wrapped into it by both sides)."""
+    L = np.array([9.0, 10.0, 11.0])
+    lo = np.array([-2.0, 1.0, 0.5])
+    pos, q, _, _ = workloads.small_system(200, tuple(L), 17)
+    pos = pos + lo
+    rng = np.random.default_rng(3)
+    for i in range(0, 24):           # faces (one coordinate) and edges (two)
+        for k in rng.choice(3, 1 + i % 2, replace=False):
+            pos[i, k] = lo[k] + (L[k] if rng.random() < 0.5 else 0.0)
+    pos[24] = lo + L                 # one corner (all corners are one point)
+    for i in range(25, 48):          # one or two periods outside
+        pos[i] += rng.integers(-2, 3, 3) * L
+    params = hs.Params(precision=prec, p=6, K=100, F=200, lam=1.4)
+    check(params, pos, q, lo, L, fp32=prec == 1, label="boundary and wrapped positions")
+
+
+def test_single_neutral_particle():
+    """n = 1 with zero charge: neutral, every output zero."""
+    L = np.array([5.0, 5.0, 5.0])
+    with hs.Plan(hs.Params(precision=0, p=4, K=60, F=200, lam=1.5), [0, 0, 0], L) as plan:
+        e, pot, f = plan.compute(np.array([[1.0, 2.0, 3.0]]), np.array([0.0]))
+    assert e == 0.0 and np.all(pot == 0.0) and np.all(f == 0.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("gam", [(0.0, 0.0), (-0.94, -0.94), (0.5, -0.3)])
 def test_slab_matches_oracle(prec, gam):
     pos, q, lo, L = workloads.small_system(300, (20.0, 20.0, 10.0), 21, geometry=1)
