@@ -43,11 +43,11 @@ struct Work {
 // g = 0..ngroups-1 of kGroup sorted particles; its range [0, F) of (image,
 // tile) pairs cut into nch chunks of `chunk`; far wave b takes chunk
 // b / ngroups of group b % ngroups and writes slot = chunk index.  The
-// near pass cuts [0, F) into nnear chunks of near_chunk the same way and
-// writes slots nch .. nch + nnear - 1.
+// near pass deals the (image entry, block of 64 tiles) pairs round-robin
+// to nnear waves per group, which write slots nch .. nch + nnear - 1.
 constexpr int kMaxNearSplit = 16;
 struct PartSched {
-  int n, ngroups, ndesc, F, nch, chunk, nnear, near_chunk;
+  int n, ngroups, ndesc, F, nch, chunk, nnear;
 };
 
 // Check-target schedule of one check group: far waves first_work ..

@@ -49,6 +49,14 @@ template <typename Real> struct SrcT;
 template <> struct SrcT<float> { typedef float4 T; };
 template <> struct SrcT<double> { typedef double4 T; };
 
+// Lane l's value of v (l wave-uniform), as a VALU read, no memory access.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_min(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   return v;
@@ -486,11 +494,14 @@ __device__ __forceinline__ double gap2_of(double dlx, double dly, double dlz, do
 // Register budget of the pair kernels: 8 waves per SIMD (<= 64 VGPRs).  The
 // loop is bound by VALU + transcendental issue, and without this bound the
 // compiler spends registers on interleaving and drops to 4 waves (-25 %).
-// (The FP64 variant keeps 4 waves so that its doubles do not spill.)
+// The FP64 variant keeps 4 waves so that its doubles do not spill; the FP32
+// near pass, a few per cent of the pairs, gets 6 for its FP64 close-pair
+// registers.
 #ifndef HSMA_WAVES_PER_EU
 #define HSMA_WAVES_PER_EU 8
 #endif
-#define HSMA_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? HSMA_WAVES_PER_EU : 4)))
+#define HSMA_PAIR_ATTR \
+  __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? (NEAR ? 6 : HSMA_WAVES_PER_EU) : 4)))
 
 template <typename Real, bool NEAR, bool PARTICLES>
 __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ cgroups,
@@ -510,12 +521,11 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   if constexpr (PARTICLES) {
     int gi;
     if constexpr (NEAR) {
-      // near work split over ps.nnear waves per group (small systems have
-      // few groups); slots nch .. nch + nnear - 1
+      // near work split over ps.nnear waves per group (blocks of kWave
+      // tiles dealt round-robin, see below); slots nch .. nch + nnear - 1
       const int c = blockIdx.x / ps.ngroups;
       gi = blockIdx.x - c * ps.ngroups;
-      const int f0 = c * ps.near_chunk;
-      w = Work{gi, f0, min(ps.F, f0 + ps.near_chunk), ps.nch + c};
+      w = Work{gi, 0, ps.F, ps.nch + c};
       part_i = c;
       nparts = ps.nnear;
     } else {
@@ -668,6 +678,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       if (m == ~0ull) far_loop(std::false_type{});
       else far_loop(std::true_type{});
     } else {
+      // the tile's FP64 positions, one per lane: a close pair reads its
+      // source's from lane k (no memory access inside the loop)
+      const double4 p64 = pos64[(long)tile * kTile + lane];
+#pragma unroll 2
       for (int k = 0; k < kTile; ++k) {
         const S v = s[k];
 #pragma unroll
@@ -685,10 +699,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
             r2 = (Real)1;
           } else if ((double)r2 < rc2) {
             // close pair: difference vector from the FP64 positions
-            const double4 ps = pos64[si];
-            dx = (Real)(tp[j].x - (ps.x + ds.sx));
-            dy = (Real)(tp[j].y - (ps.y + ds.sy));
-            dz = sg * (Real)(tp[j].z - (ds.sigma * ps.z + ds.sz));
+            const double psx = readlane_d(p64.x, k), psy = readlane_d(p64.y, k), psz = readlane_d(p64.z, k);
+            dx = (Real)(tp[j].x - (psx + ds.sx));
+            dy = (Real)(tp[j].y - (psy + ds.sy));
+            dz = sg * (Real)(tp[j].z - (ds.sigma * psz + ds.sz));
             r2 = dx * dx + dy * dy + dz * dz;
           }
           const Real ri = rsq(r2);
@@ -735,10 +749,11 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     const int f0 = min(C, part_i * per), f1 = min(C, f0 + per);
     const unsigned tmask = (1u << kTileBits) - 1u;
     if constexpr (NEAR) {
-      for (int fb = f0; fb < f1; fb += kWave) {
+      // blocks of kWave list entries dealt round-robin to the group's waves
+      for (int fb = part_i * kWave; fb < C; fb += nparts * kWave) {
         const int fl = fb + lane;
         bool near = false;
-        if (fl < f1) {
+        if (fl < C) {
           const unsigned e = cv.list[fl];
           const int tile = (int)(e & tmask);
           const Desc dsl = desc[g.desc_off + (int)(e >> kTileBits)];
@@ -791,22 +806,26 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       }
     }
   }
-  int f = cv.list ? w.f1 : w.f0;  // the cell stencil walks [f0, f1) of the entry-major range
-  while (f < w.f1) {
-    const int di = f / ntiles;
-    const int t0 = f - di * ntiles;
-    const int t1 = min(ntiles, t0 + (w.f1 - f));
-    f += t1 - t0;
-    const Desc ds = desc[g.desc_off + di];
-    // every tile of this image lies inside the shifted box: if the box is
-    // far from the group, so is each of its tiles
-    const bool img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
-                                 __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
-    if constexpr (NEAR) {
-      if (img_far) continue;
-      // lane-parallel scan: lane l classifies tile tb + l, then the wave
-      // walks the near ones in increasing tile order
-      for (int tb = t0; tb < t1; tb += kWave) {
+  if constexpr (NEAR) {
+    if (!cv.list) {
+      // near pass over the cell stencil: the group's (image entry, block of
+      // kWave tiles) pairs dealt round-robin to its nparts waves.  The near
+      // tiles cluster in the central image, so contiguous shares of the
+      // entry range would leave almost all of them to one wave.
+      const int nblk = (ntiles + kWave - 1) / kWave;
+      const int nb = g.ndesc * nblk;
+      for (int b = part_i; b < nb; b += nparts) {
+        const int di = b / nblk;
+        const int tb = (b - di * nblk) * kWave;
+        const int t1 = min(ntiles, tb + kWave);
+        const Desc ds = desc[g.desc_off + di];
+        // every tile of this image lies inside the shifted box: if the box
+        // is far from the group, so is each of its tiles
+        if (gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz), __dadd_rn(hgx, hbox.x),
+                    __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2)
+          continue;
+        // lane-parallel scan: lane l classifies tile tb + l, then the wave
+        // walks the near ones in increasing tile order
         const int tile = tb + lane;
         bool near = false;
         if (tile < t1) {
@@ -831,7 +850,21 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           do_tile(ds, nt >= own0 && nt <= own1, nt, dlx, dly, dlz, cull ? cull[(long)di * ntiles + nt] : ~0ull);
         }
       }
-    } else {
+    }
+  }
+  // far kernel over the cell stencil: [f0, f1) of the entry-major range
+  int f = (NEAR || cv.list) ? w.f1 : w.f0;
+  while (f < w.f1) {
+    const int di = f / ntiles;
+    const int t0 = f - di * ntiles;
+    const int t1 = min(ntiles, t0 + (w.f1 - f));
+    f += t1 - t0;
+    const Desc ds = desc[g.desc_off + di];
+    // every tile of this image lies inside the shifted box: if the box is
+    // far from the group, so is each of its tiles
+    const bool img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
+                                 __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
+    if constexpr (!NEAR) {
       for (int tile = t0; tile < t1; ++tile) {
         unsigned long long cm = ~0ull;
         if (cull) {
@@ -1291,12 +1324,11 @@ static PartSched part_schedule(int64_t n, int ndesc, int target) {
   want = std::min<long long>(want, std::max<long long>(1, ps.F / 2));
   ps.chunk = (int)((ps.F + want - 1) / want);
   ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
-  // near pass: one wave per group, or up to kMaxNearSplit waves per group
-  // when there are fewer groups than about 2048
-  const long long nw = std::min<long long>({(long long)kMaxNearSplit, (long long)ps.F,
-                                            std::max<long long>(1, (2048 + ps.ngroups - 1) / ps.ngroups)});
-  ps.near_chunk = (int)((ps.F + nw - 1) / nw);
-  ps.nnear = (ps.F + ps.near_chunk - 1) / ps.near_chunk;
+  // near pass: up to kMaxNearSplit waves per group, so that the launch has
+  // about 8192 waves, at most one per (image entry, block of kWave tiles)
+  const long long nblk = (ntiles + kWave - 1) / kWave;
+  ps.nnear = (int)std::min<long long>({(long long)kMaxNearSplit, (long long)ndesc * nblk,
+                                       std::max<long long>(1, (8192 + ps.ngroups - 1) / ps.ngroups)});
   return ps;
 }
 
