@@ -38,6 +38,11 @@ __device__ __forceinline__ double rsq(double x) {
   return __fma_rn(0.5 * y, r, y);
 }
 
+// Waves per block of the partial-sum reductions (finalize, check rows):
+// wave w sums every kFinParts-th slot; the waves' sums are combined in
+// wave order.
+constexpr int kFinParts = 4;
+
 // Knuth's error-free sum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   s = a + b;
@@ -749,8 +754,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     const int f0 = min(C, part_i * per), f1 = min(C, f0 + per);
     const unsigned tmask = (1u << kTileBits) - 1u;
     if constexpr (NEAR) {
-      // blocks of kWave list entries dealt round-robin to the group's waves
-      for (int fb = part_i * kWave; fb < C; fb += nparts * kWave) {
+      // every wave scans the list in blocks of kWave entries; the near
+      // entries, in list order, are dealt round-robin to the group's waves
+      int skip = part_i;  // near entries to pass over before this wave's next one
+      for (int fb = 0; fb < C; fb += kWave) {
         const int fl = fb + lane;
         bool near = false;
         if (fl < C) {
@@ -766,9 +773,19 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                          __dadd_rn(hgz, (double)hs.z)) < rc2;
         }
         unsigned long long m = __ballot(near);
+        const int cnt = __popcll(m);
+        if (cnt <= skip) {
+          skip -= cnt;
+          continue;
+        }
         while (m) {
           const int l = __ffsll((long long)m) - 1;
           m &= m - 1;
+          if (skip > 0) {
+            --skip;
+            continue;
+          }
+          skip = nparts - 1;
           const unsigned e = cv.list[fb + l];
           const int di = (int)(e >> kTileBits), nt = (int)(e & tmask);
           const Desc ds = desc[g.desc_off + di];
@@ -808,13 +825,16 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   }
   if constexpr (NEAR) {
     if (!cv.list) {
-      // near pass over the cell stencil: the group's (image entry, block of
-      // kWave tiles) pairs dealt round-robin to its nparts waves.  The near
-      // tiles cluster in the central image, so contiguous shares of the
-      // entry range would leave almost all of them to one wave.
+      // near pass over the cell stencil: every wave of the group scans the
+      // (image entry, block of kWave tiles) pairs, and the near tiles, in
+      // scan order, are dealt round-robin to its nparts waves.  The near
+      // tiles cluster in a few blocks of the central image, so dealing
+      // whole blocks (or contiguous ranges) would leave most of them to one
+      // wave.
       const int nblk = (ntiles + kWave - 1) / kWave;
       const int nb = g.ndesc * nblk;
-      for (int b = part_i; b < nb; b += nparts) {
+      int skip = part_i;  // near tiles to pass over before this wave's next one
+      for (int b = 0; b < nb; ++b) {
         const int di = b / nblk;
         const int tb = (b - di * nblk) * kWave;
         const int t1 = min(ntiles, tb + kWave);
@@ -839,9 +859,19 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           if (cull && near) near = cull[(long)di * ntiles + tile] != 0ull;
         }
         unsigned long long m = __ballot(near);
+        const int cnt = __popcll(m);
+        if (cnt <= skip) {
+          skip -= cnt;
+          continue;
+        }
         while (m) {
           const int l = __ffsll((long long)m) - 1;
           m &= m - 1;
+          if (skip > 0) {
+            --skip;
+            continue;
+          }
+          skip = nparts - 1;
           const int nt = tb + l;
           const double4 cs = tile_c[nt];
           const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
@@ -974,22 +1004,23 @@ __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ 
 // check group; the two halves of the block take alternate slots and are
 // combined at the end (error-free for the FP32 potential).
 template <typename Real>
-__global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __restrict__ groups,
-                                                      const CheckSched* __restrict__ csched, int gbase,
-                                                      const int* __restrict__ axis, const Real* __restrict__ part,
-                                                      long slot_elems, double* __restrict__ v) {
-  __shared__ double sh_phi[kGroup], sh_e[kGroup];
+__global__ __launch_bounds__(kGroup * kFinParts) void k_reduce_check(const Group* __restrict__ groups,
+                                                              const CheckSched* __restrict__ csched, int gbase,
+                                                              const int* __restrict__ axis,
+                                                              const Real* __restrict__ part, long slot_elems,
+                                                              double* __restrict__ v) {
+  __shared__ double sh_phi[kFinParts - 1][kGroup], sh_e[kFinParts - 1][kGroup];
   const Group g = groups[blockIdx.x + gbase];
   const CheckSched cs = csched[blockIdx.x + gbase];
-  const int2 sr = make_int2(cs.slot0, cs.nch + 1);
-  const int local = threadIdx.x % kGroup, half = threadIdx.x / kGroup;
+  const int s0 = cs.slot0, s1 = cs.slot0 + cs.nch + 1;  // far chunks + the near slot
+  const int local = threadIdx.x % kGroup, wpart = threadIdx.x / kGroup;
   const bool ok = local < g.count;
   const int t = g.first + (ok ? local : 0);
   const int ax = axis[t];
   double phi = 0, e = 0;
   if constexpr (sizeof(Real) == 4) {
     float hi = 0, lo = 0, ea = 0, ec = 0;
-    for (int w = sr.x + half; w < sr.x + sr.y; w += 2) {
+    for (int w = s0 + wpart; w < s1; w += kFinParts) {
       const Real* p = part + (long)w * slot_elems + local;
       float sm, er;
       two_sum(hi, p[0], sm, er);
@@ -1002,20 +1033,24 @@ __global__ __launch_bounds__(2 * kGroup) void k_reduce_check(const Group* __rest
     phi = (double)hi + (double)lo;
     e = (double)ea + (double)ec;
   } else {
-    for (int w = sr.x + half; w < sr.x + sr.y; w += 2) {
+    for (int w = s0 + wpart; w < s1; w += kFinParts) {
       const Real* p = part + (long)w * slot_elems + local;
       phi += p[0];
       e += p[(2 + ax) * kGroup];
     }
   }
-  if (half == 1) {
-    sh_phi[local] = phi;
-    sh_e[local] = e;
+  if (wpart > 0) {
+    sh_phi[wpart - 1][local] = phi;
+    sh_e[wpart - 1][local] = e;
   }
   __syncthreads();
-  if (half == 0 && ok) {
-    v[2 * t] = phi + sh_phi[local];
-    v[2 * t + 1] = e + sh_e[local];
+  if (wpart == 0 && ok) {
+    for (int w = 0; w < kFinParts - 1; ++w) {
+      phi += sh_phi[w][local];
+      e += sh_e[w][local];
+    }
+    v[2 * t] = phi;
+    v[2 * t + 1] = e;
   }
 }
 
@@ -1060,23 +1095,28 @@ __global__ __launch_bounds__(64) void k_sphere_sources(int F, int nb, const doub
 // Sum the nslot partials of every particle (fixed order), scale by the
 // Coulomb constant, write potential and force in the caller's order, and
 // per-block energy partials q_i Phi_i.  Invalid input -> NaN outputs.
+// A block holds kGroup particles and kFinParts waves: wave w sums slots
+// w, w + kFinParts, ... (compensated in FP32), the waves' sums are combined
+// in FP64 in wave order, so the result does not depend on timing.
 // The images of a particle itself (every image entry except the identity)
 // are summed here in FP64 for each particle.
 template <typename Real>
-__global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* __restrict__ part, long comp_stride,
-                                                  const double4* __restrict__ pos64, const int* __restrict__ perm,
-                                                  const Desc* __restrict__ desc, int ndesc,
-                                                  const unsigned long long* __restrict__ cull, int ntiles,
-                                                  double kc, const int* __restrict__ status, double* __restrict__ pot,
-                                                  double* __restrict__ force, double* __restrict__ epart) {
-  __shared__ double s[256];
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  double e = 0;
+__global__ __launch_bounds__(kWave * kFinParts) void k_finalize(int n, int nslot, const Real* __restrict__ part,
+                                                              long comp_stride, const double4* __restrict__ pos64,
+                                                              const int* __restrict__ perm,
+                                                              const Desc* __restrict__ desc, int ndesc,
+                                                              const unsigned long long* __restrict__ cull,
+                                                              int ntiles, double kc, const int* __restrict__ status,
+                                                              double* __restrict__ pot, double* __restrict__ force,
+                                                              double* __restrict__ epart) {
+  __shared__ double sh[kFinParts - 1][4][kWave];
+  const int lane = threadIdx.x % kWave, wpart = threadIdx.x / kWave;
+  const int t = blockIdx.x * kWave + lane;
+  double phi = 0, fx = 0, fy = 0, fz = 0;
   if (t < n) {
-    double phi, fx, fy, fz;
     if constexpr (sizeof(Real) == 4) {
       float hi = 0, lo = 0, ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;
-      for (int c = 0; c < nslot; ++c) {
+      for (int c = wpart; c < nslot; c += kFinParts) {
         const Real* p = part + (long)c * 5 * comp_stride + t;
         float sm, er;
         two_sum(hi, p[0], sm, er);
@@ -1091,14 +1131,30 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* 
       fy = (double)ay + (double)cy;
       fz = (double)az + (double)cz;
     } else {
-      phi = fx = fy = fz = 0;
-      for (int c = 0; c < nslot; ++c) {
+      for (int c = wpart; c < nslot; c += kFinParts) {
         const Real* p = part + (long)c * 5 * comp_stride + t;
         phi += p[0];
         fx += p[2 * comp_stride];
         fy += p[3 * comp_stride];
         fz += p[4 * comp_stride];
       }
+    }
+  }
+  if (wpart > 0) {
+    sh[wpart - 1][0][lane] = phi;
+    sh[wpart - 1][1][lane] = fx;
+    sh[wpart - 1][2][lane] = fy;
+    sh[wpart - 1][3][lane] = fz;
+  }
+  __syncthreads();
+  if (wpart != 0) return;
+  double e = 0;
+  if (t < n) {
+    for (int w = 0; w < kFinParts - 1; ++w) {
+      phi += sh[w][0][lane];
+      fx += sh[w][1][lane];
+      fy += sh[w][2][lane];
+      fz += sh[w][3][lane];
     }
     const double4 p = pos64[t];
     const double q = p.w;
@@ -1134,13 +1190,9 @@ __global__ __launch_bounds__(256) void k_finalize(int n, int nslot, const Real* 
     }
     e = q * phi;
   }
-  s[threadIdx.x] = e;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) epart[blockIdx.x] = s[0];
+  // fixed-order (butterfly) sum of the block's kWave energy terms
+  for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  if (lane == 0) epart[blockIdx.x] = e;
 }
 
 __global__ __launch_bounds__(256) void k_energy(int nblk, const double* __restrict__ epart, double* __restrict__ energy) {
@@ -1325,9 +1377,8 @@ static PartSched part_schedule(int64_t n, int ndesc, int target) {
   ps.chunk = (int)((ps.F + want - 1) / want);
   ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
   // near pass: up to kMaxNearSplit waves per group, so that the launch has
-  // about 8192 waves, at most one per (image entry, block of kWave tiles)
-  const long long nblk = (ntiles + kWave - 1) / kWave;
-  ps.nnear = (int)std::min<long long>({(long long)kMaxNearSplit, (long long)ndesc * nblk,
+  // about 8192 waves, at most one per near candidate (image entry, tile)
+  ps.nnear = (int)std::min<long long>({(long long)kMaxNearSplit, (long long)ndesc * ntiles,
                                        std::max<long long>(1, (8192 + ps.ngroups - 1) / ps.ngroups)});
   return ps;
 }
@@ -1399,7 +1450,7 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   HIPCHK(hipMalloc((void**)&d_tile_h, sizeof(float4) * cnt));
   HIPCHK(hipMalloc((void**)&d_perm, sizeof(int) * cpad));
   HIPCHK(hipMalloc((void**)&d_red, sizeof(double) * 3 * ((cn + 255) / 256)));
-  HIPCHK(hipMalloc((void**)&d_epart, sizeof(double) * ((cn + 255) / 256)));
+  HIPCHK(hipMalloc((void**)&d_epart, sizeof(double) * ((cn + kWave - 1) / kWave)));
   HIPCHK(hipMalloc(&d_part, part_bytes));
   HIPCHK(hipMalloc(&d_cpart, cpart_bytes));
   HIPCHK(hipMalloc((void**)&d_csched, sizeof(CheckSched) * ncg));
@@ -1419,7 +1470,8 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   cwork_cap = ncwork;
   arena_bytes = sizeof(uint32_t) * cn * 2 + sizeof(int) * cn * 2 + sizeof(uint32_t) * 256 * crs +
                 sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
-                sizeof(double) * 4 * ((cn + 255) / 256) + part_bytes + cpart_bytes + sizeof(CheckSched) * ncg +
+                sizeof(double) * 3 * ((cn + 255) / 256) + sizeof(double) * ((cn + kWave - 1) / kWave) + part_bytes +
+                cpart_bytes + sizeof(CheckSched) * ncg +
                 (sizeof(unsigned long long) + sizeof(unsigned)) * ncull;
   cur_n = -1;
   return HSMA_OK;
@@ -1494,6 +1546,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   const bool fp64 = host.prm.precision == HSMA_FP64;
   const int slab = host.prm.geometry == HSMA_GEOM_2D;
   const int nblk = (n + 255) / 256;
+  const int nfin = (n + kWave - 1) / kWave;  // finalize blocks (energy partials)
   if ((s = record(st, kStStep, 0, err)) != HSMA_OK) return s;
   hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(256), 0, st, n, d_xyz, d_q, (const StepParams*)d_sp, slab, d_pos_w, d_key[0],
                      d_val[0], d_red);
@@ -1558,7 +1611,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                          ncg, (G0), psched_, (const Desc*)d_desc_check, ntiles_, (const double4*)d_tile_c,         \
                          (const float4*)d_tile_h, (const SC*)SRCC, (const double4*)d_pos64,                         \
                          (const StepParams*)d_sp, cv, (RealC*)d_cpart, ccomp, cslot_e);                             \
-      hipLaunchKernelGGL(k_reduce_check<RealC>, dim3((G1) - (G0)), dim3(2 * kGroup), 0, st,                         \
+      hipLaunchKernelGGL(k_reduce_check<RealC>, dim3((G1) - (G0)), dim3(kGroup * kFinParts), 0, st,                 \
                          (const Group*)d_check_groups, (const CheckSched*)d_csched, (G0), (const int*)d_check_axis, \
                          (const RealC*)d_cpart, cslot_e, d_v);                                                      \
     }                                                                                                               \
@@ -1584,7 +1637,8 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
                        (const double4*)d_surf64, F, sph_chunk_, (Real*)d_part, comp, nchunks_ + psched_.nnear);     \
     if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;                                                   \
-    hipLaunchKernelGGL(k_finalize<Real>, dim3(nblk), dim3(256), 0, st, n, nchunks_ + psched_.nnear + nsphere_,     \
+    hipLaunchKernelGGL(k_finalize<Real>, dim3(nfin), dim3(kWave * kFinParts), 0, st, n,                          \
+                       nchunks_ + psched_.nnear + nsphere_,                                                         \
                        (const Real*)d_part, comp, (const double4*)d_pos64, (const int*)d_perm,                     \
                        (const Desc*)d_desc_part, (int)host.desc_particles.size(), cullp, ntiles_,                   \
                        host.prm.coulomb_k, (const int*)d_status, d_pot, d_force, d_epart);                          \
@@ -1634,7 +1688,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
 #undef HSMA_CHECKS
 #undef HSMA_PARTICLES_NEAR
 #undef HSMA_PARTICLES_SPHERE
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nblk, (const double*)d_epart,
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nfin, (const double*)d_epart,
                      d_energy ? d_energy : d_energy_scratch);
   HIPCHK(hipGetLastError());
   if ((s = record(st, kStStep, 1, err)) != HSMA_OK) return s;
