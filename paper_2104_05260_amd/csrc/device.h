@@ -27,8 +27,9 @@ struct DevicePlan {
   HostPlan host;
   int device = 0;
   hipStream_t own_stream = nullptr;
-  hipStream_t side = nullptr;     // check chain of a step, forked from the call's stream
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side = nullptr;       // check chain of a step, forked from the call's stream
+  hipStream_t side_near = nullptr;  // near pass of a step, forked from the call's stream
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join_near = nullptr;
 
   // tuning of the work decomposition
   int part_target = 32768;     // waves per particle pair launch (about)

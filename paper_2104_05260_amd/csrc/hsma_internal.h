@@ -43,9 +43,11 @@ struct Work {
 // g = 0..ngroups-1 of kGroup sorted particles; its range [0, F) of (image,
 // tile) pairs cut into nch chunks of `chunk`; far wave b takes chunk
 // b / ngroups of group b % ngroups and writes slot = chunk index.  The
-// near pass deals the (image entry, block of 64 tiles) pairs round-robin
-// to nnear waves per group, which write slots nch .. nch + nnear - 1.
-constexpr int kMaxNearSplit = 16;
+// near pass deals the group's near (image entry, tile) pairs, in scan
+// order, round-robin to nnear waves per group, which write slots
+// nch .. nch + nnear - 1.
+constexpr int kMaxNearSplit = 64;
+constexpr int kNearWaves = 8192;  // near-pass waves per launch (about, when there are enough candidates)
 struct PartSched {
   int n, ngroups, ndesc, F, nch, chunk, nnear;
 };

@@ -38,10 +38,11 @@ __device__ __forceinline__ double rsq(double x) {
   return __fma_rn(0.5 * y, r, y);
 }
 
-// Waves per block of the partial-sum reductions (finalize, check rows):
-// wave w sums every kFinParts-th slot; the waves' sums are combined in
-// wave order.
-constexpr int kFinParts = 4;
+// Waves per block of the partial-sum reductions (at most, for finalize;
+// always, for the check rows): wave w of P sums every P-th slot from slot
+// w, and the waves' sums are combined in wave order.
+constexpr int kFinParts = 16;
+constexpr int kFinBatch = 4;  // slots whose loads a wave issues together
 
 // Knuth's error-free sum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
@@ -349,53 +350,49 @@ __global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ ord
   build_tile(blockIdx.x, n, s < n ? order[s] : 0, pos, pos64, src32, src64, tile_c, tile_h, perm);
 }
 
-// Small systems (n <= kSmallSort): validation, the key sort and the tiles
-// in one block.  The sort is a bitonic network in LDS over unique 64-bit
-// (key, input index) words, so its order equals the stable radix sort's.
+// Small systems (n <= kSmallSort): validation and the key sort in one
+// launch of ceil(n / kWave) blocks.  Word i = (key_i, i) is unique, and its
+// rank (the number of smaller words) is its place in the sorted order, which
+// is therefore the stable radix sort's.  Every block stages the n keys in
+// LDS; its kRankWaves waves count the smaller words of its kWave targets
+// over contiguous shares of the key range, and the counts are added.  The
+// tiles are then built from the order by k_tiles.
 constexpr int kSmallSort = 4096;
 // largest system whose check chain overlaps its particle sums (side stream)
 constexpr int kOverlapMaxN = 32768;
-constexpr int kSmallThreads = 1024;
+constexpr int kRankWaves = 16;
 
-__global__ __launch_bounds__(kSmallThreads) void k_small_prep(int n, int nblk, const double* __restrict__ red,
-                                                              int* __restrict__ status, const uint32_t* __restrict__ key,
-                                                              const double4* __restrict__ pos,
-                                                              double4* __restrict__ pos64, float4* __restrict__ src32,
-                                                              double4* __restrict__ src64, double4* __restrict__ tile_c,
-                                                              float4* __restrict__ tile_h, int* __restrict__ perm) {
-  __shared__ unsigned long long sk[kSmallSort];
+__global__ __launch_bounds__(kWave * kRankWaves) void k_rank(int n, int nblk, const double* __restrict__ red,
+                                                            int* __restrict__ status,
+                                                            const uint32_t* __restrict__ key,
+                                                            int* __restrict__ order) {
+  __shared__ uint32_t sk[kSmallSort];
+  __shared__ int cnt[kRankWaves][kWave];
   __shared__ double s0[256], s1[256], s2[256];
-  validate_block(nblk, red, status, s0, s1, s2);
-  int m = kTile;
-  while (m < n) m <<= 1;
-  for (int i = threadIdx.x; i < m; i += kSmallThreads)
-    sk[i] = i < n ? (((unsigned long long)key[i] << 32) | (unsigned)i) : ~0ull;
+  if (blockIdx.x == 0) validate_block(nblk, red, status, s0, s1, s2);  // block-uniform branch
+  for (int t = threadIdx.x; t < n; t += blockDim.x) sk[t] = key[t];
   __syncthreads();
-  for (int k = 2; k <= m; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < m; i += kSmallThreads) {
-        const int l = i ^ j;
-        if (l > i) {
-          const unsigned long long a = sk[i], b = sk[l];
-          if ((a > b) == ((i & k) == 0)) {
-            sk[i] = b;
-            sk[l] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i = blockIdx.x * kWave + lane;
+  const uint32_t ki = i < n ? sk[i] : 0u;
+  // word j < word i  <=>  k_j < k_i, or k_j == k_i and j < i
+  const int per = (n + kRankWaves - 1) / kRankWaves;
+  const int j0 = min(n, w * per), j1 = min(n, j0 + per);
+  int c = 0;
+#pragma unroll 8
+  for (int j = j0; j < j1; ++j) {
+    const uint32_t kj = sk[j];  // the same address in every lane: one broadcast read
+    c += (kj < ki) | ((kj == ki) & (j < i));
   }
-  const int ntiles = (n + kTile - 1) / kTile;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  for (int t = wave; t < ntiles; t += kSmallThreads / kWave) {
-    const int s = t * kTile + lane;
-    build_tile(t, n, s < n ? (int)(unsigned)(sk[s] & 0xffffffffull) : 0, pos, pos64, src32, src64, tile_c, tile_h,
-               perm);
+  cnt[w][lane] = c;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    int r = 0;
+    for (int q = 0; q < kRankWaves; ++q) r += cnt[q][lane];
+    order[r] = i;
   }
 }
 
-// ----------------------------------------------------------------- sphere near set
 // Sphere near set: bit l of cull[d * ntiles + t] says whether the image of
 // sorted source t*64+l under image entry d lies strictly inside the sphere,
 // |y|^2 = (y_x^2 + y_y^2) + y_z^2 < R^2 in FP64 with explicitly rounded
@@ -1020,23 +1017,44 @@ __global__ __launch_bounds__(kGroup * kFinParts) void k_reduce_check(const Group
   double phi = 0, e = 0;
   if constexpr (sizeof(Real) == 4) {
     float hi = 0, lo = 0, ea = 0, ec = 0;
-    for (int w = s0 + wpart; w < s1; w += kFinParts) {
-      const Real* p = part + (long)w * slot_elems + local;
-      float sm, er;
-      two_sum(hi, p[0], sm, er);
-      hi = sm;
-      lo += er + p[kGroup];
-      two_sum(ea, p[(2 + ax) * kGroup], sm, er);
-      ea = sm;
-      ec += er;
+    for (int w0 = s0 + wpart; w0 < s1; w0 += kFinBatch * kFinParts) {
+      float v[kFinBatch][3];
+#pragma unroll
+      for (int u = 0; u < kFinBatch; ++u) {
+        const int w = w0 + u * kFinParts;
+        const Real* p = part + (long)(w < s1 ? w : s0) * slot_elems + local;
+        v[u][0] = w < s1 ? p[0] : 0.f;
+        v[u][1] = w < s1 ? p[kGroup] : 0.f;
+        v[u][2] = w < s1 ? p[(2 + ax) * kGroup] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kFinBatch; ++u) {
+        float sm, er;
+        two_sum(hi, v[u][0], sm, er);
+        hi = sm;
+        lo += er + v[u][1];
+        two_sum(ea, v[u][2], sm, er);
+        ea = sm;
+        ec += er;
+      }
     }
     phi = (double)hi + (double)lo;
     e = (double)ea + (double)ec;
   } else {
-    for (int w = s0 + wpart; w < s1; w += kFinParts) {
-      const Real* p = part + (long)w * slot_elems + local;
-      phi += p[0];
-      e += p[(2 + ax) * kGroup];
+    for (int w0 = s0 + wpart; w0 < s1; w0 += kFinBatch * kFinParts) {
+      double v[kFinBatch][2];
+#pragma unroll
+      for (int u = 0; u < kFinBatch; ++u) {
+        const int w = w0 + u * kFinParts;
+        const Real* p = part + (long)(w < s1 ? w : s0) * slot_elems + local;
+        v[u][0] = w < s1 ? p[0] : 0.0;
+        v[u][1] = w < s1 ? p[(2 + ax) * kGroup] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kFinBatch; ++u) {
+        phi += v[u][0];
+        e += v[u][1];
+      }
     }
   }
   if (wpart > 0) {
@@ -1095,8 +1113,9 @@ __global__ __launch_bounds__(64) void k_sphere_sources(int F, int nb, const doub
 // Sum the nslot partials of every particle (fixed order), scale by the
 // Coulomb constant, write potential and force in the caller's order, and
 // per-block energy partials q_i Phi_i.  Invalid input -> NaN outputs.
-// A block holds kGroup particles and kFinParts waves: wave w sums slots
-// w, w + kFinParts, ... (compensated in FP32), the waves' sums are combined
+// A block holds kWave particles and P = blockDim.x / kWave <= kFinParts
+// waves: wave w sums slots w, w + P, ... (compensated in FP32), the waves'
+// sums are combined
 // in FP64 in wave order, so the result does not depend on timing.
 // The images of a particle itself (every image entry except the identity)
 // are summed here in FP64 for each particle.
@@ -1110,33 +1129,56 @@ __global__ __launch_bounds__(kWave * kFinParts) void k_finalize(int n, int nslot
                                                               double* __restrict__ pot, double* __restrict__ force,
                                                               double* __restrict__ epart) {
   __shared__ double sh[kFinParts - 1][4][kWave];
-  const int lane = threadIdx.x % kWave, wpart = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wpart = threadIdx.x / kWave, np = blockDim.x / kWave;
   const int t = blockIdx.x * kWave + lane;
   double phi = 0, fx = 0, fy = 0, fz = 0;
   if (t < n) {
     if constexpr (sizeof(Real) == 4) {
       float hi = 0, lo = 0, ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;
-      for (int c = wpart; c < nslot; c += kFinParts) {
-        const Real* p = part + (long)c * 5 * comp_stride + t;
-        float sm, er;
-        two_sum(hi, p[0], sm, er);
-        hi = sm;
-        lo += er + p[comp_stride];
-        two_sum(ax, p[2 * comp_stride], sm, er); ax = sm; cx += er;
-        two_sum(ay, p[3 * comp_stride], sm, er); ay = sm; cy += er;
-        two_sum(az, p[4 * comp_stride], sm, er); az = sm; cz += er;
+      // slots in batches of kFinBatch: the batch's loads are all issued
+      // before the (in-order) compensated sums use them
+      for (int c0 = wpart; c0 < nslot; c0 += kFinBatch * np) {
+        float v[kFinBatch][5];
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) {
+          const int c = c0 + u * np;
+          const Real* p = part + (long)(c < nslot ? c : 0) * 5 * comp_stride + t;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) v[u][k] = c < nslot ? p[k * comp_stride] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) {
+          float sm, er;
+          two_sum(hi, v[u][0], sm, er);
+          hi = sm;
+          lo += er + v[u][1];
+          two_sum(ax, v[u][2], sm, er); ax = sm; cx += er;
+          two_sum(ay, v[u][3], sm, er); ay = sm; cy += er;
+          two_sum(az, v[u][4], sm, er); az = sm; cz += er;
+        }
       }
       phi = (double)hi + (double)lo;
       fx = (double)ax + (double)cx;
       fy = (double)ay + (double)cy;
       fz = (double)az + (double)cz;
     } else {
-      for (int c = wpart; c < nslot; c += kFinParts) {
-        const Real* p = part + (long)c * 5 * comp_stride + t;
-        phi += p[0];
-        fx += p[2 * comp_stride];
-        fy += p[3 * comp_stride];
-        fz += p[4 * comp_stride];
+      for (int c0 = wpart; c0 < nslot; c0 += kFinBatch * np) {
+        double v[kFinBatch][4];
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) {
+          const int c = c0 + u * np;
+          const Real* p = part + (long)(c < nslot ? c : 0) * 5 * comp_stride + t;
+          v[u][0] = c < nslot ? p[0] : 0.0;
+#pragma unroll
+          for (int k = 1; k < 4; ++k) v[u][k] = c < nslot ? p[(k + 1) * comp_stride] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) {
+          phi += v[u][0];
+          fx += v[u][1];
+          fy += v[u][2];
+          fz += v[u][3];
+        }
       }
     }
   }
@@ -1150,7 +1192,7 @@ __global__ __launch_bounds__(kWave * kFinParts) void k_finalize(int n, int nslot
   if (wpart != 0) return;
   double e = 0;
   if (t < n) {
-    for (int w = 0; w < kFinParts - 1; ++w) {
+    for (int w = 0; w < np - 1; ++w) {
       phi += sh[w][0][lane];
       fx += sh[w][1][lane];
       fy += sh[w][2][lane];
@@ -1281,8 +1323,10 @@ hsma_status DevicePlan::init(std::string& err) {
   HIPCHK(hipGetDevice(&device));
   // side stream of the step (default priority) and its fork/join events
   HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&side_near, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ev_join_near, hipEventDisableTiming));
   hsma_status st;
   if ((st = upload(&d_desc_part, host.desc_particles, err)) != HSMA_OK) return st;
   if ((st = upload(&d_desc_check, host.desc_check, err)) != HSMA_OK) return st;
@@ -1358,8 +1402,10 @@ DevicePlan::~DevicePlan() {
     if (p) (void)hipFree(p);
   if (own_stream) (void)hipStreamDestroy(own_stream);
   if (side) (void)hipStreamDestroy(side);
+  if (side_near) (void)hipStreamDestroy(side_near);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
+  if (ev_join_near) (void)hipEventDestroy(ev_join_near);
 }
 
 // Particle schedule for n particles: chunks sized so that a launch has
@@ -1373,13 +1419,17 @@ static PartSched part_schedule(int64_t n, int ndesc, int target) {
   ps.ndesc = ndesc;
   ps.F = ndesc * ntiles;
   long long want = std::max<long long>(1, (target + (long long)ps.ngroups - 1) / ps.ngroups);
-  want = std::min<long long>(want, std::max<long long>(1, ps.F / 2));
+  // at least 4 tiles per chunk while that leaves 4096 far waves, else at
+  // least 2 (fewer partial slots to write and to sum)
+  const long long cap4 = std::max<long long>(1, ps.F / 4);
+  want = std::min<long long>(want, cap4 * ps.ngroups >= 4096 ? cap4 : std::max<long long>(1, ps.F / 2));
   ps.chunk = (int)((ps.F + want - 1) / want);
   ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
   // near pass: up to kMaxNearSplit waves per group, so that the launch has
-  // about 8192 waves, at most one per near candidate (image entry, tile)
+  // about kNearWaves waves, at most one per near candidate (image entry,
+  // tile)
   ps.nnear = (int)std::min<long long>({(long long)kMaxNearSplit, (long long)ndesc * ntiles,
-                                       std::max<long long>(1, (8192 + ps.ngroups - 1) / ps.ngroups)});
+                                       std::max<long long>(1, (kNearWaves + ps.ngroups - 1) / ps.ngroups)});
   return ps;
 }
 
@@ -1414,10 +1464,13 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
   // every size (see sphere_chunk)
   const size_t sph = 1024 + (size_t)ngroups * ((size_t)host.prm.F / kSphereChunkMax + 2);
   const size_t ncg = host.check_groups.size();
-  part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + (2 + kMaxNearSplit) * (size_t)ngroups + sph);
+  // far slots <= part_target + ngroups; near slots <= min(kMaxNearSplit
+  // ngroups, kNearWaves + ngroups)
+  const size_t nearb = std::min<size_t>((size_t)kMaxNearSplit * ngroups, (size_t)kNearWaves + ngroups);
+  part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + ngroups + nearb + sph + 1);
   const size_t rbc = cpart_elem();
   cpart_bytes = rbc * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
-  nwork = (size_t)part_target + (2 + kMaxNearSplit) * (size_t)ngroups + 2;
+  nwork = (size_t)part_target + ngroups + nearb + 2;
   ncwork = (size_t)check_target_max + 2 * ncg + 2;
 }
 
@@ -1547,13 +1600,14 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   const int slab = host.prm.geometry == HSMA_GEOM_2D;
   const int nblk = (n + 255) / 256;
   const int nfin = (n + kWave - 1) / kWave;  // finalize blocks (energy partials)
+  // finalize waves per block: about 8 slots for each
+  const int fparts = std::min(kFinParts, std::max(1, (nchunks_ + psched_.nnear + nsphere_) / 8));
   if ((s = record(st, kStStep, 0, err)) != HSMA_OK) return s;
   hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(256), 0, st, n, d_xyz, d_q, (const StepParams*)d_sp, slab, d_pos_w, d_key[0],
                      d_val[0], d_red);
   if (n <= kSmallSort) {
-    hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, n, nblk, (const double*)d_red, d_status,
-                       (const uint32_t*)d_key[0], (const double4*)d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
-                       d_tile_h, d_perm);
+    hipLaunchKernelGGL(k_rank, dim3((n + kWave - 1) / kWave), dim3(kWave * kRankWaves), 0, st, n, nblk,
+                       (const double*)d_red, d_status, (const uint32_t*)d_key[0], d_val[0]);
   } else {
     hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, nblk, (const double*)d_red, d_status);
     // radix sort: 4 passes of 8 bits over the 30-bit keys (result back in buffer 0)
@@ -1566,9 +1620,9 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
       hipLaunchKernelGGL(k_rs_scatter, dim3(nrsblk_), dim3(256), 0, st, (const uint32_t*)d_key[a],
                          (const int*)d_val[a], d_key[b], d_val[b], n, sh, (const uint32_t*)d_hist, nrsblk_);
     }
-    hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
-                       d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
   }
+  hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
+                     d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
   const unsigned long long* cullp = nullptr;
   CullView cv{nullptr, nullptr, nullptr};
   if (host.prm.near_rule == 1) {
@@ -1616,7 +1670,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                          (const RealC*)d_cpart, cslot_e, d_v);                                                      \
     }                                                                                                               \
   } while (0)
-#define HSMA_PARTICLES_NEAR(Real, S, SRC)                                                                           \
+#define HSMA_PARTICLES_NEAR(Real, S, SRC, NST)                                                                         \
   do {                                                                                                              \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
@@ -1625,7 +1679,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                        (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
                        slot);                                                                                       \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
-    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, st,          \
+    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, (NST),       \
                        (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,      \
                        (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
                        (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
@@ -1637,7 +1691,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
                        (const double4*)d_surf64, F, sph_chunk_, (Real*)d_part, comp, nchunks_ + psched_.nnear);     \
     if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;                                                   \
-    hipLaunchKernelGGL(k_finalize<Real>, dim3(nfin), dim3(kWave * kFinParts), 0, st, n,                          \
+    hipLaunchKernelGGL(k_finalize<Real>, dim3(nfin), dim3(kWave * fparts), 0, st, n,                              \
                        nchunks_ + psched_.nnear + nsphere_,                                                         \
                        (const Real*)d_part, comp, (const double4*)d_pos64, (const int*)d_perm,                     \
                        (const Desc*)d_desc_part, (int)host.desc_particles.size(), cullp, ntiles_,                   \
@@ -1647,15 +1701,21 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   // tiles, as do the near-set sums at the particles.  For systems up to
   // kOverlapMaxN particles the first chain runs on a side stream, forked
   // from and joined back into the call's stream (event edges, so a captured
-  // step graph holds both branches), while the particle sums run on the
-  // call's stream: the chain's small, latency-bound kernels then overlap
-  // the particle sums.  Larger systems fill the GPU with the particle sums
-  // alone; there the chain runs first on the call's stream.
+  // step graph holds all branches), while the far particle sums run on the
+  // call's stream (and, above kSmallSort particles, the near pass on a
+  // second side stream): the chain's small, latency-bound kernels and the
+  // near waves then overlap the far waves.  Larger systems fill the GPU with
+  // the particle sums alone; there everything runs in order on the call's
+  // stream.
   const bool overlap = n <= kOverlapMaxN;
+  // the near pass (latency-bound waves) gets a second side stream where it
+  // is long enough to pay for the extra fork and join
+  const bool near_side = overlap && n > kSmallSort;
   {
     if (overlap) {
       HIPCHK(hipEventRecord(ev_fork, st));
       HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+      if (near_side) HIPCHK(hipStreamWaitEvent(side_near, ev_fork, 0));
     }
     {
       const hipStream_t st = overlap ? side : stream_arg;  // where the check chain's launches go
@@ -1680,9 +1740,12 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
       if (overlap) HIPCHK(hipEventRecord(ev_join, st));
     }
   }
-  if (fp64) HSMA_PARTICLES_NEAR(double, double4, d_src64);
-  else HSMA_PARTICLES_NEAR(float, float4, d_src32);
+  const hipStream_t nst = near_side ? side_near : stream_arg;
+  if (fp64) HSMA_PARTICLES_NEAR(double, double4, d_src64, nst);
+  else HSMA_PARTICLES_NEAR(float, float4, d_src32, nst);
+  if (near_side) HIPCHK(hipEventRecord(ev_join_near, side_near));
   if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+  if (near_side) HIPCHK(hipStreamWaitEvent(st, ev_join_near, 0));
   if (fp64) HSMA_PARTICLES_SPHERE(double);
   else HSMA_PARTICLES_SPHERE(float);
 #undef HSMA_CHECKS
