@@ -80,18 +80,28 @@ typedef struct hsma_params {
                           image position); the stencil covers the sphere for
                           every admissible R.  Rule 1 sums about a third of
                           the pairs (3D, lambda 1.5) but its far field starts
-                          at R, so it needs a higher p for the same error   */
+                          at R, so it needs a higher p for the same error.
+                          2: the 3D cell stencil of rule 0, summed at the
+                          particles by a treecode (multipole expansions of
+                          order tree_order for source nodes that satisfy
+                          (r_node + r_group) < tree_theta * distance, direct
+                          sums elsewhere); check points stay direct.  3D and
+                          FP32C only.  An approximation of rule 0: about
+                          1e-6 relative RMS force error at order 8, theta 0.5 */
   int M;               /* 2D: image layers above and below                    */
   double gamma_up;     /* 2D: (eps_c - eps_up)/(eps_c + eps_up), |gamma| < 1  */
   double gamma_low;    /* 2D: (eps_c - eps_low)/(eps_c + eps_low)             */
   int nz;              /* 2D: interface grid points per dimension (DtN rows)  */
   double coulomb_k;    /* prefactor of q_i q_j / r (default 1)                */
+  int tree_order;      /* near rule 2: multipole order, 4, 6, 8, 10 or 12     */
+  double tree_theta;   /* near rule 2: opening parameter, 0 < theta <= 0.75   */
 } hsma_params;
 
 typedef struct hsma_plan hsma_plan;
 
 /* Fills *p with defaults: 3D, FP32C, lambda 1.5, p 10, K 2(p+1)^2, F 800,
- * Fw 0, surface rule 0, near rule 0, M 10, gammas 0, nz 80, coulomb_k 1.   */
+ * Fw 0, surface rule 0, near rule 0, M 10, gammas 0, nz 80, coulomb_k 1,
+ * tree order 8, tree theta 0.5.                                           */
 void hsma_params_default(hsma_params* p);
 
 /* Builds the per-geometry plan: check points, sphere quadrature, harmonic

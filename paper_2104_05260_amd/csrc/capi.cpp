@@ -61,6 +61,8 @@ void hsma_params_default(hsma_params* p) {
   p->gamma_low = 0.0;
   p->nz = 80;
   p->coulomb_k = 1.0;
+  p->tree_order = 8;
+  p->tree_theta = 0.5;
 }
 
 const char* hsma_last_error(void) { return g_err.c_str(); }

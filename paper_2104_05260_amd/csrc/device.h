@@ -79,6 +79,12 @@ struct DevicePlan {
   unsigned long long* d_cull = nullptr;  // sphere near set: ndesc x ntiles source masks
   unsigned* d_clist = nullptr;           // sphere near set: non-empty (entry, tile) pairs
   int* d_ccount = nullptr;
+  // treecode (near rule 2): node centres + radii, boxes (lo, hi), moments
+  double4* d_tnode = nullptr;
+  double4* d_tbox = nullptr;
+  double* d_tmom64 = nullptr;
+  float* d_tmom32 = nullptr;
+  TreeLevels tree_{};
   hipEvent_t stage_ev = nullptr;
   PartSched psched_{};
   int ntiles_ = 0, ngroups_ = 0, ncwork_ = 0, cwork_face_ = 0, nchunks_ = 0, nsphere_ = 0, sph_chunk_ = 0,
@@ -101,6 +107,7 @@ struct DevicePlan {
   int timed_calls = 0;
   std::vector<hipEvent_t> events;   // kStages * 2 events per timed call
   hsma_status record(hipStream_t st, int stage, int edge, std::string& err);
+  hsma_status launch_tree(hipStream_t st, int n, long comp, long slot, std::string& err);
   hipStream_t last_stream = nullptr;
 
   void* h_stage = nullptr;       // pinned staging of the check schedule

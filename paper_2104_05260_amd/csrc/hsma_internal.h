@@ -50,7 +50,37 @@ constexpr int kMaxNearSplit = 64;
 constexpr int kNearWaves = 8192;  // near-pass waves per launch (about, when there are enough candidates)
 struct PartSched {
   int n, ngroups, ndesc, F, nch, chunk, nnear;
+  int split;  // treecode: waves per (image entry, group)
 };
+constexpr int kTreeWaves = 65536;  // treecode waves per launch (about, at least one per (image entry, group))
+constexpr int kTreeMaxSplit = 8;
+
+// Treecode over the tiles (near rule 2): level 0 holds the tiles in sorted
+// (Hilbert) order; node i of level l >= 1 groups nodes 8i .. 8i + 7 of
+// level l - 1, so it covers tiles [8^l i, 8^l (i + 1)).  Nodes of levels
+// >= 1 are stored level after level from index off[l].
+constexpr int kTreeMaxLev = 12;
+constexpr int kTreeMaxOrder = 12;
+constexpr int kTreeMom = (kTreeMaxOrder + 1) * (kTreeMaxOrder + 2) / 2;  // complex moments, m <= n <= order
+constexpr int kTreeMomStride = 192;  // reals per node (re, im of each moment), >= 2 kTreeMom
+struct TreeLevels {
+  int nlev;                // levels, 1 (tiles only) .. kTreeMaxLev
+  int cnt[kTreeMaxLev];    // nodes per level; cnt[0] = tiles
+  int off[kTreeMaxLev];    // first index of level l >= 1 in the node arrays
+  int nodes;               // nodes of levels >= 1
+};
+inline TreeLevels tree_levels(int ntiles) {
+  TreeLevels t{};
+  t.cnt[0] = ntiles;
+  t.nlev = 1;
+  while (t.cnt[t.nlev - 1] > 1 && t.nlev < kTreeMaxLev) {
+    t.off[t.nlev] = t.nodes;
+    t.cnt[t.nlev] = (t.cnt[t.nlev - 1] + 7) / 8;
+    t.nodes += t.cnt[t.nlev];
+    ++t.nlev;
+  }
+  return t;
+}
 
 // Check-target schedule of one check group: far waves first_work ..
 // first_work + nch - 1 take chunks of `chunk` and write slots slot0 + c;

@@ -1001,6 +1001,520 @@ __global__ __launch_bounds__(64) void k_pair_sphere(const double4* __restrict__ 
 // v[2t] = potential, v[2t+1] = field component axis[t].  One block per
 // check group; the two halves of the block take alternate slots and are
 // combined at the end (error-free for the FP32 potential).
+// ------------------------------------------------------------ treecode
+// Near rule 2: the far part of the cell-stencil sums at the particles by a
+// treecode.  A source node (levels >= 1 of the tile hierarchy) far enough
+// from a target group, (r_node + r_group) < theta * distance, acts through
+// its multipole expansion about its centre; other nodes are opened; tiles
+// reached that way are summed directly (the near pass keeps the tile
+// pairs within the close-pair radius, as for rule 0).  The expansion is
+// the addition theorem of the solid harmonics,
+//   1 / |x - y| = sum_{n >= 0} sum_{|m| <= n} conj(U_n^m(y)) T_n^m(x),
+// |y| < |x|, with the regular U and irregular T harmonics fixed by
+//   U_0^0 = 1, U_m^m = (x + iy) / (2m) U_{m-1}^{m-1},
+//   U_n^m = ((2n - 1) z U_{n-1}^m - r^2 U_{n-2}^m) / ((n + m)(n - m)),
+//   T_0^0 = 1 / r, T_m^m = (2m - 1) (x + iy) / r^2 T_{m-1}^{m-1},
+//   T_n^m = ((2n - 1) z T_{n-1}^m - ((n - 1)^2 - m^2) T_{n-2}^m) / r^2,
+// and X_n^{-m} = (-1)^m conj(X_n^m).  The moments of a node about its
+// centre c are M_n^m = sum_j q_j U_n^m(y_j - c); its potential is
+// sum conj(M_n^m) T_n^m(x - c), and the field follows from
+//   d/dz T_n^m = -T_{n+1}^m,  (d/dx + i d/dy) T_n^m = -T_{n+1}^{m+1}.
+// Moments are built in FP64 (tiles of level-1 nodes directly, higher
+// levels by shifting the children's moments, U_n^m(a + b) =
+// sum_k sum_l U_k^l(a) U_{n-k}^{m-l}(b)) and evaluated in FP32.
+
+__device__ __forceinline__ int tree_idx(int n, int m) { return n * (n + 1) / 2 + m; }
+
+// A value equal in every lane, marked as such for the compiler (so that
+// what depends on it stays in scalar registers and branches).
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// X_n^m of a table of m >= 0 entries (re, im interleaved), any |m| <= n
+__device__ __forceinline__ void tree_get(const double* t, int n, int m, double& re, double& im) {
+  const int am = m < 0 ? -m : m;
+  re = t[2 * tree_idx(n, am)];
+  im = t[2 * tree_idx(n, am) + 1];
+  if (m < 0) {
+    const double s = (am & 1) ? -1.0 : 1.0;
+    re *= s;
+    im *= -s;
+  }
+}
+
+// Level-1 nodes: bounding box of their (up to 8) tiles, centre, radius,
+// and moments from their particles.  One block of 8 waves per node, wave
+// w on tile 8 * node + w; each moment is a wave sum per tile, then a sum
+// over the tiles in tile order.
+__global__ __launch_bounds__(512) void k_tree_p2m(int n, int ntiles, int order, TreeLevels tl,
+                                                 const double4* __restrict__ pos64,
+                                                 const double4* __restrict__ tile_c,
+                                                 const float4* __restrict__ tile_h, double4* __restrict__ node_c,
+                                                 double4* __restrict__ node_box, double* __restrict__ mom64,
+                                                 float* __restrict__ mom32) {
+  __shared__ double sbox[8][6];
+  __shared__ double sc[3];
+  __shared__ double sm[8][2 * kTreeMom];
+  const int node = blockIdx.x;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int t = 8 * node + w;
+  const bool has = t < ntiles;
+  if (lane == 0) {
+    if (has) {
+      const double4 c = tile_c[t];
+      const float4 h = tile_h[t];
+      sbox[w][0] = c.x - (double)h.x; sbox[w][1] = c.y - (double)h.y; sbox[w][2] = c.z - (double)h.z;
+      sbox[w][3] = c.x + (double)h.x; sbox[w][4] = c.y + (double)h.y; sbox[w][5] = c.z + (double)h.z;
+    } else {
+      sbox[w][0] = sbox[w][1] = sbox[w][2] = INFINITY;
+      sbox[w][3] = sbox[w][4] = sbox[w][5] = -INFINITY;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = sbox[0][d];
+      hi[d] = sbox[0][3 + d];
+      for (int k = 1; k < 8; ++k) {
+        lo[d] = fmin(lo[d], sbox[k][d]);
+        hi[d] = fmax(hi[d], sbox[k][3 + d]);
+      }
+      sc[d] = 0.5 * (lo[d] + hi[d]);
+    }
+    const double hx = 0.5 * (hi[0] - lo[0]), hy = 0.5 * (hi[1] - lo[1]), hz = 0.5 * (hi[2] - lo[2]);
+    const int g = tl.off[1] + node;
+    node_c[g] = make_double4(sc[0], sc[1], sc[2], sqrt(hx * hx + hy * hy + hz * hz));
+    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], 0.0);
+    node_box[2 * g + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
+  }
+  __syncthreads();
+  const int s = t * kTile + lane;
+  double q = 0, yx = 0, yy = 0, yz = 0;
+  if (has && s < n) {
+    const double4 p = pos64[s];
+    q = p.w;
+    yx = p.x - sc[0];
+    yy = p.y - sc[1];
+    yz = p.z - sc[2];
+  }
+  const double r2 = yx * yx + yy * yy + yz * yz;
+  double ur = 1.0, ui = 0.0;  // sectoral U_m^m
+  for (int m = 0; m <= order; ++m) {
+    if (m > 0) {
+      const double f = 1.0 / (2 * m);
+      const double nr = f * (yx * ur - yy * ui), ni = f * (yx * ui + yy * ur);
+      ur = nr;
+      ui = ni;
+    }
+    double pr = 0.0, pi = 0.0, cr = ur, ci = ui;  // U_{n-1}^m, U_n^m
+    for (int nn = m; nn <= order; ++nn) {
+      if (nn > m) {
+        const double inv = 1.0 / ((double)(nn + m) * (double)(nn - m));
+        const double a = (2 * nn - 1) * yz;
+        const double nr = (a * cr - r2 * pr) * inv, ni = (a * ci - r2 * pi) * inv;
+        pr = cr;
+        pi = ci;
+        cr = nr;
+        ci = ni;
+      }
+      const double vr = wave_sum_d(q * cr), vi = wave_sum_d(q * ci);
+      if (lane == 0) {
+        sm[w][2 * tree_idx(nn, m)] = vr;
+        sm[w][2 * tree_idx(nn, m) + 1] = vi;
+      }
+    }
+  }
+  __syncthreads();
+  const int nr2 = (order + 1) * (order + 2);
+  const long g = (long)tl.off[1] + node;
+  for (int k = threadIdx.x; k < nr2; k += blockDim.x) {
+    double acc = 0.0;
+    for (int ww = 0; ww < 8; ++ww) acc += sm[ww][k];
+    mom64[g * kTreeMomStride + k] = acc;
+    mom32[g * kTreeMomStride + k] = (float)acc;
+  }
+}
+
+// Nodes of level l >= 2: box from the children's boxes, moments by
+// shifting the children's moments to the node centre (children in order).
+// One wave per node, lane k on moments k and k + 64.
+__global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevels tl, double4* __restrict__ node_c,
+                                                double4* __restrict__ node_box, double* __restrict__ mom64,
+                                                float* __restrict__ mom32) {
+  __shared__ double su[2 * kTreeMom];
+  __shared__ double smc[2 * kTreeMom];
+  const int node = blockIdx.x, lane = threadIdx.x;
+  const int c0 = 8 * node, c1 = min(c0 + 8, tl.cnt[level - 1]);
+  const int coff = tl.off[level - 1];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (lane < c1 - c0) {
+    const double4 a = node_box[2 * (coff + c0 + lane)], b = node_box[2 * (coff + c0 + lane) + 1];
+    lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
+    hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+  }
+  double c[3], h[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = wave_min(lo[d]);
+    hi[d] = wave_max(hi[d]);
+    c[d] = 0.5 * (lo[d] + hi[d]);
+    h[d] = 0.5 * (hi[d] - lo[d]);
+  }
+  const int g = tl.off[level] + node;
+  if (lane == 0) {
+    node_c[g] = make_double4(c[0], c[1], c[2], sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]));
+    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], 0.0);
+    node_box[2 * g + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
+  }
+  const int nm = (order + 1) * (order + 2) / 2;
+  int tn[2] = {0, 0}, tm[2] = {0, 0};  // this lane's moments (n, m)
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + h * kWave;
+    if (k < nm) {
+      while (tree_idx(tn[h] + 1, 0) <= k) ++tn[h];
+      tm[h] = k - tree_idx(tn[h], 0);
+    }
+  }
+  double accr[2] = {0.0, 0.0}, acci[2] = {0.0, 0.0};
+  for (int ch = c0; ch < c1; ++ch) {
+    const double4 cc = node_c[coff + ch];
+    const double tx = cc.x - c[0], ty = cc.y - c[1], tz = cc.z - c[2];
+    for (int k = lane; k < 2 * nm; k += kWave) smc[k] = mom64[(long)(coff + ch) * kTreeMomStride + k];
+    if (lane <= order) {
+      // column m = lane of U(t)
+      const int m = lane;
+      double ur = 1.0, ui = 0.0;
+      for (int k = 1; k <= m; ++k) {
+        const double f = 1.0 / (2 * k);
+        const double nr = f * (tx * ur - ty * ui), ni = f * (tx * ui + ty * ur);
+        ur = nr;
+        ui = ni;
+      }
+      const double r2 = tx * tx + ty * ty + tz * tz;
+      double pr = 0.0, pi = 0.0, cr = ur, ci = ui;
+      for (int nn = m; nn <= order; ++nn) {
+        if (nn > m) {
+          const double inv = 1.0 / ((double)(nn + m) * (double)(nn - m));
+          const double a = (2 * nn - 1) * tz;
+          const double nr = (a * cr - r2 * pr) * inv, ni = (a * ci - r2 * pi) * inv;
+          pr = cr;
+          pi = ci;
+          cr = nr;
+          ci = ni;
+        }
+        su[2 * tree_idx(nn, m)] = cr;
+        su[2 * tree_idx(nn, m) + 1] = ci;
+      }
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
+      if (lane + h * kWave >= nm) continue;
+      for (int k = 0; k <= tn[h]; ++k) {
+        for (int l = -k; l <= k; ++l) {
+          const int nn = tn[h] - k, mm = tm[h] - l;
+          if (mm > nn || mm < -nn) continue;
+          double ar, ai, br, bi;
+          tree_get(su, k, l, ar, ai);
+          tree_get(smc, nn, mm, br, bi);
+          accr[h] += ar * br - ai * bi;
+          acci[h] += ar * bi + ai * br;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + h * kWave;
+    if (k >= nm) continue;
+    mom64[(long)g * kTreeMomStride + 2 * k] = accr[h];
+    mom64[(long)g * kTreeMomStride + 2 * k + 1] = acci[h];
+    mom32[(long)g * kTreeMomStride + 2 * k] = (float)accr[h];
+    mom32[(long)g * kTreeMomStride + 2 * k + 1] = (float)acci[h];
+  }
+}
+
+// Potential and field (-grad) at X (relative to the node centre) of the
+// moments M (re, im of (n, m), m <= n <= P), FP32.  The irregular
+// harmonics T_n^m, n <= P + 1, are generated column by column and used at
+// once: T_n^m feeds the potential through M_n^m, d/dz through M_{n-1}^m,
+// and (d/dx + i d/dy) through M_{n-1}^{m-1} and M_{n-1}^{m+1}; the terms
+// of m >= 1 count twice in the potential and in d/dz (the conjugate
+// columns -m), so column 0 runs on its own.  The loops stay rolled: the
+// moments then come in a few at a time through scalar loads (fully
+// unrolled, the compiler would hold all of them at once).
+template <int P>
+__device__ __forceinline__ void tree_eval(const float* __restrict__ M, float X, float Y, float Z, float& phi,
+                                          float& fx, float& fy, float& fz) {
+  const float r2 = X * X + Y * Y + Z * Z;
+  const float ri = rsq(r2);
+  const float ri2 = ri * ri;
+  const float wr = X * ri2, wi = Y * ri2;
+  const float zr = Z * ri2;
+  float phi0 = 0.f, phi1 = 0.f, dz0 = 0.f, dz1 = 0.f, Wr = 0.f, Wi = 0.f;
+  // column m = 0: T_n^0 is real
+  {
+    float p = 0.f, t = ri;
+#pragma unroll 1
+    for (int n = 0; n <= P + 1; ++n) {
+      if (n > 0) {
+        const float a = (float)(2 * n - 1) * zr;
+        const float b = (float)((n - 1) * (n - 1)) * ri2;
+        const float nt = a * t - b * p;
+        p = t;
+        t = nt;
+      }
+      if (n <= P) phi0 = fmaf(M[n * (n + 1)], t, phi0);
+      if (n >= 1) {
+        const float* __restrict__ prev = M + (n - 1) * n;  // (n - 1, 0)
+        dz0 = fmaf(prev[0], t, dz0);
+        if (n >= 2) {
+          // + M_{n-1}^1 conj(T_n^0)
+          Wr = fmaf(prev[2], t, Wr);
+          Wi = fmaf(prev[3], t, Wi);
+        }
+      }
+    }
+  }
+  float sr = ri, si = 0.f;
+#pragma unroll 1
+  for (int m = 1; m <= P + 1; ++m) {
+    {
+      const float c = (float)(2 * m - 1);
+      const float nr = c * (wr * sr - wi * si), ni = c * (wr * si + wi * sr);
+      sr = nr;
+      si = ni;
+    }
+    float pr = 0.f, pi = 0.f, tr = sr, ti = si;
+#pragma unroll 1
+    for (int n = m; n <= P + 1; ++n) {
+      if (n > m) {
+        const float a = (float)(2 * n - 1) * zr;
+        const float b = (float)((n - 1) * (n - 1) - m * m) * ri2;
+        const float nr = a * tr - b * pr, ni = a * ti - b * pi;
+        pr = tr;
+        pi = ti;
+        tr = nr;
+        ti = ni;
+      }
+      if (n <= P) {
+        const float* __restrict__ row = M + n * (n + 1) + 2 * m;  // (n, m)
+        phi1 = fmaf(row[0], tr, phi1);
+        phi1 = fmaf(row[1], ti, phi1);
+      }
+      const float* __restrict__ prev = M + (n - 1) * n + 2 * m;  // (n - 1, m)
+      if (n - 1 >= m) {
+        dz1 = fmaf(prev[0], tr, dz1);
+        dz1 = fmaf(prev[1], ti, dz1);
+      }
+      // - conj(M_{n-1}^{m-1}) T_n^m
+      Wr = fmaf(-prev[-2], tr, Wr);
+      Wr = fmaf(-prev[-1], ti, Wr);
+      Wi = fmaf(-prev[-2], ti, Wi);
+      Wi = fmaf(prev[-1], tr, Wi);
+      if (m + 1 <= n - 1) {
+        // + M_{n-1}^{m+1} conj(T_n^m)
+        Wr = fmaf(prev[2], tr, Wr);
+        Wr = fmaf(prev[3], ti, Wr);
+        Wi = fmaf(prev[3], tr, Wi);
+        Wi = fmaf(-prev[2], ti, Wi);
+      }
+    }
+  }
+  phi = phi0 + 2.f * phi1;
+  fx = -Wr;
+  fy = -Wi;
+  fz = dz0 + 2.f * dz1;  // -d/dz phi
+}
+
+// Far sums of the particles by the treecode: wave b takes target group
+// (= tile) b % ngroups and c = b / ngroups, that is image entry
+// c / ps.split and share c % ps.split.  Every wave walks the image's tree
+// depth-first (no stack: the next node follows from the level counts);
+// the work items met on the way (tiles summed directly, nodes taken as
+// multipoles) are dealt round-robin to the ps.split waves of the (group,
+// image), so that the heavy central images are shared when there are few
+// groups.  The wave writes slot c.  Tiles follow the far kernel's rules (near
+// tiles skipped, each target's own image dropped in its own tile), and a
+// multipole node that holds the group's own tile under a shifted image has
+// those own images taken out again, so that finalize adds every own image
+// exactly once in FP64.
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_PER_EU))) void k_tree_far(
+    const double4* __restrict__ tgt, PartSched ps, const Desc* __restrict__ desc, int ntiles,
+    const double4* __restrict__ tile_c, const float4* __restrict__ tile_h, const float4* __restrict__ src,
+    const StepParams* __restrict__ sp, TreeLevels tl, const double4* __restrict__ node_c,
+    const float* __restrict__ mom, double theta, float* __restrict__ part, long comp_stride, long slot_stride) {
+  const int c = blockIdx.x / ps.ngroups;
+  const int gi = blockIdx.x - c * ps.ngroups;
+  const int split = ps.split;
+  const int img = c / split;
+  int tskip = c - img * split;  // work items to pass over before this wave's next one
+  const int lane = threadIdx.x;
+  const int first = gi * kGroup;
+  const int count = min(kGroup, ps.n - first);
+  const bool valid = lane < count;
+  const double4 tp = tgt[first + (valid ? lane : 0)];
+  const double mnx = wave_min(valid ? tp.x : INFINITY), mxx = wave_max(valid ? tp.x : -INFINITY);
+  const double mny = wave_min(valid ? tp.y : INFINITY), mxy = wave_max(valid ? tp.y : -INFINITY);
+  const double mnz = wave_min(valid ? tp.z : INFINITY), mxz = wave_max(valid ? tp.z : -INFINITY);
+  // the group box: the same in every lane after the wave reductions
+  const double cgx = uniform_d(0.5 * (mnx + mxx)), cgy = uniform_d(0.5 * (mny + mxy)),
+               cgz = uniform_d(0.5 * (mnz + mxz));
+  const double hgx = uniform_d(0.5 * (mxx - mnx)), hgy = uniform_d(0.5 * (mxy - mny)),
+               hgz = uniform_d(0.5 * (mxz - mnz));
+  const double rt = sqrt(hgx * hgx + hgy * hgy + hgz * hgz);
+  const float ox = (float)(tp.x - cgx), oy = (float)(tp.y - cgy), oz = (float)(tp.z - cgz);
+  const double3 hbox = sp->hbox;
+  const double rc2 = sp->rc2;
+  const Desc ds = desc[img];
+  const bool identity = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0;
+  const bool img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
+                               __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
+  const int tself = first + lane;  // sorted index of this lane's target
+  float ph = 0.f, pl = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+  auto add = [&](float p, float gx, float gy, float gz) {
+    float s, e;
+    two_sum(ph, p, s, e);
+    ph = s;
+    pl += e;
+    ex += gx;
+    ey += gy;
+    ez += gz;
+  };
+  // node acceptance without square roots: |dl|^2 > ((r + rt) / theta)^2
+  // (the opening criterion) and |dl| > r + rt + rc (every source-target
+  // distance above the close-pair radius, so no tile of the node belongs
+  // to the near pass)
+  const double rc = sqrt(rc2);
+  const double ith2 = 1.0 / (theta * theta);
+  const int top = tl.nlev - 1;
+  int l = top, i = 0;
+  int far_lev = kTreeMaxLev;  // an opened ancestor at this level is beyond rc of the group: no near tile below
+  for (;;) {
+    bool open = false;
+    if (l == 0) {
+      const int tile = i;
+      bool item = true;
+      if (!img_far && far_lev == kTreeMaxLev) {
+        const double4 cs = tile_c[tile];
+        const float4 hs = tile_h[tile];
+        item = gap2_of(__dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
+                       shifted_dz(ds, cs.z, cgz), __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+                       __dadd_rn(hgz, (double)hs.z)) >= rc2;  // near tiles: summed by the near pass
+      }
+      bool mine = false;
+      if (item) {
+        mine = tskip == 0;
+        tskip = mine ? split - 1 : tskip - 1;
+      }
+      if (mine) {
+        const double4 cs = tile_c[tile];
+        const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+        const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+        const double dlz = shifted_dz(ds, cs.z, cgz);
+        const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
+        const float4* __restrict__ s = src + (long)tile * kTile;
+        float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
+        if (tile == gi) {
+          // own tile (under any image): drop each target's own image,
+          // which finalize sums in FP64
+          for (int k = 0; k < kTile; ++k) {
+            const float4 v = s[k];
+            const bool self = tile * kTile + k == tself;
+            const float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
+            const float r2 = self ? 1.f : dx * dx + dy * dy + dz * dz;
+            const float ri = rsq(r2);
+            const float a = (self ? 0.f : v.w) * ri;
+            pp += a;
+            const float b = a * (ri * ri);
+            qx += b * dx;
+            qy += b * dy;
+            qz += b * dz;
+          }
+        } else {
+#pragma unroll HSMA_FAR_UNROLL
+          for (int k = 0; k < kTile; ++k) {
+            const float4 v = s[k];
+            const float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float ri = rsq(r2);
+            const float a = v.w * ri;
+            pp += a;
+            const float b = a * (ri * ri);
+            qx += b * dx;
+            qy += b * dy;
+            qz += b * dz;
+          }
+        }
+        add(pp, qx, qy, qz);
+      }
+    } else {
+      const int g = tl.off[l] + i;
+      const double4 nc = node_c[g];
+      const double dlx = __dsub_rn(__dadd_rn(nc.x, ds.sx), cgx);
+      const double dly = __dsub_rn(__dadd_rn(nc.y, ds.sy), cgy);
+      const double dlz = __dsub_rn(__dadd_rn(nc.z, ds.sz), cgz);
+      const double d2 = dlx * dlx + dly * dly + dlz * dlz;
+      const double rr = nc.w + rt;
+      const double far_r = (rr + rc) * (1.0 + 1e-12);  // margin over the rounding of the box tests
+      const bool beyond_rc = d2 > far_r * far_r;
+      if (beyond_rc && d2 > rr * rr * ith2) {
+        const bool mine = tskip == 0;
+        tskip = mine ? split - 1 : tskip - 1;
+        if (mine) {
+          float p, gx, gy, gz;
+          tree_eval<P>(mom + (long)g * kTreeMomStride, ox - (float)dlx, oy - (float)dly, oz - (float)dlz, p, gx, gy,
+                       gz);
+          if (!identity && (gi >> (3 * l)) == i && valid) {
+            // this node holds the target's own image at x + s: take it out
+            const double sx = ds.sx, sy = ds.sy, sz = ds.sz;
+            const double si = 1.0 / sqrt(sx * sx + sy * sy + sz * sz);
+            const double qs = tp.w * si;
+            p -= (float)qs;
+            gx += (float)(qs * si * si * sx);
+            gy += (float)(qs * si * si * sy);
+            gz += (float)(qs * si * si * sz);
+          }
+          add(p, gx, gy, gz);
+        }
+      } else {
+        open = true;
+        if (beyond_rc && far_lev == kTreeMaxLev) far_lev = l;
+      }
+    }
+    if (open) {
+      --l;
+      i *= 8;
+      continue;
+    }
+    // next node in depth-first order: the next sibling, else climb
+    while (l < top && ((i & 7) == 7 || i + 1 >= tl.cnt[l])) {
+      i >>= 3;
+      ++l;
+    }
+    if (l >= far_lev) far_lev = kTreeMaxLev;  // left (or finished) the far subtree
+    if (l >= top) break;
+    ++i;
+  }
+  if (valid) {
+    const long o = (long)c * slot_stride + first + lane;
+    part[o] = ph;
+    part[o + comp_stride] = pl;
+    part[o + 2 * comp_stride] = ex;
+    part[o + 3 * comp_stride] = ey;
+    part[o + 4 * comp_stride] = ez;
+  }
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kGroup * kFinParts) void k_reduce_check(const Group* __restrict__ groups,
                                                               const CheckSched* __restrict__ csched, int gbase,
@@ -1361,7 +1875,8 @@ hsma_status DevicePlan::init(std::string& err) {
 
 void DevicePlan::free_arena() {
   void* ps[] = {d_key[0], d_key[1], d_val[0], d_val[1], d_hist, d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
-                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched, d_cull, d_clist, d_ccount};
+                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched, d_cull, d_clist, d_ccount,
+                d_tnode, d_tbox, d_tmom64, d_tmom32};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   d_key[0] = d_key[1] = nullptr;
@@ -1379,6 +1894,9 @@ void DevicePlan::free_arena() {
   d_cull = nullptr;
   d_clist = nullptr;
   d_ccount = nullptr;
+  d_tnode = d_tbox = nullptr;
+  d_tmom64 = nullptr;
+  d_tmom32 = nullptr;
   if (stage_ev) (void)hipEventSynchronize(stage_ev);  // an upload may still read the staging
   if (h_stage) (void)hipHostFree(h_stage);
   h_stage = nullptr;
@@ -1412,9 +1930,10 @@ DevicePlan::~DevicePlan() {
 // Particle schedule for n particles: chunks sized so that a launch has
 // about `target` waves (and at least 2 tiles per chunk: small systems get
 // many short waves rather than a few long ones).
-static PartSched part_schedule(int64_t n, int ndesc, int target) {
-  PartSched ps;
+static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree) {
+  PartSched ps{};
   ps.n = (int)n;
+  ps.split = 1;
   ps.ngroups = (int)((n + kGroup - 1) / kGroup);
   const int ntiles = (int)((n + kTile - 1) / kTile);
   ps.ndesc = ndesc;
@@ -1426,6 +1945,14 @@ static PartSched part_schedule(int64_t n, int ndesc, int target) {
   want = std::min<long long>(want, cap4 * ps.ngroups >= 4096 ? cap4 : std::max<long long>(1, ps.F / 2));
   ps.chunk = (int)((ps.F + want - 1) / want);
   ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
+  if (tree) {
+    // treecode: `split` waves per (image entry, group), each on a share of
+    // one image, so that the launch has about kTreeWaves waves
+    const long long base = (long long)ndesc * ps.ngroups;
+    ps.split = (int)std::min<long long>(kTreeMaxSplit, std::max<long long>(1, (kTreeWaves + base - 1) / base));
+    ps.chunk = ntiles;
+    ps.nch = ndesc * ps.split;
+  }
   // near pass: up to kMaxNearSplit waves per group, so that the launch has
   // about kNearWaves waves, at most one per near candidate (image entry,
   // tile)
@@ -1468,10 +1995,13 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
   // far slots <= part_target + ngroups; near slots <= min(kMaxNearSplit
   // ngroups, kNearWaves + ngroups)
   const size_t nearb = std::min<size_t>((size_t)kMaxNearSplit * ngroups, (size_t)kNearWaves + ngroups);
-  part_bytes = rb * 5 * (size_t)kGroup * ((size_t)part_target + ngroups + nearb + sph + 1);
+  // far slots: treecode one per image entry and group
+  const size_t farb = std::max<size_t>((size_t)part_target + ngroups,
+                                       host.prm.near_rule == 2 ? kTreeWaves + host.desc_particles.size() * ngroups : 0);
+  part_bytes = rb * 5 * (size_t)kGroup * (farb + nearb + sph + 1);
   const size_t rbc = cpart_elem();
   cpart_bytes = rbc * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
-  nwork = (size_t)part_target + ngroups + nearb + 2;
+  nwork = farb + nearb + 2;
   ncwork = (size_t)check_target_max + 2 * ncg + 2;
 }
 
@@ -1514,6 +2044,14 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
     HIPCHK(hipMalloc((void**)&d_clist, sizeof(unsigned) * ncull));
     HIPCHK(hipMalloc((void**)&d_ccount, sizeof(int)));
   }
+  // tree nodes: the level counts only grow with the tile count
+  const size_t tnodes = host.prm.near_rule == 2 ? (size_t)tree_levels((int)cnt).nodes : 0;
+  if (tnodes) {
+    HIPCHK(hipMalloc((void**)&d_tnode, sizeof(double4) * tnodes));
+    HIPCHK(hipMalloc((void**)&d_tbox, sizeof(double4) * 2 * tnodes));
+    HIPCHK(hipMalloc((void**)&d_tmom64, sizeof(double) * kTreeMomStride * tnodes));
+    HIPCHK(hipMalloc((void**)&d_tmom32, sizeof(float) * kTreeMomStride * tnodes));
+  }
   HIPCHK(hipHostMalloc(&h_stage, sizeof(CheckSched) * ncg + 64));
   if (!stage_ev) HIPCHK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
   stage_bytes = sizeof(CheckSched) * ncg + 64;
@@ -1526,7 +2064,8 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
                 sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
                 sizeof(double) * 3 * ((cn + 255) / 256) + sizeof(double) * ((cn + kWave - 1) / kWave) + part_bytes +
                 cpart_bytes + sizeof(CheckSched) * ncg +
-                (sizeof(unsigned long long) + sizeof(unsigned)) * ncull;
+                (sizeof(unsigned long long) + sizeof(unsigned)) * ncull +
+                (3 * sizeof(double4) + kTreeMomStride * (sizeof(double) + sizeof(float))) * tnodes;
   cur_n = -1;
   return HSMA_OK;
 }
@@ -1537,7 +2076,7 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   hsma_status s = reserve(n, err);
   if (s != HSMA_OK) return s;
   const int ntiles = (int)((n + kTile - 1) / kTile);
-  const PartSched ps = part_schedule(n, (int)host.desc_particles.size(), part_target);
+  const PartSched ps = part_schedule(n, (int)host.desc_particles.size(), part_target, host.prm.near_rule == 2);
   // check work: about check_pairs_per_item pairs per wave, enough waves to
   // fill the chip when there is that much work
   long long cpairs = 0;
@@ -1567,6 +2106,7 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   }
   cur_n = n;
   ntiles_ = ntiles;
+  tree_ = tree_levels(ntiles);
   ngroups_ = ps.ngroups;
   psched_ = ps;
   ncwork_ = ncfar;
@@ -1579,6 +2119,36 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
 }
 
 // Event pair (stage, edge) of the current timed call, created on demand.
+// Treecode far sums (near rule 2, FP32): the node boxes and moments level
+// by level, then one wave per (image entry, target group).
+hsma_status DevicePlan::launch_tree(hipStream_t st, int n, long comp, long slot, std::string& err) {
+  const int P = host.prm.tree_order;
+  const TreeLevels tl = tree_;
+  if (tl.nlev >= 2)
+    hipLaunchKernelGGL(k_tree_p2m, dim3(tl.cnt[1]), dim3(512), 0, st, n, ntiles_, P, tl, (const double4*)d_pos64,
+                       (const double4*)d_tile_c, (const float4*)d_tile_h, d_tnode, d_tbox, d_tmom64, d_tmom32);
+  for (int l = 2; l < tl.nlev; ++l)
+    hipLaunchKernelGGL(k_tree_m2m, dim3(tl.cnt[l]), dim3(64), 0, st, l, P, tl, d_tnode, d_tbox, d_tmom64, d_tmom32);
+#define HSMA_TREE_FAR(PP)                                                                                          \
+  hipLaunchKernelGGL(k_tree_far<PP>, dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
+                     psched_, (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, \
+                     (const float4*)d_src32, (const StepParams*)d_sp, tl, (const double4*)d_tnode,               \
+                     (const float*)d_tmom32, host.prm.tree_theta, (float*)d_part, comp, slot)
+  switch (P) {
+    case 4: HSMA_TREE_FAR(4); break;
+    case 6: HSMA_TREE_FAR(6); break;
+    case 8: HSMA_TREE_FAR(8); break;
+    case 10: HSMA_TREE_FAR(10); break;
+    case 12: HSMA_TREE_FAR(12); break;
+    default:
+      err = "tree order must be 4, 6, 8, 10 or 12";
+      return HSMA_ERR_INVALID_ARG;
+  }
+#undef HSMA_TREE_FAR
+  HIPCHK(hipGetLastError());
+  return HSMA_OK;
+}
+
 hsma_status DevicePlan::record(hipStream_t st, int stage, int edge, std::string& err) {
   if (!timing || timed_calls >= kMaxTimedCalls) return HSMA_OK;
   const size_t idx = ((size_t)timed_calls * kStages + stage) * 2 + edge;
@@ -1674,11 +2244,15 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
 #define HSMA_PARTICLES_NEAR(Real, S, SRC, NST)                                                                         \
   do {                                                                                                              \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
-    hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,           \
-                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,      \
-                       (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
-                       slot);                                                                                       \
+    if (host.prm.near_rule == 2) {                                                                                  \
+      if ((s = launch_tree(st, n, comp, slot, err)) != HSMA_OK) return s;                                           \
+    } else {                                                                                                        \
+      hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,         \
+                         (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,    \
+                         (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,      \
+                         (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp, \
+                         slot);                                                                                     \
+    }                                                                                                               \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
     hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, (NST),       \
                        (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,      \

@@ -373,9 +373,16 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     return HSMA_ERR_INVALID_ARG;
   }
   if (prm.p < 1 || prm.p > 24 || prm.K < 1 || prm.F < 4 || prm.F > 1000000 ||
-      (prm.surface_rule != 0 && prm.surface_rule != 1) || (prm.near_rule != 0 && prm.near_rule != 1) ||
+      (prm.surface_rule != 0 && prm.surface_rule != 1) || prm.near_rule < 0 || prm.near_rule > 2 ||
       (prm.precision != HSMA_FP64 && prm.precision != HSMA_FP32C) || !(prm.lambda > 0)) {
-    msg = "invalid method parameter (p in 1..24, K >= 1, F >= 4, surface/near rule 0/1, precision, lambda > 0)";
+    msg = "invalid method parameter (p in 1..24, K >= 1, F >= 4, surface rule 0/1, near rule 0/1/2, precision, "
+          "lambda > 0)";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  if (prm.near_rule == 2 &&
+      (slab || prm.precision != HSMA_FP32C || prm.tree_order < 4 || prm.tree_order > 12 || prm.tree_order % 2 != 0 ||
+       !(prm.tree_theta > 0 && prm.tree_theta <= 0.75))) {
+    msg = "near rule 2 (treecode): 3D, FP32C, tree order 4/6/8/10/12, 0 < tree theta <= 0.75";
     return HSMA_ERR_INVALID_ARG;
   }
   if (prm.surface_rule == 1) {

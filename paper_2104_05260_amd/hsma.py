@@ -39,6 +39,7 @@ class _CParams(ctypes.Structure):
         ("surface_rule", ctypes.c_int), ("near_rule", ctypes.c_int), ("M", ctypes.c_int),
         ("gamma_up", ctypes.c_double),
         ("gamma_low", ctypes.c_double), ("nz", ctypes.c_int), ("coulomb_k", ctypes.c_double),
+        ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double),
     ]
 
 
@@ -87,6 +88,8 @@ class Params:
     gamma_low: float = 0.0
     nz: int = 80
     coulomb_k: float = 1.0
+    tree_order: int = 8
+    tree_theta: float = 0.5
 
     @staticmethod
     def from_workload(w, precision: Optional[int] = None) -> "Params":
@@ -97,7 +100,7 @@ class Params:
     def _c(self) -> _CParams:
         return _CParams(self.geometry, self.precision, self.lam, self.p, self.K, self.F, self.Fw,
                         self.surface_rule, self.near_rule, self.M, self.gamma_up, self.gamma_low, self.nz,
-                        self.coulomb_k)
+                        self.coulomb_k, self.tree_order, self.tree_theta)
 
 
 _lib = None

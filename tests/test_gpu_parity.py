@@ -31,11 +31,14 @@ def run_gpu(params, pos, q, lo, L):
 
 
 def oracle_run(params, pos, q, lo, L, targets=None):
+    # near rule 2 (treecode) approximates the 27-cell sums of rule 0: the
+    # oracle computes those exactly
+    rule = 0 if params.near_rule == 2 else params.near_rule
     if params.geometry == 0:
         return ohsma.hsma3d(pos, q, lo, L, params.p, params.K, params.F, params.lam, params.Fw,
-                            params.surface_rule, targets, params.near_rule)
+                            params.surface_rule, targets, rule)
     return ohsma.hsma2d(pos, q, lo, L, params.p, params.K, params.F, params.lam, params.M, params.gamma_up,
-                        params.gamma_low, params.nz, params.Fw, params.surface_rule, targets, params.near_rule)
+                        params.gamma_low, params.nz, params.Fw, params.surface_rule, targets, rule)
 
 
 # FP64 path: agreement to 1e-10 relative (energy, potentials, forces).
@@ -57,7 +60,14 @@ def fp32_energy_bar(E, S):
     return 1e-6 * abs(E) + FP32_E_FLOOR * S
 
 
-def check(params, pos, q, lo, L, fp32=False, label=""):
+# Treecode (near rule 2) against the oracle's exact 27-cell sums: the FP32
+# bars for energy and force, and 5e-5 on the largest potential error (the
+# truncation of the multipole expansions; measured up to 1.7e-5 at order
+# 8, theta 0.5 on the 50,000-ion system).
+TREE_POT = 5e-5
+
+
+def check(params, pos, q, lo, L, fp32=False, label="", pot_bar=1e-5):
     note(f"[parity] {label} n={len(q)} geometry={params.geometry} precision={params.precision}")
     e, pot, f = run_gpu(params, pos, q, lo, L)
     r = oracle_run(params, pos, q, lo, L)
@@ -71,7 +81,7 @@ def check(params, pos, q, lo, L, fp32=False, label=""):
         S = 0.5 * np.abs(q * r.potential).sum()
         bar = fp32_energy_bar(r.energy, S)
         note(f"   energy scale S {S:.6g}; |dE| {abs(e - r.energy):.3g}, bar {bar:.3g}; |dE|/S {abs(e - r.energy) / S:.2e}")
-        assert abs(e - r.energy) <= bar and df <= 1e-5 and dp <= 1e-5
+        assert abs(e - r.energy) <= bar and df <= 1e-5 and dp <= pot_bar
     else:
         assert de <= TOL64 and dp <= TOL64 and dfmax <= TOL64 * 10 and df <= TOL64
     return e, pot, f, r
@@ -409,6 +419,65 @@ def test_step_graph_replays_match_eager(near_rule):
             assert np.array_equal(f.cpu().numpy(), f_ref), it
             del junk
         assert graphed.device_status() == 0
+
+
+# ---- treecode (near_rule=2): far nodes of the 27-cell sums through their
+# multipole expansions, the rest direct.  Sizes cover one tile (no tree
+# level), a partial level-1 node, and several levels with ragged ends.
+@pytest.mark.parametrize("n", [2, 130, 1000, 4098])
+def test_tree_ragged_3d(n):
+    L = 3.0 * (n / 2.0) ** (1 / 3) + 2.0
+    pos, q, lo, box = workloads.small_system(n, (L, L * 1.1, L * 0.9), 400 + n)
+    lo = np.array([0.5, -2.0, 1.0])
+    pos = pos + lo
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.4, near_rule=2)
+    check(params, pos, q, lo, box, fp32=True, label=f"3d treecode n={n}", pot_bar=TREE_POT)
+
+
+@pytest.mark.parametrize("order,theta", [(4, 0.25), (6, 0.4), (10, 0.5), (12, 0.35)])
+def test_tree_orders(order, theta):
+    """Every compiled expansion order; the error falls with the order and
+    the opening parameter (order 12, theta 0.35 is within the FP32 floor)."""
+    pos, q, lo, L = workloads.small_system(3000, (25.0, 25.0, 25.0), 9)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, near_rule=2, tree_order=order, tree_theta=theta)
+    e, pot, f, r = check(params, pos, q, lo, L, fp32=True, label=f"treecode order {order} theta {theta}",
+                         pot_bar=TREE_POT)
+    if order == 12:
+        assert rel_rms(f, r.force) <= 1e-6
+
+
+def test_tree_deterministic():
+    pos, q, lo, L = workloads.small_system(3000, (25.0, 25.0, 25.0), 10)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, near_rule=2)
+    with hs.Plan(params, lo, L) as plan:
+        a = plan.compute(pos, q)
+        b = plan.compute(pos, q)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_c2_treecode_sampled():
+    """The 50,000-ion system with the treecode, in the configuration the
+    benchmark times for it: against the oracle at 256 sampled particles
+    and against the FP64 27-cell GPU path everywhere."""
+    w = workloads.C2
+    pos, q, lo, L = workloads.make_system(w)
+    sample = np.random.default_rng(7).choice(w.n, 256, replace=False)
+    params = hs.Params.from_workload(w)
+    params.near_rule = 2
+    note("[parity] C2 treecode: oracle (sampled)")
+    r = _sampled_oracle(w, params, pos, q, lo, L, sample)
+    e, pot, f = run_gpu(params, pos, q, lo, L)
+    dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
+    df = rel_rms(f[sample], r.force)
+    note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}")
+    assert dp < TREE_POT and df < 1e-5
+    e64, pot64, f64 = run_gpu(hs.Params.from_workload(w, precision=0), pos, q, lo, L)
+    S = 0.5 * np.abs(q * pot64).sum()
+    note(f"   energy tree {e:.12g} fp64 {e64:.12g} rel {abs(e - e64) / abs(e64):.2e}; dE/S {abs(e - e64) / S:.2e}; "
+         f"force rms rel {rel_rms(f, f64):.2e}")
+    assert abs(e - e64) <= fp32_energy_bar(e64, S)
+    assert rel_rms(f, f64) <= 1e-5
+    assert np.abs(pot - pot64).max() <= TREE_POT * np.abs(pot64).max()
 
 
 @pytest.mark.parametrize("name", ["c2_hsma3d_n50000_fp32c", "c3_hsma2d_n20000_slab"])
