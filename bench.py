@@ -185,6 +185,55 @@ def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells,
     return out
 
 
+def tree_rule_bench(hs, workloads, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells, e64, f64_cells,
+                    steps=10):
+    """The 27-cell sums at the particles by the treecode (near_rule=2,
+    multipole order 8, opening parameter 0.5), FP32 compensated, on the
+    same system: time, and error against the FP64 27-cell result; then the
+    999,999-ion system (timing only: its 27-cell step takes seconds)."""
+    import numpy as np
+    import torch
+    params = hs.Params.from_workload(w, precision=hs.FP32C)
+    params.near_rule = 2
+
+    def timed(pp, xx, qv, ee, pt, ff, k):
+        plan = hs.Plan(pp, lo_, L_)
+        for _ in range(2):
+            plan.compute_device(xx, qv, ee, pt, ff)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(k):
+            plan.compute_device(xx, qv, ee, pt, ff)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        plan.close()
+        return ev0.elapsed_time(ev1) / k
+
+    lo_, L_ = lo, L
+    ms = timed(params, x, qq, en, pot, f, steps)
+    out = {"near_rule": 2, "tree_order": params.tree_order, "tree_theta": params.tree_theta,
+           "precision": "fp32-compensated", "ms_per_step": ms, "particle_steps_per_s": w.n / (ms * 1e-3),
+           "speedup_vs_27_cells": ms_cells / ms}
+    if f64_cells is not None:
+        fs = f.cpu().numpy()
+        out["rel_energy_err_vs_27_cells_fp64"] = abs(en.item() - e64) / abs(e64)
+        out["rel_rms_force_err_vs_27_cells_fp64"] = float(np.sqrt(((fs - f64_cells) ** 2).sum() / (f64_cells ** 2).sum()))
+    w5 = workloads.C5
+    pos5, q5, lo_, L_ = workloads.make_system(w5)
+    dev = x.device
+    x5 = torch.tensor(pos5, device=dev)
+    q5t = torch.tensor(q5, device=dev)
+    pot5 = torch.zeros(w5.n, dtype=torch.float64, device=dev)
+    f5 = torch.zeros((w5.n, 3), dtype=torch.float64, device=dev)
+    p5 = hs.Params.from_workload(w5, precision=hs.FP32C)
+    p5.near_rule = 2
+    ms5 = timed(p5, x5, q5t, en, pot5, f5, 5)
+    out["large"] = {"workload": w5.name, "n": w5.n, "ms_per_step": ms5, "particle_steps_per_s": w5.n / (ms5 * 1e-3)}
+    del x5, q5t, pot5, f5
+    return out
+
+
 def slab_near_sets_bench(hs, workloads, steps=5):
     """The 20,000-ion slab with both near sets: the 189-entry stencil at the
     workload's p = 10 and the sphere near set at p = 14 (K = 450, F = 1152),
@@ -238,6 +287,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix measurement")
     ap.add_argument("--no-sphere-rule", action="store_true",
                     help="skip the sphere-near-set measurement (near_rule=1 at matched accuracy)")
+    ap.add_argument("--no-tree", action="store_true", help="skip the treecode measurement (near_rule=2)")
     ap.add_argument("--workload", default="c2_hsma3d_n50000_fp32c",
                     help="configuration to time (default: the 50,000-ion benchmark system)")
     ap.add_argument("--near-rule", type=int, default=None, help="override the near set (0 cells, 1 sphere)")
@@ -273,7 +323,7 @@ def main():
         w = dataclasses.replace(w, **over)
     if not default_run:
         # a profiling run of another configuration: the timed loop only
-        args.no_fp64 = args.no_serving = args.no_sphere_rule = True
+        args.no_fp64 = args.no_serving = args.no_sphere_rule = args.no_tree = True
     pos, q, lo, L = workloads.make_system(w)
     dev = torch.device("cuda:0")
     x = torch.tensor(pos, device=dev)
@@ -380,6 +430,9 @@ def main():
         out["sphere_near_set"] = sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
                                                    None if args.no_fp64 else f64)
         out["sphere_near_set_slab"] = slab_near_sets_bench(hs, workloads)
+    if not args.no_tree:
+        out["tree_near_set"] = tree_rule_bench(hs, workloads, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
+                                               None if args.no_fp64 else e64, None if args.no_fp64 else f64)
     if not args.no_serving:
         out["serving"] = serving_bench(hs, workloads)
     if not args.no_cpu_baseline:

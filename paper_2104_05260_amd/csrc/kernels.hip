@@ -1063,6 +1063,7 @@ __global__ __launch_bounds__(512) void k_tree_p2m(int n, int ntiles, int order, 
                                                  float* __restrict__ mom32) {
   __shared__ double sbox[8][6];
   __shared__ double sc[3];
+  __shared__ double srad[8];
   __shared__ double sm[8][2 * kTreeMom];
   const int node = blockIdx.x;
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -1093,8 +1094,7 @@ __global__ __launch_bounds__(512) void k_tree_p2m(int n, int ntiles, int order, 
     }
     const double hx = 0.5 * (hi[0] - lo[0]), hy = 0.5 * (hi[1] - lo[1]), hz = 0.5 * (hi[2] - lo[2]);
     const int g = tl.off[1] + node;
-    node_c[g] = make_double4(sc[0], sc[1], sc[2], sqrt(hx * hx + hy * hy + hz * hz));
-    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], 0.0);
+    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], sqrt(hx * hx + hy * hy + hz * hz));
     node_box[2 * g + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
   }
   __syncthreads();
@@ -1108,6 +1108,9 @@ __global__ __launch_bounds__(512) void k_tree_p2m(int n, int ntiles, int order, 
     yz = p.z - sc[2];
   }
   const double r2 = yx * yx + yy * yy + yz * yz;
+  // radius of the node's particles about its centre (the opening test's r)
+  const double rw = wave_max(has && s < n ? sqrt(r2) : 0.0);
+  if (lane == 0) srad[w] = rw;
   double ur = 1.0, ui = 0.0;  // sectoral U_m^m
   for (int m = 0; m <= order; ++m) {
     if (m > 0) {
@@ -1137,6 +1140,11 @@ __global__ __launch_bounds__(512) void k_tree_p2m(int n, int ntiles, int order, 
   __syncthreads();
   const int nr2 = (order + 1) * (order + 2);
   const long g = (long)tl.off[1] + node;
+  if (threadIdx.x == 0) {
+    double r = srad[0];
+    for (int k = 1; k < 8; ++k) r = fmax(r, srad[k]);
+    node_c[g] = make_double4(sc[0], sc[1], sc[2], r);
+  }
   for (int k = threadIdx.x; k < nr2; k += blockDim.x) {
     double acc = 0.0;
     for (int ww = 0; ww < 8; ++ww) acc += sm[ww][k];
@@ -1157,10 +1165,13 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevel
   const int c0 = 8 * node, c1 = min(c0 + 8, tl.cnt[level - 1]);
   const int coff = tl.off[level - 1];
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (lane < c1 - c0) {
+  double4 cc4 = make_double4(0, 0, 0, 0);
+  const bool hasc = lane < c1 - c0;
+  if (hasc) {
     const double4 a = node_box[2 * (coff + c0 + lane)], b = node_box[2 * (coff + c0 + lane) + 1];
     lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
     hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+    cc4 = node_c[coff + c0 + lane];
   }
   double c[3], h[3];
   for (int d = 0; d < 3; ++d) {
@@ -1169,10 +1180,15 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevel
     c[d] = 0.5 * (lo[d] + hi[d]);
     h[d] = 0.5 * (hi[d] - lo[d]);
   }
+  // particle radius: within the box's half diagonal, and within each
+  // child's centre distance plus its radius; the smaller bound is kept
+  const double ex = cc4.x - c[0], ey = cc4.y - c[1], ez = cc4.z - c[2];
+  const double hd = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  const double rad = fmin(hd, wave_max(hasc ? sqrt(ex * ex + ey * ey + ez * ez) + cc4.w : 0.0));
   const int g = tl.off[level] + node;
   if (lane == 0) {
-    node_c[g] = make_double4(c[0], c[1], c[2], sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]));
-    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], 0.0);
+    node_c[g] = make_double4(c[0], c[1], c[2], rad);
+    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], hd);
     node_box[2 * g + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
   }
   const int nm = (order + 1) * (order + 2) / 2;
@@ -1352,7 +1368,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_P
     const double4* __restrict__ tgt, PartSched ps, const Desc* __restrict__ desc, int ntiles,
     const double4* __restrict__ tile_c, const float4* __restrict__ tile_h, const float4* __restrict__ src,
     const StepParams* __restrict__ sp, TreeLevels tl, const double4* __restrict__ node_c,
-    const float* __restrict__ mom, double theta, float* __restrict__ part, long comp_stride, long slot_stride) {
+    const double4* __restrict__ node_box, const float* __restrict__ mom, double theta, float* __restrict__ part,
+    long comp_stride, long slot_stride) {
   const int c = blockIdx.x / ps.ngroups;
   const int gi = blockIdx.x - c * ps.ngroups;
   const int split = ps.split;
@@ -1371,8 +1388,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_P
                cgz = uniform_d(0.5 * (mnz + mxz));
   const double hgx = uniform_d(0.5 * (mxx - mnx)), hgy = uniform_d(0.5 * (mxy - mny)),
                hgz = uniform_d(0.5 * (mxz - mnz));
+  // group radii: of its box (close-pair test), of its targets (opening test)
   const double rt = sqrt(hgx * hgx + hgy * hgy + hgz * hgz);
-  const float ox = (float)(tp.x - cgx), oy = (float)(tp.y - cgy), oz = (float)(tp.z - cgz);
+  const double ptx = tp.x - cgx, pty = tp.y - cgy, ptz = tp.z - cgz;
+  const double rtp = uniform_d(wave_max(valid ? sqrt(ptx * ptx + pty * pty + ptz * ptz) : 0.0));
+  const float ox = (float)ptx, oy = (float)pty, oz = (float)ptz;
   const double3 hbox = sp->hbox;
   const double rc2 = sp->rc2;
   const Desc ds = desc[img];
@@ -1464,9 +1484,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_P
       const double dly = __dsub_rn(__dadd_rn(nc.y, ds.sy), cgy);
       const double dlz = __dsub_rn(__dadd_rn(nc.z, ds.sz), cgz);
       const double d2 = dlx * dlx + dly * dly + dlz * dlz;
-      const double rr = nc.w + rt;
-      const double far_r = (rr + rc) * (1.0 + 1e-12);  // margin over the rounding of the box tests
+      const double far_r = (node_box[2 * g].w + rt + rc) * (1.0 + 1e-12);  // boxes; margin over rounding
       const bool beyond_rc = d2 > far_r * far_r;
+      const double rr = nc.w + rtp;  // particle radii
       if (beyond_rc && d2 > rr * rr * ith2) {
         const bool mine = tskip == 0;
         tskip = mine ? split - 1 : tskip - 1;
@@ -2133,7 +2153,7 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, int n, long comp, long slot,
   hipLaunchKernelGGL(k_tree_far<PP>, dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
                      psched_, (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, \
                      (const float4*)d_src32, (const StepParams*)d_sp, tl, (const double4*)d_tnode,               \
-                     (const float*)d_tmom32, host.prm.tree_theta, (float*)d_part, comp, slot)
+                     (const double4*)d_tbox, (const float*)d_tmom32, host.prm.tree_theta, (float*)d_part, comp, slot)
   switch (P) {
     case 4: HSMA_TREE_FAR(4); break;
     case 6: HSMA_TREE_FAR(6); break;

@@ -40,7 +40,7 @@ class Workload:
     Fw: int = 0                   # lattice generator for the surface rule (0 = auto)
     surface_rule: int = 0
     precision: int = 1            # 0 = fp64, 1 = fp32 compensated
-    near_rule: int = 0            # 0 = cell/layer stencil, 1 = images inside the sphere only
+    near_rule: int = 0            # 0 = cell/layer stencil, 1 = images inside the sphere only, 2 = stencil by treecode
 
 
 # The five systems.  Box lower corner is the origin; slab walls sit at z=0
