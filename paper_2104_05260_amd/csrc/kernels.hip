@@ -1351,23 +1351,28 @@ __device__ __forceinline__ void tree_eval(const float* __restrict__ M, float X, 
   fz = dz0 + 2.f * dz1;  // -d/dz phi
 }
 
-// Far sums of the particles by the treecode: wave b takes target group
-// (= tile) b % ngroups and c = b / ngroups, that is image entry
+// Near-set sums of the particles by the treecode: wave b takes target
+// group (= tile) b % ngroups and c = b / ngroups, that is image entry
 // c / ps.split and share c % ps.split.  Every wave walks the image's tree
 // depth-first (no stack: the next node follows from the level counts);
 // the work items met on the way (tiles summed directly, nodes taken as
 // multipoles) are dealt round-robin to the ps.split waves of the (group,
 // image), so that the heavy central images are shared when there are few
-// groups.  The wave writes slot c.  Tiles follow the far kernel's rules (near
+// groups.  The wave writes slot c.  Tiles within the close-pair radius are
+// summed here too (there is no separate near pass for this rule).  Tiles follow the far kernel's rules (near
 // tiles skipped, each target's own image dropped in its own tile), and a
 // multipole node that holds the group's own tile under a shifted image has
 // those own images taken out again, so that finalize adds every own image
 // exactly once in FP64.
+#ifndef HSMA_TREE_WAVES
+#define HSMA_TREE_WAVES 8
+#endif
 template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_PER_EU))) void k_tree_far(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WAVES))) void k_tree_far(
     const double4* __restrict__ tgt, PartSched ps, const Desc* __restrict__ desc, int ntiles,
     const double4* __restrict__ tile_c, const float4* __restrict__ tile_h, const float4* __restrict__ src,
-    const StepParams* __restrict__ sp, TreeLevels tl, const double4* __restrict__ node_c,
+    const double4* __restrict__ pos64, const StepParams* __restrict__ sp, TreeLevels tl,
+    const double4* __restrict__ node_c,
     const double4* __restrict__ node_box, const float* __restrict__ mom, double theta, float* __restrict__ part,
     long comp_stride, long slot_stride) {
   const int c = blockIdx.x / ps.ngroups;
@@ -1393,6 +1398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_P
   const double ptx = tp.x - cgx, pty = tp.y - cgy, ptz = tp.z - cgz;
   const double rtp = uniform_d(wave_max(valid ? sqrt(ptx * ptx + pty * pty + ptz * ptz) : 0.0));
   const float ox = (float)ptx, oy = (float)pty, oz = (float)ptz;
+  const double qt = tp.w;  // (the FP64 position is read again where a close pair needs it)
   const double3 hbox = sp->hbox;
   const double rc2 = sp->rc2;
   const Desc ds = desc[img];
@@ -1423,20 +1429,55 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_P
     bool open = false;
     if (l == 0) {
       const int tile = i;
-      bool item = true;
+      // a tile within the close-pair radius of the group (the far kernel's
+      // test) runs the checked loop: pairs closer than rc take their
+      // difference vector from the FP64 positions
+      bool near = false;
       if (!img_far && far_lev == kTreeMaxLev) {
         const double4 cs = tile_c[tile];
         const float4 hs = tile_h[tile];
-        item = gap2_of(__dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
+        near = gap2_of(__dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
                        shifted_dz(ds, cs.z, cgz), __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
-                       __dadd_rn(hgz, (double)hs.z)) >= rc2;  // near tiles: summed by the near pass
+                       __dadd_rn(hgz, (double)hs.z)) < rc2;
       }
-      bool mine = false;
-      if (item) {
-        mine = tskip == 0;
-        tskip = mine ? split - 1 : tskip - 1;
-      }
-      if (mine) {
+      const bool mine = tskip == 0;
+      tskip = mine ? split - 1 : tskip - 1;
+      if (mine && near) {
+        const double4 cs = tile_c[tile];
+        const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+        const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+        const double dlz = shifted_dz(ds, cs.z, cgz);
+        const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
+        const float4* __restrict__ s = src + (long)tile * kTile;
+        const double4 p64 = pos64[(long)tile * kTile + lane];
+        const double4 tq = tgt[first + (valid ? lane : 0)];
+        float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
+        for (int k = 0; k < kTile; ++k) {
+          const float4 v = s[k];
+          float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
+          float r2 = dx * dx + dy * dy + dz * dz;
+          float qv = v.w;
+          if (tile == gi && tile * kTile + k == tself) {
+            // the target itself or its own image: finalize sums the images
+            qv = 0.f;
+            r2 = 1.f;
+          } else if ((double)r2 < rc2) {
+            const double psx = readlane_d(p64.x, k), psy = readlane_d(p64.y, k), psz = readlane_d(p64.z, k);
+            dx = (float)(tq.x - (psx + ds.sx));
+            dy = (float)(tq.y - (psy + ds.sy));
+            dz = (float)(tq.z - (psz + ds.sz));
+            r2 = dx * dx + dy * dy + dz * dz;
+          }
+          const float ri = rsq(r2);
+          const float a = qv * ri;
+          pp += a;
+          const float b = a * (ri * ri);
+          qx += b * dx;
+          qy += b * dy;
+          qz += b * dz;
+        }
+        add(pp, qx, qy, qz);
+      } else if (mine) {
         const double4 cs = tile_c[tile];
         const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
         const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
@@ -1498,7 +1539,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_WAVES_P
             // this node holds the target's own image at x + s: take it out
             const double sx = ds.sx, sy = ds.sy, sz = ds.sz;
             const double si = 1.0 / sqrt(sx * sx + sy * sy + sz * sz);
-            const double qs = tp.w * si;
+            const double qs = qt * si;
             p -= (float)qs;
             gx += (float)(qs * si * si * sx);
             gy += (float)(qs * si * si * sy);
@@ -1973,6 +2014,10 @@ static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree) {
     ps.chunk = ntiles;
     ps.nch = ndesc * ps.split;
   }
+  if (tree) {
+    ps.nnear = 0;  // the treecode sums the near tiles itself
+    return ps;
+  }
   // near pass: up to kMaxNearSplit waves per group, so that the launch has
   // about kNearWaves waves, at most one per near candidate (image entry,
   // tile)
@@ -2152,7 +2197,8 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, int n, long comp, long slot,
 #define HSMA_TREE_FAR(PP)                                                                                          \
   hipLaunchKernelGGL(k_tree_far<PP>, dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
                      psched_, (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, \
-                     (const float4*)d_src32, (const StepParams*)d_sp, tl, (const double4*)d_tnode,               \
+                     (const float4*)d_src32, (const double4*)d_pos64, (const StepParams*)d_sp, tl,                \
+                     (const double4*)d_tnode,                                                                    \
                      (const double4*)d_tbox, (const float*)d_tmom32, host.prm.tree_theta, (float*)d_part, comp, slot)
   switch (P) {
     case 4: HSMA_TREE_FAR(4); break;
@@ -2274,11 +2320,12 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                          slot);                                                                                     \
     }                                                                                                               \
     if ((s = record(st, kStNear, 1, err)) != HSMA_OK) return s;                                                     \
-    hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, (NST),       \
-                       (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,      \
-                       (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,        \
-                       (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp,   \
-                       slot);                                                                                       \
+    if (psched_.nnear > 0)                                                                                          \
+      hipLaunchKernelGGL((k_pair<Real, true, true>), dim3(psched_.nnear * psched_.ngroups), dim3(64), 0, (NST),     \
+                         (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,    \
+                         (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,      \
+                         (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp, \
+                         slot);                                                                                     \
   } while (0)
 #define HSMA_PARTICLES_SPHERE(Real)                                                                                 \
   do {                                                                                                              \
