@@ -13,6 +13,7 @@ For profiling the other workloads the same timed loop runs on any named
 configuration, optionally with the sphere near set and other p, K, F:
 
   python bench.py --workload c3_hsma2d_n20000_slab [--near-rule 1 --p 14 --K 450 --F 1152]
+  python bench.py --workload c5_hsma3d_n999999_2to1 --near-rule 2   (treecode)
 
 Besides the throughput it reports the dominant kernel's roofline position
 (FP32 VALU bound; algorithmic 20 flop per near pair over its HIP-event
