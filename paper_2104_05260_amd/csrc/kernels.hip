@@ -1259,7 +1259,8 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevel
 }
 
 // Potential and field (-grad) at X (relative to the node centre) of the
-// moments M (re, im of (n, m), m <= n <= P), FP32.  The irregular
+// moments M (re, im of (n, m), m <= n <= P; P may be below the order the
+// moments were built to), FP32.  The irregular
 // harmonics T_n^m, n <= P + 1, are generated column by column and used at
 // once: T_n^m feeds the potential through M_n^m, d/dz through M_{n-1}^m,
 // and (d/dx + i d/dy) through M_{n-1}^{m-1} and M_{n-1}^{m+1}; the terms
@@ -1267,8 +1268,7 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevel
 // columns -m), so column 0 runs on its own.  The loops stay rolled: the
 // moments then come in a few at a time through scalar loads (fully
 // unrolled, the compiler would hold all of them at once).
-template <int P>
-__device__ __forceinline__ void tree_eval(const float* __restrict__ M, float X, float Y, float Z, float& phi,
+__device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, float X, float Y, float Z, float& phi,
                                           float& fx, float& fy, float& fz) {
   const float r2 = X * X + Y * Y + Z * Z;
   const float ri = rsq(r2);
@@ -1532,9 +1532,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
         const bool mine = tskip == 0;
         tskip = mine ? split - 1 : tskip - 1;
         if (mine) {
+          // order used for this node: the truncation ratio r / (d - rt)
+          // of a node well inside the opening radius reaches, at a lower
+          // order p, the bound the same node would have at the opening
+          // radius with order P (one order of margin)
+          const double d = sqrt(d2);
+          const double rho = nc.w / (d - rtp);
+          const double rho_b = nc.w / (rr / theta - rtp);
+          const float pr = (float)(P + 1) * (__logf((float)rho_b) / __logf((float)rho));
+          const int pe = __builtin_amdgcn_readfirstlane(min(P, max(2, (int)ceilf(pr))));
           float p, gx, gy, gz;
-          tree_eval<P>(mom + (long)g * kTreeMomStride, ox - (float)dlx, oy - (float)dly, oz - (float)dlz, p, gx, gy,
-                       gz);
+          tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, oz - (float)dlz, p, gx,
+                    gy, gz);
           if (!identity && (gi >> (3 * l)) == i && valid) {
             // this node holds the target's own image at x + s: take it out
             const double sx = ds.sx, sy = ds.sy, sz = ds.sz;
