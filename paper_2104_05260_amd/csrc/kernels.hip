@@ -238,25 +238,36 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
 
 // In-place exclusive scan of len entries with one 1024-thread block.
 __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, int len) {
-  __shared__ uint32_t s[1024];
-  const int per = (len + 1023) / 1024;
-  const int b = threadIdx.x * per;
-  const int e = min(len, b + per);
-  uint32_t sum = 0;
-  for (int i = b; i < e; ++i) sum += a[i];
-  s[threadIdx.x] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t v = threadIdx.x >= o ? s[threadIdx.x - o] : 0u;
+  // exclusive prefix sum in place, one block walking the array in
+  // coalesced tiles of 4096 counters (4 per thread) with a running carry
+  __shared__ uint32_t ws[16];
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  uint32_t carry = 0;
+  for (int base = 0; base < len; base += 4096) {
+    const int i0 = base + 4 * tid;
+    const uint32_t v0 = i0 < len ? a[i0] : 0u, v1 = i0 + 1 < len ? a[i0 + 1] : 0u;
+    const uint32_t v2 = i0 + 2 < len ? a[i0 + 2] : 0u, v3 = i0 + 3 < len ? a[i0 + 3] : 0u;
+    const uint32_t t1 = v0 + v1, t2 = t1 + v2, t3 = t2 + v3;
+    uint32_t x = t3;  // inclusive scan of the thread totals across the wave
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) ws[wv] = x;
     __syncthreads();
-    s[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t run = s[threadIdx.x] - sum;
-  for (int i = b; i < e; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
+    uint32_t wpre = 0, total = 0;
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t w = ws[k];
+      wpre += k < wv ? w : 0u;
+      total += w;
+    }
+    const uint32_t ex = carry + wpre + (x - t3);
+    if (i0 < len) a[i0] = ex;
+    if (i0 + 1 < len) a[i0 + 1] = ex + v0;
+    if (i0 + 2 < len) a[i0 + 2] = ex + t1;
+    if (i0 + 3 < len) a[i0 + 3] = ex + t2;
+    carry += total;
+    __syncthreads();  // ws is rewritten by the next tile
   }
 }
 
