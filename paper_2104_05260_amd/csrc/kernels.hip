@@ -1165,57 +1165,59 @@ __global__ __launch_bounds__(512) void k_tree_p2m(int n, int ntiles, int order, 
 }
 
 // Nodes of level l >= 2: box from the children's boxes, moments by
-// shifting the children's moments to the node centre (children in order).
-// One wave per node, lane k on moments k and k + 64.
-__global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevels tl, double4* __restrict__ node_c,
-                                                double4* __restrict__ node_box, double* __restrict__ mom64,
-                                                float* __restrict__ mom32) {
-  __shared__ double su[2 * kTreeMom];
-  __shared__ double smc[2 * kTreeMom];
-  const int node = blockIdx.x, lane = threadIdx.x;
+// shifting the children's moments to the node centre.  One block of 8
+// waves per node: wave w shifts child 8 * node + w (lane k on moments k and
+// k + 64), and the 8 shifted sets are added in child order.
+__global__ __launch_bounds__(512) void k_tree_m2m(int level, int order, TreeLevels tl, double4* __restrict__ node_c,
+                                                 double4* __restrict__ node_box, double* __restrict__ mom64,
+                                                 float* __restrict__ mom32) {
+  __shared__ double su[8][2 * kTreeMom];
+  __shared__ double smc[8][2 * kTreeMom];
+  __shared__ double sc[3];
+  const int node = blockIdx.x;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int c0 = 8 * node, c1 = min(c0 + 8, tl.cnt[level - 1]);
   const int coff = tl.off[level - 1];
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  double4 cc4 = make_double4(0, 0, 0, 0);
-  const bool hasc = lane < c1 - c0;
-  if (hasc) {
-    const double4 a = node_box[2 * (coff + c0 + lane)], b = node_box[2 * (coff + c0 + lane) + 1];
-    lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
-    hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
-    cc4 = node_c[coff + c0 + lane];
-  }
-  double c[3], h[3];
-  for (int d = 0; d < 3; ++d) {
-    lo[d] = wave_min(lo[d]);
-    hi[d] = wave_max(hi[d]);
-    c[d] = 0.5 * (lo[d] + hi[d]);
-    h[d] = 0.5 * (hi[d] - lo[d]);
-  }
-  // particle radius: within the box's half diagonal, and within each
-  // child's centre distance plus its radius; the smaller bound is kept
-  const double ex = cc4.x - c[0], ey = cc4.y - c[1], ez = cc4.z - c[2];
-  const double hd = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-  const double rad = fmin(hd, wave_max(hasc ? sqrt(ex * ex + ey * ey + ez * ez) + cc4.w : 0.0));
   const int g = tl.off[level] + node;
-  if (lane == 0) {
-    node_c[g] = make_double4(c[0], c[1], c[2], rad);
-    node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], hd);
-    node_box[2 * g + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
-  }
-  const int nm = (order + 1) * (order + 2) / 2;
-  int tn[2] = {0, 0}, tm[2] = {0, 0};  // this lane's moments (n, m)
-  for (int h = 0; h < 2; ++h) {
-    const int k = lane + h * kWave;
-    if (k < nm) {
-      while (tree_idx(tn[h] + 1, 0) <= k) ++tn[h];
-      tm[h] = k - tree_idx(tn[h], 0);
+  if (w == 0) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double4 cc4 = make_double4(0, 0, 0, 0);
+    const bool hasc = lane < c1 - c0;
+    if (hasc) {
+      const double4 a = node_box[2 * (coff + c0 + lane)], b = node_box[2 * (coff + c0 + lane) + 1];
+      lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
+      hi[0] = b.x; hi[1] = b.y; hi[2] = b.z;
+      cc4 = node_c[coff + c0 + lane];
+    }
+    double c[3], h[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = wave_min(lo[d]);
+      hi[d] = wave_max(hi[d]);
+      c[d] = 0.5 * (lo[d] + hi[d]);
+      h[d] = 0.5 * (hi[d] - lo[d]);
+    }
+    // particle radius: within the box's half diagonal, and within each
+    // child's centre distance plus its radius; the smaller bound is kept
+    const double ex = cc4.x - c[0], ey = cc4.y - c[1], ez = cc4.z - c[2];
+    const double hd = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    const double rad = fmin(hd, wave_max(hasc ? sqrt(ex * ex + ey * ey + ez * ez) + cc4.w : 0.0));
+    if (lane == 0) {
+      sc[0] = c[0];
+      sc[1] = c[1];
+      sc[2] = c[2];
+      node_c[g] = make_double4(c[0], c[1], c[2], rad);
+      node_box[2 * g] = make_double4(lo[0], lo[1], lo[2], hd);
+      node_box[2 * g + 1] = make_double4(hi[0], hi[1], hi[2], 0.0);
     }
   }
-  double accr[2] = {0.0, 0.0}, acci[2] = {0.0, 0.0};
-  for (int ch = c0; ch < c1; ++ch) {
+  __syncthreads();
+  const int nm = (order + 1) * (order + 2) / 2;
+  const int ch = c0 + w;
+  const bool has = ch < c1;
+  if (has) {
     const double4 cc = node_c[coff + ch];
-    const double tx = cc.x - c[0], ty = cc.y - c[1], tz = cc.z - c[2];
-    for (int k = lane; k < 2 * nm; k += kWave) smc[k] = mom64[(long)(coff + ch) * kTreeMomStride + k];
+    const double tx = cc.x - sc[0], ty = cc.y - sc[1], tz = cc.z - sc[2];
+    for (int k = lane; k < 2 * nm; k += kWave) smc[w][k] = mom64[(long)(coff + ch) * kTreeMomStride + k];
     if (lane <= order) {
       // column m = lane of U(t)
       const int m = lane;
@@ -1238,34 +1240,48 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int level, int order, TreeLevel
           cr = nr;
           ci = ni;
         }
-        su[2 * tree_idx(nn, m)] = cr;
-        su[2 * tree_idx(nn, m) + 1] = ci;
+        su[w][2 * tree_idx(nn, m)] = cr;
+        su[w][2 * tree_idx(nn, m) + 1] = ci;
       }
     }
-    __syncthreads();
-    for (int h = 0; h < 2; ++h) {
-      if (lane + h * kWave >= nm) continue;
-      for (int k = 0; k <= tn[h]; ++k) {
+  }
+  __syncthreads();
+  // this wave's child, shifted: lane k on moments k and k + 64
+  double accr[2] = {0.0, 0.0}, acci[2] = {0.0, 0.0};
+  if (has) {
+    for (int hh = 0; hh < 2; ++hh) {
+      const int kk = lane + hh * kWave;
+      if (kk >= nm) continue;
+      int tn = 0;
+      while (tree_idx(tn + 1, 0) <= kk) ++tn;
+      const int tm = kk - tree_idx(tn, 0);
+      for (int k = 0; k <= tn; ++k) {
         for (int l = -k; l <= k; ++l) {
-          const int nn = tn[h] - k, mm = tm[h] - l;
+          const int nn = tn - k, mm = tm - l;
           if (mm > nn || mm < -nn) continue;
           double ar, ai, br, bi;
-          tree_get(su, k, l, ar, ai);
-          tree_get(smc, nn, mm, br, bi);
-          accr[h] += ar * br - ai * bi;
-          acci[h] += ar * bi + ai * br;
+          tree_get(su[w], k, l, ar, ai);
+          tree_get(smc[w], nn, mm, br, bi);
+          accr[hh] += ar * br - ai * bi;
+          acci[hh] += ar * bi + ai * br;
         }
       }
     }
-    __syncthreads();
   }
-  for (int h = 0; h < 2; ++h) {
-    const int k = lane + h * kWave;
-    if (k >= nm) continue;
-    mom64[(long)g * kTreeMomStride + 2 * k] = accr[h];
-    mom64[(long)g * kTreeMomStride + 2 * k + 1] = acci[h];
-    mom32[(long)g * kTreeMomStride + 2 * k] = (float)accr[h];
-    mom32[(long)g * kTreeMomStride + 2 * k + 1] = (float)acci[h];
+  __syncthreads();  // the tables are read; reuse su as the per-child results
+  for (int hh = 0; hh < 2; ++hh) {
+    const int kk = lane + hh * kWave;
+    if (kk < nm) {
+      su[w][2 * kk] = accr[hh];
+      su[w][2 * kk + 1] = acci[hh];
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * nm; k += blockDim.x) {
+    double acc = 0.0;
+    for (int ww = 0; ww < c1 - c0; ++ww) acc += su[ww][k];
+    mom64[(long)g * kTreeMomStride + k] = acc;
+    mom32[(long)g * kTreeMomStride + k] = (float)acc;
   }
 }
 
@@ -2213,7 +2229,7 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, int n, long comp, long slot,
     hipLaunchKernelGGL(k_tree_p2m, dim3(tl.cnt[1]), dim3(512), 0, st, n, ntiles_, P, tl, (const double4*)d_pos64,
                        (const double4*)d_tile_c, (const float4*)d_tile_h, d_tnode, d_tbox, d_tmom64, d_tmom32);
   for (int l = 2; l < tl.nlev; ++l)
-    hipLaunchKernelGGL(k_tree_m2m, dim3(tl.cnt[l]), dim3(64), 0, st, l, P, tl, d_tnode, d_tbox, d_tmom64, d_tmom32);
+    hipLaunchKernelGGL(k_tree_m2m, dim3(tl.cnt[l]), dim3(512), 0, st, l, P, tl, d_tnode, d_tbox, d_tmom64, d_tmom32);
 #define HSMA_TREE_FAR(PP)                                                                                          \
   hipLaunchKernelGGL(k_tree_far<PP>, dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
                      psched_, (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, \

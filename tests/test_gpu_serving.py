@@ -143,3 +143,29 @@ def test_served_sphere_near_set():
         df = np.sqrt(((b["force"] - ref.force) ** 2).sum() / (ref.force ** 2).sum())
         note(f"   sphere near set n={len(q)}: dE/S {abs(b['energy'] - ref.energy) / S:.2e} force rel {df:.2e}")
         assert abs(b["energy"] - ref.energy) <= 1e-10 * S and df <= 1e-10
+
+
+def test_served_treecode():
+    """The treecode (near rule 2, FP32C) through the server: results within
+    the FP32 bars of the oracle's exact 27-cell sums (5e-5 on the largest
+    potential error, the treecode's truncation), and every result the same
+    alone and in the mix."""
+    _, systems = mix(count=3, seed0=2300)
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    prm = params(1)
+    prm.near_rule = 2
+    with hs.Server(prm, UNIT, max_n=nmax, max_slots=3) as sv:
+        alone = [sv.wait(sv.submit(pos, q, lo, L)) for _, pos, q, lo, L in systems]
+        tickets = [sv.submit(pos, q, lo, L) for _, pos, q, lo, L in systems]
+        together = [sv.wait(t) for t in tickets]
+    for (w, pos, q, lo, L), a, b in zip(systems, alone, together):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["energy"] == b["energy"] and np.array_equal(a["force"], b["force"])
+        ref = ohsma.hsma3d(pos, q, lo, np.array([L, L, L]), 8, 162, 512, 1.5)
+        S = 0.5 * np.abs(q * ref.potential).sum()
+        df = np.sqrt(((b["force"] - ref.force) ** 2).sum() / (ref.force ** 2).sum())
+        dp = np.abs(b["potential"] - ref.potential).max() / np.abs(ref.potential).max()
+        note(f"   treecode n={len(q)}: dE/S {abs(b['energy'] - ref.energy) / S:.2e} force rel {df:.2e} "
+             f"potential max rel {dp:.2e}")
+        assert abs(b["energy"] - ref.energy) <= 1e-6 * abs(ref.energy) + 1e-7 * S
+        assert df <= 1e-5 and dp <= 5e-5
