@@ -387,7 +387,7 @@ def test_c5_million_ions_sampled():
     assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())
 
 
-@pytest.mark.parametrize("near_rule", [0, 1])
+@pytest.mark.parametrize("near_rule", [0, 1, 2])
 def test_step_graph_replays_match_eager(near_rule):
     """A plan in graph mode captures the step on the second identical call
     and replays it; every replay (new positions each time, eager work and
@@ -444,6 +444,21 @@ def test_tree_orders(order, theta):
                          pot_bar=TREE_POT)
     if order == 12:
         assert rel_rms(f, r.force) <= 1e-6
+
+
+def test_tree_clustered():
+    """Strongly non-uniform sources (a tight cluster across a box corner, a
+    thin sheet, a uniform rest): elongated and tiny nodes, many close pairs
+    through the checked loop."""
+    rng = np.random.default_rng(12)
+    L = np.array([24.0, 24.0, 24.0])
+    a = rng.normal(0.0, 0.6, (1000, 3)) % L                      # around the corner, wrapped
+    b = np.column_stack([rng.random(1000) * 24.0, rng.random(1000) * 24.0, 12.0 + rng.normal(0, 0.05, 1000)])
+    c = rng.random((1000, 3)) * L
+    pos = np.vstack([a, b, c])
+    q = np.where(np.arange(3000) % 2 == 0, 1.0, -1.0)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, near_rule=2)
+    check(params, pos, q, np.zeros(3), L, fp32=True, label="treecode clustered", pot_bar=TREE_POT)
 
 
 def test_tree_deterministic():
