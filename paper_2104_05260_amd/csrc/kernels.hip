@@ -1459,16 +1459,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
       // a tile within the close-pair radius of the group (the far kernel's
       // test) runs the checked loop: pairs closer than rc take their
       // difference vector from the FP64 positions
+      const bool mine = tskip == 0;
+      tskip = mine ? split - 1 : tskip - 1;
       bool near = false;
-      if (!img_far && far_lev == kTreeMaxLev) {
+      if (mine && !img_far && far_lev == kTreeMaxLev) {
         const double4 cs = tile_c[tile];
         const float4 hs = tile_h[tile];
         near = gap2_of(__dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
                        shifted_dz(ds, cs.z, cgz), __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
                        __dadd_rn(hgz, (double)hs.z)) < rc2;
       }
-      const bool mine = tskip == 0;
-      tskip = mine ? split - 1 : tskip - 1;
       if (mine && near) {
         const double4 cs = tile_c[tile];
         const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
