@@ -1450,157 +1450,184 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
   const double rc = sqrt(rc2);
   const double ith2 = 1.0 / (theta * theta);
   const int top = tl.nlev - 1;
-  int l = top, i = 0;
-  int far_lev = kTreeMaxLev;  // an opened ancestor at this level is beyond rc of the group: no near tile below
-  for (;;) {
-    bool open = false;
-    if (l == 0) {
-      const int tile = i;
-      // a tile within the close-pair radius of the group (the far kernel's
-      // test) runs the checked loop: pairs closer than rc take their
-      // difference vector from the FP64 positions
-      const bool mine = tskip == 0;
-      tskip = mine ? split - 1 : tskip - 1;
-      bool near = false;
-      if (mine && !img_far && far_lev == kTreeMaxLev) {
-        const double4 cs = tile_c[tile];
-        const float4 hs = tile_h[tile];
-        near = gap2_of(__dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
-                       shifted_dz(ds, cs.z, cgz), __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
-                       __dadd_rn(hgz, (double)hs.z)) < rc2;
+  // work items, dealt round-robin to the split waves in traversal order:
+  // a tile (direct; the checked loop when within rc of the group; far_sub:
+  // an ancestor is beyond rc, so the tile is not) ...
+  auto leaf = [&](const int tile, const bool far_sub) {
+    // a tile within the close-pair radius of the group (the far kernel's
+    // test) runs the checked loop: pairs closer than rc take their
+    // difference vector from the FP64 positions
+    const bool mine = tskip == 0;
+    tskip = mine ? split - 1 : tskip - 1;
+    bool near = false;
+    if (mine && !img_far && !far_sub) {
+      const double4 cs = tile_c[tile];
+      const float4 hs = tile_h[tile];
+      near = gap2_of(__dsub_rn(__dadd_rn(cs.x, ds.sx), cgx), __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy),
+                     shifted_dz(ds, cs.z, cgz), __dadd_rn(hgx, (double)hs.x), __dadd_rn(hgy, (double)hs.y),
+                     __dadd_rn(hgz, (double)hs.z)) < rc2;
+    }
+    if (mine && near) {
+      const double4 cs = tile_c[tile];
+      const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+      const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+      const double dlz = shifted_dz(ds, cs.z, cgz);
+      const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
+      const float4* __restrict__ s = src + (long)tile * kTile;
+      const double4 p64 = pos64[(long)tile * kTile + lane];
+      const double4 tq = tgt[first + (valid ? lane : 0)];
+      float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
+      for (int k = 0; k < kTile; ++k) {
+        const float4 v = s[k];
+        float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
+        float r2 = dx * dx + dy * dy + dz * dz;
+        float qv = v.w;
+        if (tile == gi && tile * kTile + k == tself) {
+          // the target itself or its own image: finalize sums the images
+          qv = 0.f;
+          r2 = 1.f;
+        } else if ((double)r2 < rc2) {
+          const double psx = readlane_d(p64.x, k), psy = readlane_d(p64.y, k), psz = readlane_d(p64.z, k);
+          dx = (float)(tq.x - (psx + ds.sx));
+          dy = (float)(tq.y - (psy + ds.sy));
+          dz = (float)(tq.z - (psz + ds.sz));
+          r2 = dx * dx + dy * dy + dz * dz;
+        }
+        const float ri = rsq(r2);
+        const float a = qv * ri;
+        pp += a;
+        const float b = a * (ri * ri);
+        qx += b * dx;
+        qy += b * dy;
+        qz += b * dz;
       }
-      if (mine && near) {
-        const double4 cs = tile_c[tile];
-        const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
-        const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
-        const double dlz = shifted_dz(ds, cs.z, cgz);
-        const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
-        const float4* __restrict__ s = src + (long)tile * kTile;
-        const double4 p64 = pos64[(long)tile * kTile + lane];
-        const double4 tq = tgt[first + (valid ? lane : 0)];
-        float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
+      add(pp, qx, qy, qz);
+    } else if (mine) {
+      const double4 cs = tile_c[tile];
+      const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
+      const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
+      const double dlz = shifted_dz(ds, cs.z, cgz);
+      const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
+      const float4* __restrict__ s = src + (long)tile * kTile;
+      float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
+      if (tile == gi) {
+        // own tile (under any image): drop each target's own image,
+        // which finalize sums in FP64
         for (int k = 0; k < kTile; ++k) {
           const float4 v = s[k];
-          float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
-          float r2 = dx * dx + dy * dy + dz * dz;
-          float qv = v.w;
-          if (tile == gi && tile * kTile + k == tself) {
-            // the target itself or its own image: finalize sums the images
-            qv = 0.f;
-            r2 = 1.f;
-          } else if ((double)r2 < rc2) {
-            const double psx = readlane_d(p64.x, k), psy = readlane_d(p64.y, k), psz = readlane_d(p64.z, k);
-            dx = (float)(tq.x - (psx + ds.sx));
-            dy = (float)(tq.y - (psy + ds.sy));
-            dz = (float)(tq.z - (psz + ds.sz));
-            r2 = dx * dx + dy * dy + dz * dz;
-          }
+          const bool self = tile * kTile + k == tself;
+          const float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
+          const float r2 = self ? 1.f : dx * dx + dy * dy + dz * dz;
           const float ri = rsq(r2);
-          const float a = qv * ri;
+          const float a = (self ? 0.f : v.w) * ri;
           pp += a;
           const float b = a * (ri * ri);
           qx += b * dx;
           qy += b * dy;
           qz += b * dz;
         }
-        add(pp, qx, qy, qz);
-      } else if (mine) {
-        const double4 cs = tile_c[tile];
-        const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
-        const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
-        const double dlz = shifted_dz(ds, cs.z, cgz);
-        const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
-        const float4* __restrict__ s = src + (long)tile * kTile;
-        float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
-        if (tile == gi) {
-          // own tile (under any image): drop each target's own image,
-          // which finalize sums in FP64
-          for (int k = 0; k < kTile; ++k) {
-            const float4 v = s[k];
-            const bool self = tile * kTile + k == tself;
-            const float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
-            const float r2 = self ? 1.f : dx * dx + dy * dy + dz * dz;
-            const float ri = rsq(r2);
-            const float a = (self ? 0.f : v.w) * ri;
-            pp += a;
-            const float b = a * (ri * ri);
-            qx += b * dx;
-            qy += b * dy;
-            qz += b * dz;
-          }
-        } else {
-#pragma unroll HSMA_FAR_UNROLL
-          for (int k = 0; k < kTile; ++k) {
-            const float4 v = s[k];
-            const float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float ri = rsq(r2);
-            const float a = v.w * ri;
-            pp += a;
-            const float b = a * (ri * ri);
-            qx += b * dx;
-            qy += b * dy;
-            qz += b * dz;
-          }
-        }
-        add(pp, qx, qy, qz);
-      }
-    } else {
-      const int g = tl.off[l] + i;
-      const double4 nc = node_c[g];
-      const double dlx = __dsub_rn(__dadd_rn(nc.x, ds.sx), cgx);
-      const double dly = __dsub_rn(__dadd_rn(nc.y, ds.sy), cgy);
-      const double dlz = __dsub_rn(__dadd_rn(nc.z, ds.sz), cgz);
-      const double d2 = dlx * dlx + dly * dly + dlz * dlz;
-      const double far_r = (node_box[2 * g].w + rt + rc) * (1.0 + 1e-12);  // boxes; margin over rounding
-      const bool beyond_rc = d2 > far_r * far_r;
-      const double rr = nc.w + rtp;  // particle radii
-      if (beyond_rc && d2 > rr * rr * ith2) {
-        const bool mine = tskip == 0;
-        tskip = mine ? split - 1 : tskip - 1;
-        if (mine) {
-          // order used for this node: the truncation ratio r / (d - rt)
-          // of a node well inside the opening radius reaches, at a lower
-          // order p, the bound the same node would have at the opening
-          // radius with order P (one order of margin)
-          const double d = sqrt(d2);
-          const double rho = nc.w / (d - rtp);
-          const double rho_b = nc.w / (rr / theta - rtp);
-          const float pr = (float)(P + 1) * (__logf((float)rho_b) / __logf((float)rho));
-          const int pe = __builtin_amdgcn_readfirstlane(min(P, max(2, (int)ceilf(pr))));
-          float p, gx, gy, gz;
-          tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, oz - (float)dlz, p, gx,
-                    gy, gz);
-          if (!identity && (gi >> (3 * l)) == i && valid) {
-            // this node holds the target's own image at x + s: take it out
-            const double sx = ds.sx, sy = ds.sy, sz = ds.sz;
-            const double si = 1.0 / sqrt(sx * sx + sy * sy + sz * sz);
-            const double qs = qt * si;
-            p -= (float)qs;
-            gx += (float)(qs * si * si * sx);
-            gy += (float)(qs * si * si * sy);
-            gz += (float)(qs * si * si * sz);
-          }
-          add(p, gx, gy, gz);
-        }
       } else {
-        open = true;
-        if (beyond_rc && far_lev == kTreeMaxLev) far_lev = l;
+#pragma unroll HSMA_FAR_UNROLL
+        for (int k = 0; k < kTile; ++k) {
+          const float4 v = s[k];
+          const float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          const float ri = rsq(r2);
+          const float a = v.w * ri;
+          pp += a;
+          const float b = a * (ri * ri);
+          qx += b * dx;
+          qy += b * dy;
+          qz += b * dz;
+        }
       }
+      add(pp, qx, qy, qz);
     }
-    if (open) {
-      --l;
-      i *= 8;
-      continue;
+  };
+  // ... or an accepted node (multipole at its own order)
+  auto node = [&](const int l, const int i, const double dlx, const double dly, const double dlz, const double d2,
+                  const double rr) {
+    const bool mine = tskip == 0;
+    tskip = mine ? split - 1 : tskip - 1;
+    if (!mine) return;
+    const int g = tl.off[l] + i;
+    const double rn = node_c[g].w;
+    // order used for this node: the truncation ratio r / (d - rt) of a
+    // node well inside the opening radius reaches, at a lower order p, the
+    // bound the same node would have at the opening radius with order P
+    // (one order of margin)
+    const double d = sqrt(d2);
+    const double rho = rn / (d - rtp);
+    const double rho_b = rn / (rr / theta - rtp);
+    const float pr = (float)(P + 1) * (__logf((float)rho_b) / __logf((float)rho));
+    const int pe = __builtin_amdgcn_readfirstlane(min(P, max(2, (int)ceilf(pr))));
+    float p, gx, gy, gz;
+    tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, oz - (float)dlz, p, gx, gy, gz);
+    if (!identity && (gi >> (3 * l)) == i && valid) {
+      // this node holds the target's own image at x + s: take it out
+      const double sx = ds.sx, sy = ds.sy, sz = ds.sz;
+      const double si = 1.0 / sqrt(sx * sx + sy * sy + sz * sz);
+      const double qs = qt * si;
+      p -= (float)qs;
+      gx += (float)(qs * si * si * sx);
+      gy += (float)(qs * si * si * sy);
+      gz += (float)(qs * si * si * sz);
     }
-    // next node in depth-first order: the next sibling, else climb
-    while (l < top && ((i & 7) == 7 || i + 1 >= tl.cnt[l])) {
-      i >>= 3;
-      ++l;
+    add(p, gx, gy, gz);
+  };
+  // Traversal: the children of every opened node (and the root, the one
+  // child of a virtual parent above it) are classified by eight lanes at
+  // once; accepted children and tiles are processed in child order, then
+  // the walk descends into the first opened child not yet visited, deepest
+  // level first.  Per children level L (0..top), 8 bits of open_bits mark
+  // the opened children still to visit and 8 bits of bey_bits those beyond
+  // rc of the group; bit L of far_bits says that their parent is.  (Tiles
+  // are at most 2^20, so top <= 7 and the bits fit one 64-bit word.)
+  unsigned long long open_bits = 0ull, bey_bits = 0ull;
+  unsigned far_bits = 0u;
+  int lc = top, par = 0;  // children level, and their parent's index at level lc + 1
+  bool farp = false;
+  for (;;) {
+    const int c0 = 8 * par, cc = min(8, tl.cnt[lc] - c0);
+    if (lc == 0) {
+      for (int k = 0; k < cc; ++k) leaf(c0 + k, farp);
+    } else {
+      double cdx = 0.0, cdy = 0.0, cdz = 0.0, cd2 = 0.0, crr = 0.0;
+      bool acc = false, bey = false;
+      if (lane < cc) {
+        const int g = tl.off[lc] + c0 + lane;
+        const double4 nc = node_c[g];
+        cdx = __dsub_rn(__dadd_rn(nc.x, ds.sx), cgx);
+        cdy = __dsub_rn(__dadd_rn(nc.y, ds.sy), cgy);
+        cdz = __dsub_rn(__dadd_rn(nc.z, ds.sz), cgz);
+        cd2 = cdx * cdx + cdy * cdy + cdz * cdz;
+        const double far_r = (node_box[2 * g].w + rt + rc) * (1.0 + 1e-12);  // boxes; margin over rounding
+        bey = cd2 > far_r * far_r;
+        crr = nc.w + rtp;  // particle radii
+        acc = bey && cd2 > crr * crr * ith2;
+      }
+      const unsigned long long m_acc = __ballot(acc), m_bey = __ballot(bey);
+      const unsigned long long m_open = __ballot(lane < cc) & ~m_acc;
+      for (int k = 0; k < cc; ++k)
+        if ((m_acc >> k) & 1ull)
+          node(lc, c0 + k, readlane_d(cdx, k), readlane_d(cdy, k), readlane_d(cdz, k), readlane_d(cd2, k),
+               readlane_d(crr, k));
+      const int sh = 8 * lc;
+      open_bits = (open_bits & ~(0xffull << sh)) | ((m_open & 0xffull) << sh);
+      bey_bits = (bey_bits & ~(0xffull << sh)) | ((m_bey & 0xffull) << sh);
+      far_bits = farp ? (far_bits | (1u << lc)) : (far_bits & ~(1u << lc));
     }
-    if (l >= far_lev) far_lev = kTreeMaxLev;  // left (or finished) the far subtree
-    if (l >= top) break;
-    ++i;
+    // next opened child: the deepest level with one left
+    int L = lc >= 1 ? lc : 1;
+    while (L <= top && ((open_bits >> (8 * L)) & 0xffull) == 0ull) ++L;
+    if (L > top) break;
+    const unsigned mk = (unsigned)((open_bits >> (8 * L)) & 0xffull);
+    const int k = __builtin_ctz(mk);
+    open_bits &= ~(1ull << (8 * L + k));
+    const int q = par >> (3 * (L - lc));  // the parent (level L + 1) of the level-L children
+    farp = ((far_bits >> L) & 1u) || ((bey_bits >> (8 * L + k)) & 1ull);
+    par = 8 * q + k;
+    lc = L - 1;
   }
   if (valid) {
     const long o = (long)c * slot_stride + first + lane;
@@ -2445,6 +2472,10 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   }
   if (host.prm.near_rule == 1 && (n64 + kTile - 1) / kTile > (int64_t)1 << kTileBits) {
     err = "too many particles for the sphere near set (at most 2^26)";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  if (host.prm.near_rule == 2 && (n64 + kTile - 1) / kTile > (int64_t)1 << 20) {
+    err = "too many particles for the treecode (at most 2^26)";
     return HSMA_ERR_INVALID_ARG;
   }
   hsma_status s = prepare(n64, st, err);
