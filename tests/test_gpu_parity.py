@@ -114,8 +114,8 @@ def test_ragged_sizes_3d(n, prec):
     check(params, pos, q, lo, box, fp32=prec == 1, label=f"3d ragged n={n}")
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_boundary_and_wrapped_positions(prec):
+@pytest.mark.parametrize("prec,rule", [(0, 0), (1, 0), (1, 2)])
+def test_boundary_and_wrapped_positions(prec, rule):
     """Ions exactly on box faces, edges and corners, and ions given one or
     two box lengths outside the box (wrapped into it by both sides)."""
     L = np.array([9.0, 10.0, 11.0])
@@ -129,8 +129,9 @@ def test_boundary_and_wrapped_positions(prec):
     pos[24] = lo + L                 # one corner (all corners are one point)
     for i in range(25, 48):          # one or two periods outside
         pos[i] += rng.integers(-2, 3, 3) * L
-    params = hs.Params(precision=prec, p=6, K=100, F=200, lam=1.4)
-    check(params, pos, q, lo, L, fp32=prec == 1, label="boundary and wrapped positions")
+    params = hs.Params(precision=prec, p=6, K=100, F=200, lam=1.4, near_rule=rule)
+    check(params, pos, q, lo, L, fp32=prec == 1, label=f"boundary and wrapped positions, near rule {rule}",
+          pot_bar=TREE_POT if rule == 2 else 1e-5)
 
 
 def test_single_neutral_particle():
