@@ -1429,7 +1429,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
   const double3 hbox = sp->hbox;
   const double rc2 = sp->rc2;
   const Desc ds = desc[img];
-  const bool identity = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0;
+  const bool identity = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.0;
+  // slab images: z -> sigma z + sz with strength scale (3D: 1, 1)
+  const float sg = (float)ds.sigma, sc = (float)ds.scale;
   const bool img_far = gap2_of(__dsub_rn(ds.sx, cgx), __dsub_rn(ds.sy, cgy), __dsub_rn(ds.sz, cgz),
                                __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
   const int tself = first + lane;  // sorted index of this lane's target
@@ -1472,7 +1474,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
       const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
       const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
       const double dlz = shifted_dz(ds, cs.z, cgz);
-      const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
+      const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = sg * (oz - (float)dlz);
       const float4* __restrict__ s = src + (long)tile * kTile;
       const double4 p64 = pos64[(long)tile * kTile + lane];
       const double4 tq = tgt[first + (valid ? lane : 0)];
@@ -1490,7 +1492,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
           const double psx = readlane_d(p64.x, k), psy = readlane_d(p64.y, k), psz = readlane_d(p64.z, k);
           dx = (float)(tq.x - (psx + ds.sx));
           dy = (float)(tq.y - (psy + ds.sy));
-          dz = (float)(tq.z - (psz + ds.sz));
+          dz = sg * (float)(tq.z - (ds.sigma * psz + ds.sz));
           r2 = dx * dx + dy * dy + dz * dz;
         }
         const float ri = rsq(r2);
@@ -1501,13 +1503,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
         qy += b * dy;
         qz += b * dz;
       }
-      add(pp, qx, qy, qz);
+      add(sc * pp, sc * qx, sc * qy, (sc * sg) * qz);
     } else if (mine) {
       const double4 cs = tile_c[tile];
       const double dlx = __dsub_rn(__dadd_rn(cs.x, ds.sx), cgx);
       const double dly = __dsub_rn(__dadd_rn(cs.y, ds.sy), cgy);
       const double dlz = shifted_dz(ds, cs.z, cgz);
-      const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = oz - (float)dlz;
+      const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = sg * (oz - (float)dlz);
       const float4* __restrict__ s = src + (long)tile * kTile;
       float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
       if (tile == gi) {
@@ -1541,7 +1543,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
           qz += b * dz;
         }
       }
-      add(pp, qx, qy, qz);
+      add(sc * pp, sc * qx, sc * qy, (sc * sg) * qz);
     }
   };
   // ... or an accepted node (multipole at its own order)
@@ -1561,17 +1563,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
     const double rho_b = rn / (rr / theta - rtp);
     const float pr = (float)(P + 1) * (__logf((float)rho_b) / __logf((float)rho));
     const int pe = __builtin_amdgcn_readfirstlane(min(P, max(2, (int)ceilf(pr))));
+    // the image of the node acts at x as the node itself at the mirrored
+    // point (x, y, sigma (z - sz)): evaluate there, scale, mirror E_z
     float p, gx, gy, gz;
-    tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, oz - (float)dlz, p, gx, gy, gz);
+    tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, sg * (oz - (float)dlz), p, gx,
+              gy, gz);
+    p *= sc;
+    gx *= sc;
+    gy *= sc;
+    gz *= sc * sg;
     if (!identity && (gi >> (3 * l)) == i && valid) {
-      // this node holds the target's own image at x + s: take it out
-      const double sx = ds.sx, sy = ds.sy, sz = ds.sz;
-      const double si = 1.0 / sqrt(sx * sx + sy * sy + sz * sz);
-      const double qs = qt * si;
+      // this node holds the target's own image: take it out
+      const double tz = tgt[first + lane].z;
+      const double ddx = -ds.sx, ddy = -ds.sy, ddz = tz - (ds.sigma * tz + ds.sz);
+      const double si = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+      const double qs = ds.scale * qt * si;
       p -= (float)qs;
-      gx += (float)(qs * si * si * sx);
-      gy += (float)(qs * si * si * sy);
-      gz += (float)(qs * si * si * sz);
+      gx -= (float)(qs * si * si * ddx);
+      gy -= (float)(qs * si * si * ddy);
+      gz -= (float)(qs * si * si * ddz);
     }
     add(p, gx, gy, gz);
   };
@@ -1599,7 +1609,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
         const double4 nc = node_c[g];
         cdx = __dsub_rn(__dadd_rn(nc.x, ds.sx), cgx);
         cdy = __dsub_rn(__dadd_rn(nc.y, ds.sy), cgy);
-        cdz = __dsub_rn(__dadd_rn(nc.z, ds.sz), cgz);
+        cdz = shifted_dz(ds, nc.z, cgz);
         cd2 = cdx * cdx + cdy * cdy + cdz * cdz;
         const double far_r = (node_box[2 * g].w + rt + rc) * (1.0 + 1e-12);  // boxes; margin over rounding
         bey = cd2 > far_r * far_r;

@@ -380,9 +380,9 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     return HSMA_ERR_INVALID_ARG;
   }
   if (prm.near_rule == 2 &&
-      (slab || prm.precision != HSMA_FP32C || prm.tree_order < 4 || prm.tree_order > 12 || prm.tree_order % 2 != 0 ||
+      (prm.precision != HSMA_FP32C || prm.tree_order < 4 || prm.tree_order > 12 || prm.tree_order % 2 != 0 ||
        !(prm.tree_theta > 0 && prm.tree_theta <= 0.75))) {
-    msg = "near rule 2 (treecode): 3D, FP32C, tree order 4/6/8/10/12, 0 < tree theta <= 0.75";
+    msg = "near rule 2 (treecode): FP32C, tree order 4/6/8/10/12, 0 < tree theta <= 0.75";
     return HSMA_ERR_INVALID_ARG;
   }
   if (prm.surface_rule == 1) {

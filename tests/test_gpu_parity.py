@@ -447,6 +447,39 @@ def test_tree_orders(order, theta):
         assert rel_rms(f, r.force) <= 1e-6
 
 
+@pytest.mark.parametrize("gam", [(0.0, 0.0), (-0.94, -0.94), (0.5, -0.3)])
+def test_tree_slab(gam):
+    """The slab's image layers through the treecode: mirrored images act as
+    the node at the mirrored point, scaled by the layer strength."""
+    pos, q, lo, L = workloads.small_system(2000, (40.0, 40.0, 20.0), 25, geometry=1)
+    params = hs.Params(geometry=1, precision=1, p=8, K=200, F=512, lam=1.6, M=6, gamma_up=gam[0],
+                       gamma_low=gam[1], nz=40, near_rule=2)
+    check(params, pos, q, lo, L, fp32=True, label=f"slab treecode gamma={gam}", pot_bar=TREE_POT)
+
+
+def test_c3_slab_treecode_sampled():
+    """The 20,000-ion slab with the treecode: against the oracle at 256
+    sampled particles and against the FP64 stencil GPU path everywhere."""
+    w = workloads.C3
+    pos, q, lo, L = workloads.make_system(w)
+    sample = np.random.default_rng(8).choice(w.n, 256, replace=False)
+    params = hs.Params.from_workload(w)
+    params.near_rule = 2
+    note("[parity] C3 slab treecode: oracle (sampled)")
+    r = _sampled_oracle(w, params, pos, q, lo, L, sample)
+    e, pot, f = run_gpu(params, pos, q, lo, L)
+    dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
+    df = rel_rms(f[sample], r.force)
+    note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}")
+    assert dp < TREE_POT and df < 1e-5
+    e64, pot64, f64 = run_gpu(hs.Params.from_workload(w, precision=0), pos, q, lo, L)
+    S = 0.5 * np.abs(q * pot64).sum()
+    note(f"   energy tree {e:.12g} fp64 {e64:.12g} rel {abs(e - e64) / abs(e64):.2e}; dE/S {abs(e - e64) / S:.2e}; "
+         f"force rms rel {rel_rms(f, f64):.2e}")
+    assert abs(e - e64) <= fp32_energy_bar(e64, S)
+    assert rel_rms(f, f64) <= 1e-5
+
+
 def test_tree_clustered():
     """Strongly non-uniform sources (a tight cluster across a box corner, a
     thin sheet, a uniform rest): elongated and tiny nodes, many close pairs

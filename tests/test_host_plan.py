@@ -59,7 +59,6 @@ def test_no_device_is_reported():
     (dict(near_rule=3), "HSMA_ERR_INVALID_ARG"),
     # the treecode (near rule 2): 3D, FP32C, even order 4..12, 0 < theta <= 0.75
     (dict(near_rule=2, precision=0), "HSMA_ERR_INVALID_ARG"),
-    (dict(near_rule=2, geometry=1), "HSMA_ERR_INVALID_ARG"),
     (dict(near_rule=2, tree_order=7), "HSMA_ERR_INVALID_ARG"),
     (dict(near_rule=2, tree_order=14), "HSMA_ERR_INVALID_ARG"),
     (dict(near_rule=2, tree_theta=0.8), "HSMA_ERR_INVALID_ARG"),
