@@ -107,7 +107,10 @@ struct DevicePlan {
   int timed_calls = 0;
   std::vector<hipEvent_t> events;   // kStages * 2 events per timed call
   hsma_status record(hipStream_t st, int stage, int edge, std::string& err);
-  hsma_status launch_tree(hipStream_t st, int n, long comp, long slot, std::string& err);
+  void build_tree(hipStream_t st, int n);
+  template <bool CHECKS>
+  hsma_status launch_tree(hipStream_t st, long comp, long slot, std::string& err);
+  int tree_cwaves_ = 0, tree_csplit_ = 1;  // treecode at the check targets (0: direct check sums)
   hipStream_t last_stream = nullptr;
 
   void* h_stage = nullptr;       // pinned staging of the check schedule

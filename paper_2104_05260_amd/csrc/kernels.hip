@@ -1394,22 +1394,51 @@ __device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, fl
 #ifndef HSMA_TREE_WAVES
 #define HSMA_TREE_WAVES 8
 #endif
-template <int P>
+template <int P, bool CHECKS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WAVES))) void k_tree_far(
-    const double4* __restrict__ tgt, PartSched ps, const Desc* __restrict__ desc, int ntiles,
+    const double4* __restrict__ tgt, PartSched ps, const Group* __restrict__ cgroups,
+    const CheckSched* __restrict__ csched, int ncg, int csplit, const Desc* __restrict__ desc, int ntiles,
     const double4* __restrict__ tile_c, const float4* __restrict__ tile_h, const float4* __restrict__ src,
     const double4* __restrict__ pos64, const StepParams* __restrict__ sp, TreeLevels tl,
     const double4* __restrict__ node_c,
     const double4* __restrict__ node_box, const float* __restrict__ mom, double theta, float* __restrict__ part,
     long comp_stride, long slot_stride) {
-  const int c = blockIdx.x / ps.ngroups;
-  const int gi = blockIdx.x - c * ps.ngroups;
-  const int split = ps.split;
-  const int img = c / split;
-  int tskip = c - img * split;  // work items to pass over before this wave's next one
+  // the wave's target group, image entry, share and output slot
+  int gi, split, img, tskip, first, count;
+  long obase;
+  const Desc* __restrict__ dtab = desc;
+  if constexpr (CHECKS) {
+    // check targets: the check group whose waves include this one (binary
+    // search over the waves' first indices), its own image table
+    const int bid = blockIdx.x;
+    int lo = 0, hi = ncg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (csched[mid].first_work <= bid) lo = mid;
+      else hi = mid - 1;
+    }
+    gi = lo;
+    const CheckSched cs = csched[gi];
+    const Group g = cgroups[gi];
+    const int cw = bid - cs.first_work;
+    split = csplit;
+    img = cw / split;
+    tskip = cw - img * split;
+    first = g.first;
+    count = g.count;
+    dtab = desc + g.desc_off;
+    obase = (long)(cs.slot0 + cw) * slot_stride;
+  } else {
+    const int c = blockIdx.x / ps.ngroups;
+    gi = blockIdx.x - c * ps.ngroups;
+    split = ps.split;
+    img = c / split;
+    tskip = c - img * split;  // work items to pass over before this wave's next one
+    first = gi * kGroup;
+    count = min(kGroup, ps.n - first);
+    obase = (long)c * slot_stride + first;
+  }
   const int lane = threadIdx.x;
-  const int first = gi * kGroup;
-  const int count = min(kGroup, ps.n - first);
   const bool valid = lane < count;
   const double4 tp = tgt[first + (valid ? lane : 0)];
   const double mnx = wave_min(valid ? tp.x : INFINITY), mxx = wave_max(valid ? tp.x : -INFINITY);
@@ -1427,8 +1456,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
   const float ox = (float)ptx, oy = (float)pty, oz = (float)ptz;
   const double qt = tp.w;  // (the FP64 position is read again where a close pair needs it)
   const double3 hbox = sp->hbox;
-  const double rc2 = sp->rc2;
-  const Desc ds = desc[img];
+  const double rc2 = CHECKS ? sp->rc2c : sp->rc2;
+  const Desc ds = dtab[img];
   const bool identity = ds.sx == 0.0 && ds.sy == 0.0 && ds.sz == 0.0 && ds.sigma > 0.0;
   // slab images: z -> sigma z + sz with strength scale (3D: 1, 1)
   const float sg = (float)ds.sigma, sc = (float)ds.scale;
@@ -1484,7 +1513,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
         float dx = ux - v.x, dy = uy - v.y, dz = uz - v.z;
         float r2 = dx * dx + dy * dy + dz * dz;
         float qv = v.w;
-        if (tile == gi && tile * kTile + k == tself) {
+        if (!CHECKS && tile == gi && tile * kTile + k == tself) {
           // the target itself or its own image: finalize sums the images
           qv = 0.f;
           r2 = 1.f;
@@ -1512,7 +1541,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
       const float ux = ox - (float)dlx, uy = oy - (float)dly, uz = sg * (oz - (float)dlz);
       const float4* __restrict__ s = src + (long)tile * kTile;
       float pp = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
-      if (tile == gi) {
+      if (!CHECKS && tile == gi) {
         // own tile (under any image): drop each target's own image,
         // which finalize sums in FP64
         for (int k = 0; k < kTile; ++k) {
@@ -1572,7 +1601,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
     gx *= sc;
     gy *= sc;
     gz *= sc * sg;
-    if (!identity && (gi >> (3 * l)) == i && valid) {
+    if (!CHECKS && !identity && (gi >> (3 * l)) == i && valid) {
       // this node holds the target's own image: take it out
       const double tz = tgt[first + lane].z;
       const double ddx = -ds.sx, ddy = -ds.sy, ddz = tz - (ds.sigma * tz + ds.sz);
@@ -1640,7 +1669,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
     lc = L - 1;
   }
   if (valid) {
-    const long o = (long)c * slot_stride + first + lane;
+    const long o = obase + lane;
     part[o] = ph;
     part[o + comp_stride] = pl;
     part[o + 2 * comp_stride] = ex;
@@ -2224,6 +2253,27 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   std::vector<CheckSched> cs;
   int ncfar = 0, ncslots = 0;
   check_schedule(host.check_groups, ntiles, ctarget, cs, ncfar, ncslots);
+  // treecode at the check targets (near rule 2): `split` waves per (check
+  // group, image entry), each wave its own slot; the row reduction sums the
+  // group's nch + 1 slots
+  tree_cwaves_ = 0;
+  tree_csplit_ = 1;
+  if (host.prm.near_rule == 2 && !cs.empty()) {
+    long long nd = 0;
+    for (const Group& g : host.check_groups) nd += g.ndesc;
+    if (nd <= check_target_max) {
+      const int split = (int)std::max<long long>(1, std::min<long long>(kTreeMaxSplit, check_target_max / nd));
+      int w = 0;
+      for (size_t gi = 0; gi < cs.size(); ++gi) {
+        const int nw = host.check_groups[gi].ndesc * split;
+        cs[gi] = CheckSched{w, nw - 1, 1, w};
+        w += nw;
+      }
+      ncfar = ncslots = w;
+      tree_cwaves_ = w;
+      tree_csplit_ = split;
+    }
+  }
   const int sch = sphere_chunk(host.prm.F, ps.ngroups);
   const int nsc = (host.prm.F + sch - 1) / sch;
   const size_t rb = host.prm.precision == HSMA_FP64 ? sizeof(double) : sizeof(float);
@@ -2257,9 +2307,9 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
 }
 
 // Event pair (stage, edge) of the current timed call, created on demand.
-// Treecode far sums (near rule 2, FP32): the node boxes and moments level
-// by level, then one wave per (image entry, target group).
-hsma_status DevicePlan::launch_tree(hipStream_t st, int n, long comp, long slot, std::string& err) {
+// Treecode (near rule 2, FP32): the node boxes and moments level by level
+// (after the tiles, before the check and particle branches fork).
+void DevicePlan::build_tree(hipStream_t st, int n) {
   const int P = host.prm.tree_order;
   const TreeLevels tl = tree_;
   if (tl.nlev >= 2)
@@ -2267,12 +2317,27 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, int n, long comp, long slot,
                        (const double4*)d_tile_c, (const float4*)d_tile_h, d_tnode, d_tbox, d_tmom64, d_tmom32);
   for (int l = 2; l < tl.nlev; ++l)
     hipLaunchKernelGGL(k_tree_m2m, dim3(tl.cnt[l]), dim3(512), 0, st, l, P, tl, d_tnode, d_tbox, d_tmom64, d_tmom32);
+}
+
+// Treecode sums at the particles (CHECKS false: one wave per (image entry,
+// share, group), slots of the particle buffer) or at the check targets
+// (CHECKS true: tree_cwaves_ waves in check-group order, the check
+// schedule's slots).
+template <bool CHECKS>
+hsma_status DevicePlan::launch_tree(hipStream_t st, long comp, long slot, std::string& err) {
+  const int P = host.prm.tree_order;
+  const TreeLevels tl = tree_;
+  const int grid = CHECKS ? tree_cwaves_ : psched_.nch * psched_.ngroups;
+  if (grid <= 0) return HSMA_OK;
 #define HSMA_TREE_FAR(PP)                                                                                          \
-  hipLaunchKernelGGL(k_tree_far<PP>, dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st, (const double4*)d_pos64, \
-                     psched_, (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h, \
-                     (const float4*)d_src32, (const double4*)d_pos64, (const StepParams*)d_sp, tl,                \
-                     (const double4*)d_tnode,                                                                    \
-                     (const double4*)d_tbox, (const float*)d_tmom32, host.prm.tree_theta, (float*)d_part, comp, slot)
+  hipLaunchKernelGGL((k_tree_far<PP, CHECKS>), dim3(grid), dim3(64), 0, st,                                        \
+                     CHECKS ? (const double4*)d_check_pos : (const double4*)d_pos64, psched_,                     \
+                     (const Group*)d_check_groups, (const CheckSched*)d_csched, (int)host.check_groups.size(),     \
+                     tree_csplit_, CHECKS ? (const Desc*)d_desc_check : (const Desc*)d_desc_part, ntiles_,         \
+                     (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,                   \
+                     (const double4*)d_pos64, (const StepParams*)d_sp, tl, (const double4*)d_tnode,               \
+                     (const double4*)d_tbox, (const float*)d_tmom32, host.prm.tree_theta,                         \
+                     CHECKS ? (float*)d_cpart : (float*)d_part, comp, slot)
   switch (P) {
     case 4: HSMA_TREE_FAR(4); break;
     case 6: HSMA_TREE_FAR(6); break;
@@ -2333,6 +2398,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   }
   hipLaunchKernelGGL(k_tiles, dim3(ntiles_), dim3(64), 0, st, n, (const int*)d_val[0], (const double4*)d_pos_w,
                      d_pos64, d_src32, d_src64, d_tile_c, d_tile_h, d_perm);
+  if (host.prm.near_rule == 2) build_tree(st, n);
   const unsigned long long* cullp = nullptr;
   CullView cv{nullptr, nullptr, nullptr};
   if (host.prm.near_rule == 1) {
@@ -2384,7 +2450,7 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   do {                                                                                                              \
     if ((s = record(st, kStNear, 0, err)) != HSMA_OK) return s;                                                     \
     if (host.prm.near_rule == 2) {                                                                                  \
-      if ((s = launch_tree(st, n, comp, slot, err)) != HSMA_OK) return s;                                           \
+      if ((s = launch_tree<false>(st, comp, slot, err)) != HSMA_OK) return s;                                       \
     } else {                                                                                                        \
       hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,         \
                          (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,    \
@@ -2443,6 +2509,12 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
         const int gf = host.face_groups;
         HSMA_CHECKS(double, double4, d_src64, 0, cwork_face_, 0, gf);
         HSMA_CHECKS(float, float4, d_src32, cwork_face_, ncwork_, gf, ncg);
+      } else if (tree_cwaves_ > 0) {
+        // treecode at the check targets, then the same row reduction
+        if ((s = launch_tree<true>(st, ccomp, 5L * kGroup, err)) != HSMA_OK) return s;
+        hipLaunchKernelGGL(k_reduce_check<float>, dim3(ncg), dim3(kGroup * kFinParts), 0, st,
+                           (const Group*)d_check_groups, (const CheckSched*)d_csched, 0, (const int*)d_check_axis,
+                           (const float*)d_cpart, 5L * kGroup, d_v);
       } else {
         HSMA_CHECKS(float, float4, d_src32, 0, ncwork_, 0, ncg);
       }
