@@ -246,10 +246,11 @@ def tree_rule_bench(hs, workloads, w, pos, q, lo, L, x, qq, en, pot, f, stream, 
 
 
 def slab_near_sets_bench(hs, workloads, steps=5):
-    """The 20,000-ion slab with both near sets: the 189-entry stencil at the
-    workload's p = 10 and the sphere near set at p = 14 (K = 450, F = 1152),
-    FP32 compensated, timed on the current stream; the sphere result's RMS
-    force difference from the stencil's FP64 result."""
+    """The 20,000-ion slab with the near sets: the 189-entry stencil at the
+    workload's p = 10, the sphere near set at p = 14 (K = 450, F = 1152),
+    and the stencil by the treecode (order 8, theta 0.5), FP32 compensated,
+    timed on the current stream; their differences from the stencil's FP64
+    result."""
     import dataclasses
     import numpy as np
     import torch
@@ -278,14 +279,24 @@ def slab_near_sets_bench(hs, workloads, steps=5):
         return ev0.elapsed_time(ev1) / k, f.cpu().numpy(), pairs
 
     ws = dataclasses.replace(w, p=14, K=450, F=1152, near_rule=1)
+    wt = dataclasses.replace(w, near_rule=2)
     ms_cells, _, pairs_cells = timed(w, hs.FP32C, steps)
     _, f64_cells, _ = timed(w, hs.FP64, 1)
+    e64 = en.item()
     ms_sphere, f_sphere, pairs_sphere = timed(ws, hs.FP32C, steps)
+    ms_tree, f_tree, _ = timed(wt, hs.FP32C, steps)
+    e_tree = en.item()
+
+    def rms(a):
+        return float(np.sqrt(((a - f64_cells) ** 2).sum() / (f64_cells ** 2).sum()))
+
     return {"workload": w.name, "stencil_ms_per_step": ms_cells, "sphere_ms_per_step": ms_sphere,
             "speedup": ms_cells / ms_sphere, "stencil_near_pairs": pairs_cells, "sphere_near_pairs": pairs_sphere,
             "sphere_p": ws.p, "sphere_K": ws.K, "sphere_F": ws.F,
-            "rel_rms_force_diff_vs_stencil_fp64": float(np.sqrt(((f_sphere - f64_cells) ** 2).sum()
-                                                                / (f64_cells ** 2).sum()))}
+            "rel_rms_force_diff_vs_stencil_fp64": rms(f_sphere),
+            "tree": {"ms_per_step": ms_tree, "speedup": ms_cells / ms_tree, "tree_order": 8, "tree_theta": 0.5,
+                     "rel_energy_err_vs_stencil_fp64": abs(e_tree - e64) / abs(e64),
+                     "rel_rms_force_err_vs_stencil_fp64": rms(f_tree)}}
 
 
 def main():
