@@ -81,13 +81,14 @@ typedef struct hsma_params {
                           every admissible R.  Rule 1 sums about a third of
                           the pairs (3D, lambda 1.5) but its far field starts
                           at R, so it needs a higher p for the same error.
-                          2: the 3D cell stencil of rule 0, summed at the
-                          particles by a treecode (multipole expansions of
-                          order tree_order for source nodes that satisfy
-                          (r_node + r_group) < tree_theta * distance, direct
-                          sums elsewhere); check points stay direct.  3D and
-                          FP32C only.  An approximation of rule 0: about
-                          1e-6 relative RMS force error at order 8, theta 0.5 */
+                          2: the stencil of rule 0, summed at the particles
+                          and at the check points by a treecode (multipole
+                          expansions, up to order tree_order, of the source
+                          nodes that satisfy (r_node + r_group) < tree_theta
+                          * distance; direct sums elsewhere).  FP32C only.
+                          An approximation of rule 0: about 3e-6 relative
+                          RMS force error at order 8, theta 0.5 (50,000
+                          ions); order 12 reaches 3e-7                        */
   int M;               /* 2D: image layers above and below                    */
   double gamma_up;     /* 2D: (eps_c - eps_up)/(eps_c + eps_up), |gamma| < 1  */
   double gamma_low;    /* 2D: (eps_c - eps_low)/(eps_c + eps_low)             */
