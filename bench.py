@@ -152,6 +152,13 @@ def serving_bench(hs, workloads, n_systems=256, slots=8, loads=(0.5, 0.8, 0.95),
             out["poisson"].append({"offered_fraction": f, "offered_requests_per_s": lam,
                                    "achieved_requests_per_s": n_systems / span,
                                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
+    # the same mix with the stencil summed by the treecode (saturated rate)
+    prm2 = hs.Params(precision=hs.FP32C, p=8, K=162, F=512, lam=1.5, near_rule=2)
+    with hs.Server(prm2, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots) as sv:
+        run_all(sv)  # warm-up
+        dt2, _ = run_all(sv)
+        out["treecode"] = {"saturated_requests_per_s": n_systems / dt2,
+                           "saturated_particle_steps_per_s": total_particles / dt2}
     return out
 
 
