@@ -111,6 +111,8 @@ struct DevicePlan {
   template <bool CHECKS>
   hsma_status launch_tree(hipStream_t st, long comp, long slot, std::string& err);
   int tree_cwaves_ = 0, tree_csplit_ = 1;  // treecode at the check targets (0: direct check sums)
+  int tree_cgroup0_ = 0;                    // first check group summed by the treecode
+  int tree_cbase_ = 0;                      // direct check waves before the treecode's
   hipStream_t last_stream = nullptr;
 
   void* h_stage = nullptr;       // pinned staging of the check schedule

@@ -1397,7 +1397,8 @@ __device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, fl
 template <int P, bool CHECKS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WAVES))) void k_tree_far(
     const double4* __restrict__ tgt, PartSched ps, const Group* __restrict__ cgroups,
-    const CheckSched* __restrict__ csched, int ncg, int csplit, const Desc* __restrict__ desc, int ntiles,
+    const CheckSched* __restrict__ csched, int cg0, int ncg, int cbase, int csplit, const Desc* __restrict__ desc,
+    int ntiles,
     const double4* __restrict__ tile_c, const float4* __restrict__ tile_h, const float4* __restrict__ src,
     const double4* __restrict__ pos64, const StepParams* __restrict__ sp, TreeLevels tl,
     const double4* __restrict__ node_c,
@@ -1408,10 +1409,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
   long obase;
   const Desc* __restrict__ dtab = desc;
   if constexpr (CHECKS) {
-    // check targets: the check group whose waves include this one (binary
-    // search over the waves' first indices), its own image table
-    const int bid = blockIdx.x;
-    int lo = 0, hi = ncg - 1;
+    // check targets: the check group of [cg0, ncg) whose waves include this
+    // one (binary search over the waves' first indices, which continue
+    // those of the direct check groups before cg0), its own image table
+    const int bid = (int)blockIdx.x + cbase;
+    int lo = cg0, hi = ncg - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (csched[mid].first_work <= bid) lo = mid;
@@ -2257,25 +2259,42 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   std::vector<CheckSched> cs;
   int ncfar = 0, ncslots = 0;
   check_schedule(host.check_groups, ntiles, ctarget, cs, ncfar, ncslots);
-  // treecode at the check targets (near rule 2): `split` waves per (check
-  // group, image entry), each wave its own slot; the row reduction sums the
-  // group's nch + 1 slots
+  // treecode at the check targets (near rule 2) for the groups from gtree
+  // on: on the slab all of them (its 189 image entries per target make the
+  // direct check sums 45 % of the direct step, and the interface groups
+  // are compact patches of the interface grids); in 3D none (the face
+  // groups span a whole face, few nodes pass the opening test for them,
+  // and over the telescoped sets the direct sums were as fast or faster:
+  // 0.22 against 0.45 ms on 50,000 ions).  `split` waves per (check group,
+  // image entry), each wave its own slot, after the direct groups' slots;
+  // the row reduction sums the group's nch + 1 slots
+  // (the face groups come first; with the sphere near set their direct
+  // waves [0, cwork_face_) run in FP64)
+  const int nface = std::min<int>(host.face_groups, (int)cs.size());
+  const int face_waves = nface < (int)cs.size() ? cs[nface].first_work : ncfar;
+  const int gtree = host.prm.geometry == HSMA_GEOM_2D ? 0 : (int)cs.size();
   tree_cwaves_ = 0;
   tree_csplit_ = 1;
-  if (host.prm.near_rule == 2 && !cs.empty()) {
+  tree_cgroup0_ = gtree;
+  tree_cbase_ = ncfar;
+  if (host.prm.near_rule == 2 && gtree < (int)cs.size()) {
+    const int direct_waves = cs[gtree].first_work, direct_slots = cs[gtree].slot0;
     long long nd = 0;
-    for (const Group& g : host.check_groups) nd += g.ndesc;
-    if (nd <= check_target_max) {
-      const int split = (int)std::max<long long>(1, std::min<long long>(kTreeMaxSplit, check_target_max / nd));
+    for (size_t gi = gtree; gi < cs.size(); ++gi) nd += host.check_groups[gi].ndesc;
+    const long long budget = check_target_max - direct_slots;
+    if (nd <= budget) {
+      const int split = (int)std::max<long long>(1, std::min<long long>(kTreeMaxSplit, budget / nd));
       int w = 0;
-      for (size_t gi = 0; gi < cs.size(); ++gi) {
+      for (size_t gi = gtree; gi < cs.size(); ++gi) {
         const int nw = host.check_groups[gi].ndesc * split;
-        cs[gi] = CheckSched{w, nw - 1, 1, w};
+        cs[gi] = CheckSched{direct_waves + w, nw - 1, 1, direct_slots + w};
         w += nw;
       }
-      ncfar = ncslots = w;
+      ncfar = direct_waves + w;
+      ncslots = direct_slots + w;
       tree_cwaves_ = w;
       tree_csplit_ = split;
+      tree_cbase_ = direct_waves;
     }
   }
   const int sch = sphere_chunk(host.prm.F, ps.ngroups);
@@ -2302,7 +2321,7 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   ngroups_ = ps.ngroups;
   psched_ = ps;
   ncwork_ = ncfar;
-  cwork_face_ = host.face_groups < (int)cs.size() ? cs[host.face_groups].first_work : ncfar;
+  cwork_face_ = face_waves;
   nchunks_ = ps.nch;
   nsphere_ = nsc;
   sph_chunk_ = sch;
@@ -2336,7 +2355,8 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, long comp, long slot, std::s
 #define HSMA_TREE_FAR(PP)                                                                                          \
   hipLaunchKernelGGL((k_tree_far<PP, CHECKS>), dim3(grid), dim3(64), 0, st,                                        \
                      CHECKS ? (const double4*)d_check_pos : (const double4*)d_pos64, psched_,                     \
-                     (const Group*)d_check_groups, (const CheckSched*)d_csched, (int)host.check_groups.size(),     \
+                     (const Group*)d_check_groups, (const CheckSched*)d_csched, tree_cgroup0_,                   \
+                     (int)host.check_groups.size(), tree_cbase_,                                                 \
                      tree_csplit_, CHECKS ? (const Desc*)d_desc_check : (const Desc*)d_desc_part, ntiles_,         \
                      (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,                   \
                      (const double4*)d_pos64, (const StepParams*)d_sp, tl, (const double4*)d_tnode,               \
@@ -2514,10 +2534,13 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
         HSMA_CHECKS(double, double4, d_src64, 0, cwork_face_, 0, gf);
         HSMA_CHECKS(float, float4, d_src32, cwork_face_, ncwork_, gf, ncg);
       } else if (tree_cwaves_ > 0) {
-        // treecode at the check targets, then the same row reduction
+        // the groups before tree_cgroup0_ direct (none on the slab), the
+        // rest by the treecode, then the same row reduction
+        const int gf = tree_cgroup0_;
+        HSMA_CHECKS(float, float4, d_src32, 0, tree_cbase_, 0, gf);
         if ((s = launch_tree<true>(st, ccomp, 5L * kGroup, err)) != HSMA_OK) return s;
-        hipLaunchKernelGGL(k_reduce_check<float>, dim3(ncg), dim3(kGroup * kFinParts), 0, st,
-                           (const Group*)d_check_groups, (const CheckSched*)d_csched, 0, (const int*)d_check_axis,
+        hipLaunchKernelGGL(k_reduce_check<float>, dim3(ncg - gf), dim3(kGroup * kFinParts), 0, st,
+                           (const Group*)d_check_groups, (const CheckSched*)d_csched, gf, (const int*)d_check_axis,
                            (const float*)d_cpart, 5L * kGroup, d_v);
       } else {
         HSMA_CHECKS(float, float4, d_src32, 0, ncwork_, 0, ncg);
