@@ -146,7 +146,8 @@ typedef struct hsma_plan_info {
   double cond;           /* condition number estimate of the (scaled) fit       */
   int64_t near_pairs;    /* pair interactions of the last step: particles      */
   int64_t check_pairs;   /*   check targets (sphere near set: counted from the
-                              last step's masks; the call waits for that step) */
+                              last step's masks; the call waits for that step;
+                              treecode: the stencil pairs it approximates)      */
   int64_t surface_pairs; /*   sphere sources                                    */
 } hsma_plan_info;
 hsma_status hsma_plan_get_info(const hsma_plan* plan, hsma_plan_info* info);
