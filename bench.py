@@ -319,7 +319,7 @@ def main():
     ap.add_argument("--no-tree", action="store_true", help="skip the treecode measurement (near_rule=2)")
     ap.add_argument("--workload", default="c2_hsma3d_n50000_fp32c",
                     help="configuration to time (default: the 50,000-ion benchmark system)")
-    ap.add_argument("--near-rule", type=int, default=None, help="override the near set (0 cells, 1 sphere)")
+    ap.add_argument("--near-rule", type=int, default=None, help="override the near set (0 cells, 1 sphere, 2 treecode)")
     ap.add_argument("--p", type=int, default=None, help="override the harmonic degree")
     ap.add_argument("--K", type=int, default=None, help="override the check-point pairs")
     ap.add_argument("--F", type=int, default=None, help="override the sphere points")
