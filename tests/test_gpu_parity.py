@@ -370,8 +370,9 @@ def test_c3_sphere_near_set_sampled():
 
 def test_c5_million_ions_sampled():
     """999,999 ions (2:1 valence) in L = 200, p = 12, F = 1152, K = 800:
-    the FP32 compensated path against the oracle at 128 sampled particles
-    (the oracle's check sums and fit use every particle)."""
+    the FP32 compensated path, with the 27 cells summed directly and by the
+    treecode (order 8, theta 0.5), against the oracle at 128 sampled
+    particles (the oracle's check sums and fit use every particle)."""
     w = workloads.C5
     pos, q, lo, L = workloads.make_system(w)
     sample = np.random.default_rng(7).choice(w.n, 128, replace=False)
@@ -386,6 +387,19 @@ def test_c5_million_ions_sampled():
     assert dp < 1e-5 and df < 1e-5
     assert np.isfinite(e)
     assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())
+    note("[parity] C5 gpu treecode")
+    params = hs.Params.from_workload(w, precision=1)
+    params.near_rule = 2
+    et, pt, ft = run_gpu(params, pos, q, lo, L)
+    dp = np.abs(pt[sample] - r.potential).max() / np.abs(r.potential).max()
+    df = rel_rms(ft[sample], r.force)
+    S = 0.5 * np.abs(q * pot).sum()
+    note(f"   treecode sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}; energy {et:.12g} "
+         f"(direct {e:.12g}, rel {abs(et - e) / abs(e):.2e}, dE/S {abs(et - e) / S:.2e}); "
+         f"force rms rel to direct {rel_rms(ft, f):.2e}")
+    assert dp < TREE_POT and df < 1e-5
+    assert rel_rms(ft, f) <= 1e-5
+    assert abs(et - e) <= fp32_energy_bar(e, S)
 
 
 @pytest.mark.parametrize("near_rule", [0, 1, 2])
