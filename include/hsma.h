@@ -116,10 +116,14 @@ hsma_status hsma_plan_create(const hsma_params* params, const double box_lo[3],
 
 void hsma_plan_destroy(hsma_plan* plan);
 
+/* Particle count of one call: 1 <= n <= 2^30 - 1 with near rule 0, and
+ * n <= 2^26 (2^20 tiles of 64) with near rules 1 and 2.  Larger counts fail
+ * with INVALID_ARG before any buffer is read or any work is enqueued.      */
+
 /* Host-memory call (synchronous).  Validates the input on the host first:
- * n >= 1, finite values, neutrality (NOT_NEUTRAL), slab domain
- * (OUT_OF_DOMAIN).  Positions outside the box are wrapped along periodic
- * axes.                                                                   */
+ * n within the limits above, finite values, neutrality (NOT_NEUTRAL), slab
+ * domain (OUT_OF_DOMAIN).  Positions outside the box are wrapped along
+ * periodic axes.                                                          */
 hsma_status hsma_compute(hsma_plan* plan, int64_t n, const double* xyz, const double* q,
                          double* energy, double* potential, double* force);
 

@@ -38,7 +38,8 @@ typedef struct hsma_server hsma_server;
 typedef struct hsma_server_cfg {
   hsma_params params;     /* method parameters shared by every request            */
   double box_len[3];      /* box shape of the class (requests: s * box_len)       */
-  int64_t max_n;          /* largest particle count a slot must hold              */
+  int64_t max_n;          /* largest particle count a slot must hold (within the
+                             per-call limit of hsma.h, else INVALID_ARG)        */
   int max_slots;          /* upper bound on resident requests                     */
   int64_t hbm_budget;     /* device bytes for the slots' arenas and plans
                              (0: half of the free device memory); the number of

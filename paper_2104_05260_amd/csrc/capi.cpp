@@ -20,6 +20,12 @@ hsma_status fail(hsma_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+
+std::string size_message(const hsma_plan* plan) {
+  const int rule = plan->dev.host.prm.near_rule;
+  return "too many particles for one call (at most " + std::to_string(hsma::max_particles(rule)) +
+         (rule == 0 ? ")" : rule == 1 ? " with the sphere near set)" : " with the treecode)");
+}
 }  // namespace
 
 namespace hsma {
@@ -102,6 +108,7 @@ hsma_status hsma_compute_device(hsma_plan* plan, void* stream, int64_t n, const 
                                 double* d_energy, double* d_potential, double* d_force) {
   if (!plan || !d_xyz || !d_q) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
   if (n < 1) return fail(HSMA_ERR_INVALID_ARG, "n must be >= 1");
+  if (n > hsma::max_particles(plan->dev.host.prm.near_rule)) return fail(HSMA_ERR_INVALID_ARG, size_message(plan));
   std::string msg;
   hsma_status s;
   try {
@@ -131,6 +138,7 @@ hsma_status hsma_compute(hsma_plan* plan, int64_t n, const double* xyz, const do
                          double* potential, double* force) {
   if (!plan || !xyz || !q) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
   if (n < 1) return fail(HSMA_ERR_INVALID_ARG, "n must be >= 1");
+  if (n > hsma::max_particles(plan->dev.host.prm.near_rule)) return fail(HSMA_ERR_INVALID_ARG, size_message(plan));
   const hsma::HostPlan& hp = plan->dev.host;
   {
     std::string msg;

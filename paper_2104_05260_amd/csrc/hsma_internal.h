@@ -19,6 +19,14 @@ constexpr int kTPL = HSMA_TPL;          // targets per lane
 constexpr int kGroup = kWave * kTPL;    // targets per wave (one "target group")
 constexpr int kTile = 64;               // sources per tile
 
+// Particles per call: 32-bit particle indices with headroom; the sphere
+// near set and the treecode pack a tile index into 20 bits (2^20 tiles).
+constexpr int64_t kMaxParticles = ((int64_t)1 << 30) - 1;
+constexpr int64_t kMaxParticlesTiled = (int64_t)kTile << 20;
+inline int64_t max_particles(int near_rule) {
+  return near_rule == 0 ? kMaxParticles : kMaxParticlesTiled;
+}
+
 // One entry of an image table: the source set is every particle mapped by
 //   (x, y, z) -> (x + sx, y + sy, sigma * z + sz)  with charge scaled by `scale`
 // (sigma = +-1).  40 bytes, read by scalar loads on the device.

@@ -172,6 +172,8 @@ hsma_status hsma_server_create(const hsma_server_cfg* cfg, hsma_server** out) {
   *out = nullptr;
   if (cfg->max_n < 1 || cfg->max_slots < 1)
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "max_n and max_slots must be positive");
+  if (cfg->max_n > hsma::max_particles(cfg->params.near_rule))
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "max_n is above the particles one call can take");
   std::unique_ptr<hsma_server> sv(new hsma_server());
   sv->cfg = *cfg;
   std::string msg;

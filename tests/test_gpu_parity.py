@@ -257,6 +257,38 @@ def test_invalid_inputs():
         assert e.value.name == "HSMA_ERR_OUT_OF_DOMAIN"
 
 
+@pytest.mark.parametrize("rule,limit", [(0, (1 << 30) - 1), (1, 1 << 26), (2, 1 << 26)])
+def test_particle_count_limits(rule, limit):
+    """A count above the per-call limit is refused on the host before any
+    buffer is read or any work is enqueued (the buffers passed here hold
+    three particles); a server whose slots would exceed it is refused at
+    creation.  The plan then still computes a valid system."""
+    import ctypes
+    import torch
+    pos, q, lo, L = workloads.small_system(200, (8.0, 8.0, 8.0), 3)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, near_rule=rule)
+    dev = torch.device("cuda:0")
+    x = torch.zeros((3, 3), dtype=torch.float64, device=dev)
+    qq = torch.zeros(3, dtype=torch.float64, device=dev)
+    out = torch.zeros(9, dtype=torch.float64, device=dev)
+    xh, qh = np.zeros((3, 3)), np.zeros(3)
+    with hs.Plan(params, lo, L) as plan:
+        lib = plan._lib
+        vp = lambda t: ctypes.c_void_p(t.data_ptr())
+        st = lib.hsma_compute_device(plan._p, None, limit + 1, vp(x), vp(qq), vp(out), vp(out), vp(out))
+        assert hs.STATUS[st] == "HSMA_ERR_INVALID_ARG"
+        assert b"too many particles" in lib.hsma_last_error()
+        dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        st = lib.hsma_compute(plan._p, limit + 1, dp(xh), dp(qh), None, None, None)
+        assert hs.STATUS[st] == "HSMA_ERR_INVALID_ARG"
+        torch.cuda.synchronize()
+        e, pot, f = plan.compute(pos, q)
+        assert np.isfinite(e) and np.isfinite(f).all()
+    with pytest.raises(hs.HSMAError) as err:
+        hs.Server(params, (8.0, 8.0, 8.0), max_n=limit + 1, max_slots=1)
+    assert err.value.name == "HSMA_ERR_INVALID_ARG"
+
+
 def _sampled_oracle(w, params, pos, q, lo, L, sample):
     """Oracle at full size, evaluated only at the sampled particles (the
     check-point sums and the fit use every particle)."""
