@@ -24,6 +24,9 @@
  *  - Layouts: positions are n x 3 row-major (x0 y0 z0 x1 ...), FP64;
  *    charges n FP64; potential n FP64; force n x 3 FP64; energy 1 FP64.
  *    Any output pointer may be NULL (that output is skipped).
+ *  - Two charges at zero distance (coincident ions, or an ion on a periodic
+ *    image of another) have no finite energy.  This is not checked: the
+ *    call returns OK, and the energy and those ions' outputs are not finite.
  *  - A plan is not thread-safe; distinct plans are independent.  No C++
  *    exception crosses this interface.  On error the call returns a negative
  *    hsma_status and hsma_last_error() describes it.

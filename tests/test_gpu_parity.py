@@ -257,6 +257,29 @@ def test_invalid_inputs():
         assert e.value.name == "HSMA_ERR_OUT_OF_DOMAIN"
 
 
+@pytest.mark.parametrize("prec,rule", [(0, 0), (1, 0), (1, 2)])
+def test_coincident_charges(prec, rule):
+    """Two charges at zero distance (here one ion placed on a periodic image
+    of another, one box length away) have no finite energy: the call
+    completes, the energy and the two ions' forces are not finite, and the
+    plan computes the next, valid system as if nothing had happened."""
+    pos, q, lo, L = workloads.small_system(200, (8.0, 8.0, 8.0), 3)
+    params = hs.Params(precision=prec, p=6, K=100, F=200, lam=1.5, near_rule=rule)
+    bad = pos.copy()
+    i, j = int(np.argmax(q > 0)), int(np.argmax(q < 0))
+    # dyadic coordinates: the wrap of ion j onto ion i is exact
+    bad[i] = lo + np.array([1.5, 2.25, 3.125])
+    bad[j] = bad[i] + np.array([L[0], 0.0, 0.0])
+    with hs.Plan(params, lo, L) as plan:
+        e, pot, f = plan.compute(bad, q)
+        assert not np.isfinite(e)
+        assert not np.isfinite(f[[i, j]]).all()
+        e2, pot2, f2 = plan.compute(pos, q)
+    with hs.Plan(params, lo, L) as fresh:
+        e3, pot3, f3 = fresh.compute(pos, q)
+    assert np.isfinite(e2) and e2 == e3 and np.array_equal(pot2, pot3) and np.array_equal(f2, f3)
+
+
 @pytest.mark.parametrize("rule,limit", [(0, (1 << 30) - 1), (1, 1 << 26), (2, 1 << 26)])
 def test_particle_count_limits(rule, limit):
     """A count above the per-call limit is refused on the host before any
