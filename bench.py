@@ -18,7 +18,8 @@ configuration, optionally with the sphere near set and other p, K, F:
 Besides the throughput it reports the dominant kernel's roofline position
 (FP32 VALU bound; algorithmic 20 flop per near pair over its HIP-event
 duration), the error against the FP64 GPU path and that path's speed, and
-the FP64 CPU oracle timed on a bounded sample as a CPU baseline.
+the FP64 CPU oracle timed as a CPU baseline (one full step when it takes at most
+30 s, else a bounded sample scaled to the step).
 """
 from __future__ import annotations
 
@@ -35,6 +36,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
 FLOP_PER_NEAR_PAIR = 20           # algorithmic convention for one Coulomb pair (potential + field)
+
+
+def progress(msg: str):
+    """One line per phase on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -59,23 +65,49 @@ def measured_traffic(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(w, pos, q, lo, L, sample_n=256):
-    """The FP64 oracle on a bounded sample of the same step: its fixed part
+def cpu_baseline(w, pos, q, lo, L, sample_n=4096, full_limit_s=30.0):
+    """The FP64 oracle timed on the same step.  First its fixed part
     (check-point sums over all particles, least-squares fit, sphere
-    sources) plus the particle sums at `sample_n` particles, extrapolated
-    linearly in the number of particles evaluated."""
+    sources) and the particle sums at `sample_n` particles give an
+    estimate linear in the number of particles evaluated; when that
+    estimate is within `full_limit_s`, one full step (every particle) is
+    then measured and reported, else the estimate is.  A first, untimed
+    call keeps one-time start-up costs out of the fixed part, where they
+    would bias the estimate low."""
     import numpy as np
     from oracle import hsma as ohsma
+
+    def run(targets):
+        # the oracle on the arrays already generated (generation is not timed)
+        if w.geometry == 0:
+            return ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets, w.near_rule)
+        return ohsma.hsma2d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.M, w.gamma_up, w.gamma_low, w.nz,
+                            w.Fw, w.surface_rule, targets, w.near_rule)
+
     rng = np.random.default_rng(11)
+    run(np.arange(1))  # untimed: loads the oracle's C sums and warms its caches
     t0 = time.perf_counter()
-    ohsma.run_workload(w, targets=np.arange(1))
+    run(np.arange(1))
     t1 = time.perf_counter()
     sample = rng.choice(w.n, sample_n, replace=False)
-    ohsma.run_workload(w, targets=sample)
+    run(sample)
     t2 = time.perf_counter()
     fixed = t1 - t0
     per_particle = max((t2 - t1) - fixed, 1e-9) / (sample_n - 1)
     est_step = fixed + per_particle * w.n
+    if est_step <= full_limit_s:
+        t3 = time.perf_counter()
+        r = run(None)
+        step = time.perf_counter() - t3
+        assert np.isfinite(r.energy)
+        how = (f"FP64 oracle: one full step (all {w.n} particles: check sums, fit, sphere sources, "
+               f"particle sums, energy) measured, {step:.1f} s (a {sample_n}-particle sample had estimated "
+               f"{est_step:.1f} s)")
+    else:
+        step = est_step
+        how = (f"FP64 oracle: fixed part (all check sums + fit + sphere sources) {fixed:.2f} s measured, "
+               f"particle sums at {sample_n} sampled particles measured and scaled to all {w.n}; "
+               f"estimated {est_step:.1f} s per step")
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     model = "unknown"
     try:
@@ -87,11 +119,8 @@ def cpu_baseline(w, pos, q, lo, L, sample_n=256):
     except OSError:
         pass
     return {
-        "value": w.n / est_step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-        "cpu_model": model, "nproc": os.cpu_count(),
-        "sample": (f"FP64 oracle: fixed part (all check sums + fit + sphere sources) {fixed:.2f} s measured, "
-                   f"particle sums at {sample_n} sampled particles measured and scaled to all {w.n}; "
-                   f"estimated {est_step:.1f} s per step"),
+        "value": w.n / step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+        "cpu_model": model, "nproc": os.cpu_count(), "sample": how,
     }
 
 
@@ -374,6 +403,7 @@ def main():
         print(json.dumps({"profile_pass": True, "copy_bytes": 512 * 1024 * 1024, "steps": args.warmup + args.steps}))
         return
 
+    progress(f"{w.name}: {args.warmup} warm-up + {args.steps} timed steps")
     for _ in range(args.warmup):
         plan.compute_device(x, qq, en, pot, f)
     torch.cuda.synchronize()
@@ -434,7 +464,9 @@ def main():
             "flop_per_launch": near_flop, "pairs_per_launch": info["near_pairs"],
         },
     }
+    progress(f"timed: {ms:.3f} ms per step")
     if not args.no_fp64:
+        progress("FP64 path")
         p64 = hs.Plan(hs.Params.from_workload(w, precision=hs.FP64), lo, L)
         p64.compute_device(x, qq, en, pot, f)
         torch.cuda.synchronize()
@@ -456,15 +488,19 @@ def main():
         p64.close()
     plan.close()
     if not args.no_sphere_rule:
+        progress("sphere near set (50,000 ions, then the slab)")
         out["sphere_near_set"] = sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
                                                    None if args.no_fp64 else f64)
         out["sphere_near_set_slab"] = slab_near_sets_bench(hs, workloads)
     if not args.no_tree:
+        progress("treecode (50,000 and 999,999 ions)")
         out["tree_near_set"] = tree_rule_bench(hs, workloads, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
                                                None if args.no_fp64 else e64, None if args.no_fp64 else f64)
     if not args.no_serving:
+        progress("serving mix")
         out["serving"] = serving_bench(hs, workloads)
     if not args.no_cpu_baseline:
+        progress("CPU oracle (bounded: a sample, then one full step if it fits 30 s)")
         out["cpu_baseline"] = cpu_baseline(w, pos, q, lo, L)
     print(json.dumps(out), flush=True)
 
