@@ -370,8 +370,6 @@ __global__ __launch_bounds__(64) void k_tiles(int n, const int* __restrict__ ord
 // over contiguous shares of the key range, and the counts are added.  The
 // tiles are then built from the order by k_tiles.
 constexpr int kSmallSort = 4096;
-// largest system whose check chain overlaps its particle sums (side stream)
-constexpr int kOverlapMaxN = 32768;
 constexpr int kRankWaves = 16;
 
 __global__ __launch_bounds__(kWave * kRankWaves) void k_rank(int n, int nblk, const double* __restrict__ red,
@@ -2503,27 +2501,23 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
                        host.prm.coulomb_k, (const int*)d_status, d_pot, d_force, d_epart);                          \
   } while (0)
   // The check sums, the fit and the sphere sources depend only on the
-  // tiles, as do the near-set sums at the particles.  For systems up to
-  // kOverlapMaxN particles the first chain runs on a side stream, forked
-  // from and joined back into the call's stream (event edges, so a captured
-  // step graph holds all branches), while the far particle sums run on the
-  // call's stream (and, above kSmallSort particles, the near pass on a
-  // second side stream): the chain's small, latency-bound kernels and the
-  // near waves then overlap the far waves.  Larger systems fill the GPU with
-  // the particle sums alone; there everything runs in order on the call's
-  // stream.
-  const bool overlap = n <= kOverlapMaxN;
+  // tiles, as do the near-set sums at the particles.  The first chain runs
+  // on a side stream, forked from and joined back into the call's stream
+  // (event edges, so a captured step graph holds all branches), while the
+  // far particle sums run on the call's stream (and, above kSmallSort
+  // particles, the near pass on a second side stream): the chain's small,
+  // latency-bound kernels and the near waves then fill what the far waves
+  // leave idle, at every size (50,000 ions: 20.40 -> 20.04 ms per step;
+  // 200,000: 313.0 -> 312.1 ms; identical results).
   // the near pass (latency-bound waves) gets a second side stream where it
   // is long enough to pay for the extra fork and join
-  const bool near_side = overlap && n > kSmallSort;
+  const bool near_side = n > kSmallSort;
   {
-    if (overlap) {
-      HIPCHK(hipEventRecord(ev_fork, st));
-      HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
-      if (near_side) HIPCHK(hipStreamWaitEvent(side_near, ev_fork, 0));
-    }
+    HIPCHK(hipEventRecord(ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(side, ev_fork, 0));
+    if (near_side) HIPCHK(hipStreamWaitEvent(side_near, ev_fork, 0));
     {
-      const hipStream_t st = overlap ? side : stream_arg;  // where the check chain's launches go
+      const hipStream_t st = side;  // where the check chain's launches go
       if ((s = record(st, kStCheck, 0, err)) != HSMA_OK) return s;
       if (fp64) {
         HSMA_CHECKS(double, double4, d_src64, 0, ncwork_, 0, ncg);
@@ -2551,14 +2545,14 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
       hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
                          (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,
                          d_surf32, d_surf64, d_qd);
-      if (overlap) HIPCHK(hipEventRecord(ev_join, st));
+      HIPCHK(hipEventRecord(ev_join, st));
     }
   }
   const hipStream_t nst = near_side ? side_near : stream_arg;
   if (fp64) HSMA_PARTICLES_NEAR(double, double4, d_src64, nst);
   else HSMA_PARTICLES_NEAR(float, float4, d_src32, nst);
   if (near_side) HIPCHK(hipEventRecord(ev_join_near, side_near));
-  if (overlap) HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+  HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
   if (near_side) HIPCHK(hipStreamWaitEvent(st, ev_join_near, 0));
   if (fp64) HSMA_PARTICLES_SPHERE(double);
   else HSMA_PARTICLES_SPHERE(float);
