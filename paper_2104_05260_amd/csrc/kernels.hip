@@ -2494,14 +2494,18 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     hipLaunchKernelGGL(k_pair_sphere<Real>, dim3(ngroups_, nsphere_), dim3(64), 0, st, (const double4*)d_pos64, n,  \
                        (const double4*)d_surf64, F, sph_chunk_, (Real*)d_part, comp, nchunks_ + psched_.nnear);     \
     if ((s = record(st, kStSphere, 1, err)) != HSMA_OK) return s;                                                   \
+  } while (0)
+#define HSMA_FINALIZE(Real)                                                                                         \
+  do {                                                                                                              \
     hipLaunchKernelGGL(k_finalize<Real>, dim3(nfin), dim3(kWave * fparts), 0, st, n,                              \
                        nchunks_ + psched_.nnear + nsphere_,                                                         \
                        (const Real*)d_part, comp, (const double4*)d_pos64, (const int*)d_perm,                     \
                        (const Desc*)d_desc_part, (int)host.desc_particles.size(), cullp, ntiles_,                   \
                        host.prm.coulomb_k, (const int*)d_status, d_pot, d_force, d_epart);                          \
   } while (0)
-  // The check sums, the fit and the sphere sources depend only on the
-  // tiles, as do the near-set sums at the particles.  The first chain runs
+  // The check sums, the fit, the sphere sources and the sphere sums at the
+  // particles depend only on the tiles, as do the near-set sums at the
+  // particles.  The first chain runs
   // on a side stream, forked from and joined back into the call's stream
   // (event edges, so a captured step graph holds all branches), while the
   // far particle sums run on the call's stream (and, above kSmallSort
@@ -2545,6 +2549,10 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
       hipLaunchKernelGGL(k_sphere_sources, dim3((F + 63) / 64), dim3(64), 0, st, F, host.nb, (const double*)d_SQ,
                          (const double*)d_SD, (const double*)d_A, (const double*)d_ysurf, (const double*)d_nsurf,
                          d_surf32, d_surf64, d_qd);
+      // the sphere sums at the particles follow on the same side stream
+      // (their own slots; only k_finalize reads them)
+      if (fp64) HSMA_PARTICLES_SPHERE(double);
+      else HSMA_PARTICLES_SPHERE(float);
       HIPCHK(hipEventRecord(ev_join, st));
     }
   }
@@ -2554,11 +2562,12 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   if (near_side) HIPCHK(hipEventRecord(ev_join_near, side_near));
   HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
   if (near_side) HIPCHK(hipStreamWaitEvent(st, ev_join_near, 0));
-  if (fp64) HSMA_PARTICLES_SPHERE(double);
-  else HSMA_PARTICLES_SPHERE(float);
+  if (fp64) HSMA_FINALIZE(double);
+  else HSMA_FINALIZE(float);
 #undef HSMA_CHECKS
 #undef HSMA_PARTICLES_NEAR
 #undef HSMA_PARTICLES_SPHERE
+#undef HSMA_FINALIZE
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, nfin, (const double*)d_epart,
                      d_energy ? d_energy : d_energy_scratch);
   HIPCHK(hipGetLastError());
