@@ -471,8 +471,15 @@ struct CullView {
 // Coordinates: targets are kept as offsets from their group's box centre;
 // each tile contributes the FP32-rounded FP64 shift between its image
 // centre and the group centre, so close pairs subtract small numbers.
-// Accumulation: plain sums within a tile, error-free (2Sum) folding of the
-// tile partials into a (hi, lo) potential across tiles.
+// Accumulation: the potential terms q / r (FP32 pair arithmetic) are
+// summed in FP64, one conversion and one FP64 add per pair.  Without it the
+// rounding of the FP32 running sum inside a tile, whose partial sums grow
+// like a random walk of +-q/r terms, was the largest error of the energy
+// (about 3.5x the pair terms' own rounding in an emulation of this loop on
+// the 20,000-ion slab); measured against the FP64 path the relative energy
+// error went from 7.0e-7 / 2.45e-6 / 5.5e-8 to 4.1e-7 / 6.3e-7 / 2.7e-7
+// on the 50,000-ion, slab and 999,999-ion systems, for 8 % of the loop's
+// throughput.  The field (bar 1e-5) keeps FP32 sums.
 //
 // The work is split by distance.  A (tile, image) whose bounding box stays
 // at least rc from the group's ("far") goes through the FAR kernel, a plain
@@ -605,13 +612,17 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   mnz = wave_min(mnz); mxz = wave_max(mxz);
   const double cgx = 0.5 * (mnx + mxx), cgy = 0.5 * (mny + mxy), cgz = 0.5 * (mnz + mxz);
   const double hgx = 0.5 * (mxx - mnx), hgy = 0.5 * (mxy - mny), hgz = 0.5 * (mxz - mnz);
-  Real ph[kTPL], pl[kTPL], ex[kTPL], ey[kTPL], ez[kTPL];
+  // potential: FP64 accumulator per target (the pair terms are summed into
+  // it in FP64, so the sum adds no rounding of its own); field: Real
+  double ph[kTPL];
+  Real ex[kTPL], ey[kTPL], ez[kTPL];
 #pragma unroll
   for (int j = 0; j < kTPL; ++j) {
     ox[j] = (Real)(tp[j].x - cgx);
     oy[j] = (Real)(tp[j].y - cgy);
     oz[j] = (Real)(tp[j].z - cgz);
-    ph[j] = pl[j] = ex[j] = ey[j] = ez[j] = (Real)0;
+    ph[j] = 0.0;
+    ex[j] = ey[j] = ez[j] = (Real)0;
   }
   const int tbase = g.first + lane;  // sorted index of this lane's first target
 
@@ -623,13 +634,15 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     const Real sg = (Real)ds.sigma;
     const Real sc = (Real)ds.scale;
     Real ux[kTPL], uy[kTPL], uz[kTPL];
-    Real pp[kTPL], qx[kTPL], qy[kTPL], qz[kTPL];
+    Real qx[kTPL], qy[kTPL], qz[kTPL];
+    double pp[kTPL];
 #pragma unroll
     for (int j = 0; j < kTPL; ++j) {
       ux[j] = ox[j] - (Real)dlx;
       uy[j] = oy[j] - (Real)dly;
       uz[j] = sg * (oz[j] - (Real)dlz);
-      pp[j] = qx[j] = qy[j] = qz[j] = (Real)0;
+      pp[j] = 0.0;
+      qx[j] = qy[j] = qz[j] = (Real)0;
     }
     const S* __restrict__ s = src + (long)tile * kTile;
     if (!NEAR && PARTICLES && own) {
@@ -648,7 +661,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           const Real r2 = self ? (Real)1 : dx * dx + dy * dy + dz * dz;
           const Real ri = rsq(r2);
           const Real a = (drop ? (Real)0 : (Real)v.w) * ri;
-          pp[j] += a;
+          pp[j] += (double)a;
           const Real b = a * (ri * ri);
           qx[j] += b * dx;
           qy[j] += b * dy;
@@ -679,7 +692,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
             const Real r2 = dx * dx + dy * dy + dz * dz;
             const Real ri = rsq(r2);
             const Real a = qv * ri;
-            pp[j] += a;
+            pp[j] += (double)a;
             const Real b = a * (ri * ri);
             qx[j] += b * dx;
             qy[j] += b * dy;
@@ -719,7 +732,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
           }
           const Real ri = rsq(r2);
           const Real a = qq * ri;
-          pp[j] += a;
+          pp[j] += (double)a;
           const Real b = a * (ri * ri);
           qx[j] += b * dx;
           qy[j] += b * dy;
@@ -729,15 +742,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
     }
 #pragma unroll
     for (int j = 0; j < kTPL; ++j) {
-      const Real t = sc * pp[j];
-      if constexpr (sizeof(Real) == 4) {
-        float hs2, e;
-        two_sum(ph[j], t, hs2, e);
-        ph[j] = hs2;
-        pl[j] += e;
-      } else {
-        ph[j] += t;
-      }
+      ph[j] += ds.scale * pp[j];
       ex[j] += sc * qx[j];
       ey[j] += sc * qy[j];
       ez[j] += (sc * sg) * qz[j];
@@ -926,8 +931,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   for (int j = 0; j < kTPL; ++j) {
     if (!valid[j]) continue;
     const long o = (long)w.slot * slot_stride + (PARTICLES ? (long)g.first : 0L) + j * kWave + lane;
-    part[o] = ph[j];
-    part[o + comp_stride] = pl[j];
+    // potential as an unevaluated (hi, lo) pair of Real
+    const Real hi = (Real)ph[j];
+    part[o] = hi;
+    part[o + comp_stride] = (Real)(ph[j] - (double)hi);
     part[o + 2 * comp_stride] = ex[j];
     part[o + 3 * comp_stride] = ey[j];
     part[o + 4 * comp_stride] = ez[j];

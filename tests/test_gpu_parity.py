@@ -43,21 +43,23 @@ def oracle_run(params, pos, q, lo, L, targets=None):
 
 # FP64 path: agreement to 1e-10 relative (energy, potentials, forces).
 # FP32 compensated path: 1e-5 relative RMS force and max potential, and
-# |dE| <= 1e-6 |E| + 1e-7 S with S = 1/2 sum |q_i Phi_i|.  The second term
-# is the rounding floor of FP32 pair terms: every term q_j / r carries a
-# few units of FP32 rounding (coordinates, r^2, the reciprocal square
-# root), independent from pair to pair, so the energy error is a random
-# walk over the pair terms that scales with S, not with E; the energy of a
-# random placement is a small remainder of its terms (|E| / S = 2.4e-3 at
-# 50,000 ions, 0.05 at 1000).  Measured |dE| / S: 2e-9 to 5e-9 at 50,000
-# ions, up to 6e-8 at 1000 (the same with FP64 accumulation inside a tile,
-# so the pair terms themselves set the floor).
+# the energy to 1e-6 relative (FP32C_E) on every benchmark system (100,
+# 50,000, the 20,000-ion slab and 999,999 ions; measured 1.3e-7 to 6.3e-7).
+# Small random test systems (the ragged sizes, the boundary and clustered
+# cases) have energies that are a small remainder of their terms (|E| / S
+# = 0.02 to 0.05 at 1000 ions, S = 1/2 sum |q_i Phi_i|), and every pair
+# term carries a few units of FP32 rounding that does not cancel, so the
+# energy error is a random walk that scales with S, not with E.  For those
+# systems the bar is 1e-6 |E| + FP32_E_FLOOR S.
 TOL64 = 1e-10
+FP32C_E = 1e-6
 FP32_E_FLOOR = 1e-7
 
 
 def fp32_energy_bar(E, S):
-    return 1e-6 * abs(E) + FP32_E_FLOOR * S
+    """Energy bar of the small cancelling test systems (not used for the
+    benchmark systems, which are held to FP32C_E |E|)."""
+    return FP32C_E * abs(E) + FP32_E_FLOOR * S
 
 
 # Treecode (near rule 2) against the oracle's exact 27-cell sums: the FP32
@@ -67,7 +69,10 @@ def fp32_energy_bar(E, S):
 TREE_POT = 5e-5
 
 
-def check(params, pos, q, lo, L, fp32=False, label="", pot_bar=1e-5):
+def check(params, pos, q, lo, L, fp32=False, label="", pot_bar=1e-5, cancel_floor=True):
+    """GPU against oracle on the whole system.  cancel_floor: the FP32 energy
+    bar of the small cancelling test systems (fp32_energy_bar); False holds
+    the energy to FP32C_E |E| alone."""
     note(f"[parity] {label} n={len(q)} geometry={params.geometry} precision={params.precision}")
     e, pot, f = run_gpu(params, pos, q, lo, L)
     r = oracle_run(params, pos, q, lo, L)
@@ -79,7 +84,7 @@ def check(params, pos, q, lo, L, fp32=False, label="", pot_bar=1e-5):
          f"force rms rel {df:.2e}, max rel {dfmax:.2e}")
     if fp32:
         S = 0.5 * np.abs(q * r.potential).sum()
-        bar = fp32_energy_bar(r.energy, S)
+        bar = fp32_energy_bar(r.energy, S) if cancel_floor else FP32C_E * abs(r.energy)
         note(f"   energy scale S {S:.6g}; |dE| {abs(e - r.energy):.3g}, bar {bar:.3g}; |dE|/S {abs(e - r.energy) / S:.2e}")
         assert abs(e - r.energy) <= bar and df <= 1e-5 and dp <= pot_bar
     else:
@@ -96,7 +101,8 @@ def test_c1_fp64_matches_oracle():
 def test_c1_fp32c_matches_oracle():
     w = workloads.C1
     pos, q, lo, L = workloads.make_system(w)
-    check(hs.Params.from_workload(w, precision=hs.FP32C), pos, q, lo, L, fp32=True, label="C1 fp32c")
+    check(hs.Params.from_workload(w, precision=hs.FP32C), pos, q, lo, L, fp32=True, label="C1 fp32c",
+          cancel_floor=False)
 
 
 @pytest.mark.parametrize("n", [2, 64, 130, 1000, 4096, 4098])
@@ -340,13 +346,10 @@ def test_c2_full_size_sampled():
         else:
             assert dp < 1e-5 and df < 1e-5
     e32, e64 = res[1][0], res[0][0]
-    # energy bar 1e-6 |E| + 1e-7 S (here |E|/S ~ 2.4e-3: the energy of a
-    # random placement is a 0.2 % remainder of its terms)
     S = 0.5 * np.abs(q * res[0][1]).sum()
     note(f"   energy fp32c {e32:.12g} fp64 {e64:.12g} rel {abs(e32 - e64) / abs(e64):.2e}; "
          f"S {S:.6g}, |E|/S {abs(e64) / S:.2e}, dE/S {abs(e32 - e64) / S:.2e}")
-    assert abs(e32 - e64) <= fp32_energy_bar(e64, S)
-    assert abs(e32 - e64) <= 1e-5 * abs(e64)
+    assert abs(e32 - e64) <= FP32C_E * abs(e64)
     assert rel_rms(res[1][2], res[0][2]) <= 1e-5
     # net force of a periodic system vanishes within the method error
     assert np.abs(res[0][2].sum(0)).max() <= 1e-4 * np.sqrt((res[0][2] ** 2).sum())
@@ -397,7 +400,7 @@ def test_c3_slab_full_size_sampled():
     S = 0.5 * np.abs(q * res[0][1]).sum()
     note(f"   energy fp32c {e32:.12g} fp64 {e64:.12g} rel {abs(e32 - e64) / abs(e64):.2e}; S {S:.6g}, "
          f"dE/S {abs(e32 - e64) / S:.2e}")
-    assert abs(e32 - e64) <= fp32_energy_bar(e64, S)
+    assert abs(e32 - e64) <= FP32C_E * abs(e64)
     assert rel_rms(res[1][2], res[0][2]) <= 1e-5
     # in-plane net force vanishes within the method error
     f64 = res[0][2]
@@ -424,37 +427,49 @@ def test_c3_sphere_near_set_sampled():
 
 
 def test_c5_million_ions_sampled():
-    """999,999 ions (2:1 valence) in L = 200, p = 12, F = 1152, K = 800:
-    the FP32 compensated path, with the 27 cells summed directly and by the
-    treecode (order 8, theta 0.5), against the oracle at 128 sampled
-    particles (the oracle's check sums and fit use every particle)."""
+    """999,999 ions (2:1 valence) in L = 200, p = 12, F = 1152, K = 800: the
+    FP64 and FP32 compensated paths with the 27 cells summed directly, and
+    the FP32 path with the treecode, against the oracle at 128 sampled
+    particles (the oracle's check sums and fit use every particle); the
+    FP32 energy against the FP64 path's over the whole system."""
     w = workloads.C5
     pos, q, lo, L = workloads.make_system(w)
     sample = np.random.default_rng(7).choice(w.n, 128, replace=False)
-    note("[parity] C5 gpu fp32c")
-    e, pot, f = run_gpu(hs.Params.from_workload(w, precision=1), pos, q, lo, L)
     note("[parity] C5 oracle (sampled)")
     r = _sampled_oracle(w, hs.Params.from_workload(w), pos, q, lo, L, sample)
-    dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
-    df = rel_rms(f[sample], r.force)
-    dfm = np.abs(f[sample] - r.force).max() / np.abs(r.force).max()
-    note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}, force max rel {dfm:.2e}")
-    assert dp < 1e-5 and df < 1e-5
-    assert np.isfinite(e)
-    assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())
+    res = {}
+    for prec in (1, 0):
+        note(f"[parity] C5 gpu precision={prec}")
+        e, pot, f = run_gpu(hs.Params.from_workload(w, precision=prec), pos, q, lo, L)
+        res[prec] = (e, pot, f)
+        dp = np.abs(pot[sample] - r.potential).max() / np.abs(r.potential).max()
+        df = rel_rms(f[sample], r.force)
+        dfm = np.abs(f[sample] - r.force).max() / np.abs(r.force).max()
+        note(f"   sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}, force max rel {dfm:.2e}")
+        if prec == 0:
+            assert dp < 1e-10 and df < 1e-10
+        else:
+            assert dp < 1e-5 and df < 1e-5
+        assert np.isfinite(e)
+        assert np.abs(f.sum(0)).max() <= 1e-3 * np.sqrt((f ** 2).sum())
+    (e, pot, f), (e64, pot64, f64) = res[1], res[0]
+    S = 0.5 * np.abs(q * pot64).sum()
+    note(f"   energy fp32c {e:.12g} fp64 {e64:.12g} rel {abs(e - e64) / abs(e64):.2e}; dE/S {abs(e - e64) / S:.2e}; "
+         f"force rms rel {rel_rms(f, f64):.2e}")
+    assert abs(e - e64) <= FP32C_E * abs(e64)
+    assert rel_rms(f, f64) <= 1e-5
     note("[parity] C5 gpu treecode")
     params = hs.Params.from_workload(w, precision=1)
     params.near_rule = 2
     et, pt, ft = run_gpu(params, pos, q, lo, L)
     dp = np.abs(pt[sample] - r.potential).max() / np.abs(r.potential).max()
     df = rel_rms(ft[sample], r.force)
-    S = 0.5 * np.abs(q * pot).sum()
     note(f"   treecode sampled: potential max rel {dp:.2e}, force rms rel {df:.2e}; energy {et:.12g} "
-         f"(direct {e:.12g}, rel {abs(et - e) / abs(e):.2e}, dE/S {abs(et - e) / S:.2e}); "
-         f"force rms rel to direct {rel_rms(ft, f):.2e}")
+         f"(fp64 direct {e64:.12g}, rel {abs(et - e64) / abs(e64):.2e}, dE/S {abs(et - e64) / S:.2e}); "
+         f"force rms rel to fp64 direct {rel_rms(ft, f64):.2e}")
     assert dp < TREE_POT and df < 1e-5
-    assert rel_rms(ft, f) <= 1e-5
-    assert abs(et - e) <= fp32_energy_bar(e, S)
+    assert rel_rms(ft, f64) <= 1e-5
+    assert abs(et - e64) <= fp32_energy_bar(e64, S)
 
 
 @pytest.mark.parametrize("near_rule", [0, 1, 2])
