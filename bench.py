@@ -1,25 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the HSMA hot path on one MI355X.
 
-One step = one full evaluation (energy, potentials, forces) of the 50,000-ion
-periodic electrolyte (L = 60, 0.5 minimum spacing, p = 10, F = 800, K = 400,
-27 near cells) in the FP32-compensated path, inputs resident in HBM: ingest
-and sort, check-point sums, least-squares fit, sphere sources, particle
-near-set and sphere sums, forces and energy.  Prints one JSON line.
+One step = one full evaluation (energy, potentials, forces) of the largest
+single-GPU system: 999,999 ions of a 2:1 electrolyte (+2 / -1) in a periodic
+box L = 200, p = 12, F = 1152, K = 800, lambda 1.5, 27 near cells summed
+directly, in the FP32-compensated path, inputs resident in HBM: ingest and
+sort, check-point sums, least-squares fit, sphere sources, particle near-set
+and sphere sums, forces and energy.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-For profiling the other workloads the same timed loop runs on any named
-configuration, optionally with the sphere near set and other p, K, F:
-
-  python bench.py --workload c3_hsma2d_n20000_slab [--near-rule 1 --p 14 --K 450 --F 1152]
-  python bench.py --workload c5_hsma3d_n999999_2to1 --near-rule 2   (treecode)
-
 Besides the throughput it reports the dominant kernel's roofline position
 (FP32 VALU bound; algorithmic 20 flop per near pair over its HIP-event
-duration), the error against the FP64 GPU path and that path's speed, and
-the FP64 CPU oracle timed as a CPU baseline (one full step when it takes at most
-30 s, else a bounded sample scaled to the step).
+duration), the error against the FP64 GPU path on the same system and that
+path's speed, the same system with the 27 cells summed by the treecode, the
+50,000-ion system (27 cells; its FP64 path, the sphere near set, the
+treecode, the slab's near sets), the serving mix, and the FP64 CPU oracle
+timed as a CPU baseline (a bounded sample scaled to the step).
+
+For profiling, the same timed loop runs alone on any named configuration,
+optionally with another near set and other p, K, F:
+
+  python bench.py --workload c2_hsma3d_n50000_fp32c
+  python bench.py --workload c3_hsma2d_n20000_slab [--near-rule 1 --p 14 --K 450 --F 1152]
+  python bench.py --workload c5_hsma3d_n999999_2to1 --near-rule 2   (treecode)
 """
 from __future__ import annotations
 
@@ -222,65 +226,6 @@ def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells,
     return out
 
 
-def tree_rule_bench(hs, workloads, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells, e64, f64_cells,
-                    steps=10):
-    """The 27-cell sums at the particles by the treecode (near_rule=2,
-    multipole order 8, opening parameter 0.5; and order 12), FP32
-    compensated, on the same system: time, and error against the FP64
-    27-cell result; then the 999,999-ion system at order 8 (timing only:
-    its 27-cell step takes seconds)."""
-    import numpy as np
-    import torch
-    params = hs.Params.from_workload(w, precision=hs.FP32C)
-    params.near_rule = 2
-
-    def timed(pp, xx, qv, ee, pt, ff, k):
-        plan = hs.Plan(pp, lo_, L_)
-        for _ in range(2):
-            plan.compute_device(xx, qv, ee, pt, ff)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(k):
-            plan.compute_device(xx, qv, ee, pt, ff)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        plan.close()
-        return ev0.elapsed_time(ev1) / k
-
-    lo_, L_ = lo, L
-
-    def entry(pp):
-        ms = timed(pp, x, qq, en, pot, f, steps)
-        o = {"near_rule": 2, "tree_order": pp.tree_order, "tree_theta": pp.tree_theta,
-             "precision": "fp32-compensated", "ms_per_step": ms, "particle_steps_per_s": w.n / (ms * 1e-3),
-             "speedup_vs_27_cells": ms_cells / ms}
-        if f64_cells is not None:
-            fs = f.cpu().numpy()
-            o["rel_energy_err_vs_27_cells_fp64"] = abs(en.item() - e64) / abs(e64)
-            o["rel_rms_force_err_vs_27_cells_fp64"] = float(np.sqrt(((fs - f64_cells) ** 2).sum()
-                                                                    / (f64_cells ** 2).sum()))
-        return o
-
-    out = entry(params)
-    # order 12: inside 1e-6 relative energy as well
-    import dataclasses
-    out["order12"] = entry(dataclasses.replace(params, tree_order=12))
-    w5 = workloads.C5
-    pos5, q5, lo_, L_ = workloads.make_system(w5)
-    dev = x.device
-    x5 = torch.tensor(pos5, device=dev)
-    q5t = torch.tensor(q5, device=dev)
-    pot5 = torch.zeros(w5.n, dtype=torch.float64, device=dev)
-    f5 = torch.zeros((w5.n, 3), dtype=torch.float64, device=dev)
-    p5 = hs.Params.from_workload(w5, precision=hs.FP32C)
-    p5.near_rule = 2
-    ms5 = timed(p5, x5, q5t, en, pot5, f5, 5)
-    out["large"] = {"workload": w5.name, "n": w5.n, "ms_per_step": ms5, "particle_steps_per_s": w5.n / (ms5 * 1e-3)}
-    del x5, q5t, pot5, f5
-    return out
-
-
 def slab_near_sets_bench(hs, workloads, steps=5):
     """The 20,000-ion slab with the near sets: the 189-entry stencil at the
     workload's p = 10, the sphere near set at p = 14 (K = 450, F = 1152),
@@ -335,19 +280,100 @@ def slab_near_sets_bench(hs, workloads, steps=5):
                      "rel_rms_force_err_vs_stencil_fp64": rms(f_tree)}}
 
 
+def timed_loop(hs, w, lo, L, x, qq, en, pot, f, steps, warmup, stream):
+    """W untimed warm-up steps, then exactly K steps on `stream` between two
+    device synchronisations; one HIP event between consecutive steps (no
+    synchronisation inside the timed region).  The plan's stage events
+    (HIP events on the call's stream) give the dominant kernel's time."""
+    import numpy as np
+    import torch
+    plan = hs.Plan(hs.Params.from_workload(w, precision=hs.FP32C), lo, L)
+    for _ in range(warmup):
+        plan.compute_device(x, qq, en, pot, f)
+    torch.cuda.synchronize()
+    if plan.device_status() != 0:
+        raise SystemExit("device-side validation failed")
+    plan.set_timing(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(steps):
+        plan.compute_device(x, qq, en, pot, f)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter()
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+    tm = plan.timing()
+    info = plan.info()
+    plan.close()
+    calls = max(1, tm["calls"])
+    near_ms = tm["near_ms"] / calls
+    near_flop = FLOP_PER_NEAR_PAIR * info["near_pairs"]
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    return {
+        "ms": ms, "median": float(np.median(per_step)), "p90": float(np.percentile(per_step, 90)),
+        "wall_ms": (wall1 - wall0) * 1e3 / steps, "near_ms": near_ms, "info": info,
+        "stage_ms": {"step": tm["step_ms"] / calls, "near": near_ms, "check": tm["check_ms"] / calls,
+                     "sphere": tm["sphere_ms"] / calls},
+        "achieved_tflops": near_flop / (near_ms * 1e-3) / 1e12, "near_flop": near_flop,
+    }
+
+
+def roofline(w, r):
+    return {
+        "kernel": "k_pair<float,false,true> (far near-set sums at the particles)",
+        "bound": "alu", "achieved": r["achieved_tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+        "frac": r["achieved_tflops"] / PEAK_FP32_TFLOPS,
+        "traffic": measured_traffic("k_pair_float_particles", w.name),
+        "flop_per_launch": r["near_flop"], "pairs_per_launch": r["info"]["near_pairs"],
+        "flop_per_pair": FLOP_PER_NEAR_PAIR, "launch_ms": r["near_ms"],
+    }
+
+
+def fp64_leg(hs, w, lo, L, x, qq, en, pot, f, e32, f32, ms32, stream, steps=1):
+    """The plain FP64 single-system GPU path on the same system: one call to
+    warm the plan where it is cheap, then `steps` timed calls; its energy
+    and forces are the reference of the FP32-compensated result."""
+    import numpy as np
+    import torch
+    p64 = hs.Plan(hs.Params.from_workload(w, precision=hs.FP64), lo, L)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if w.n <= 100_000:
+        p64.compute_device(x, qq, en, pot, f)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        p64.compute_device(x, qq, en, pot, f)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    p64.close()
+    ms64 = ev0.elapsed_time(ev1) / steps
+    e64 = en.item()
+    f64 = f.cpu().numpy()
+    return {
+        "ms_per_step": ms64, "speedup_fp32c_over_fp64": ms64 / ms32,
+        "rel_energy_err": abs(e32 - e64) / abs(e64),
+        "rel_rms_force_err": float(np.sqrt(((f32 - f64) ** 2).sum() / (f64 ** 2).sum())),
+        "max_force_err_rel_to_max": float(np.abs(f32 - f64).max() / np.abs(f64).max()),
+    }, e64, f64
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix measurement")
     ap.add_argument("--no-sphere-rule", action="store_true",
                     help="skip the sphere-near-set measurement (near_rule=1 at matched accuracy)")
     ap.add_argument("--no-tree", action="store_true", help="skip the treecode measurement (near_rule=2)")
-    ap.add_argument("--workload", default="c2_hsma3d_n50000_fp32c",
-                    help="configuration to time (default: the 50,000-ion benchmark system)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 50,000-ion system and every other secondary measurement")
+    ap.add_argument("--workload", default="c5_hsma3d_n999999_2to1",
+                    help="configuration to time (default: the 999,999-ion system, the largest one)")
     ap.add_argument("--near-rule", type=int, default=None, help="override the near set (0 cells, 1 sphere, 2 treecode)")
     ap.add_argument("--p", type=int, default=None, help="override the harmonic degree")
     ap.add_argument("--K", type=int, default=None, help="override the check-point pairs")
@@ -376,12 +402,12 @@ def main():
     w = workloads.CONFIGS[args.workload]
     over = {k: v for k, v in (("near_rule", args.near_rule), ("p", args.p), ("K", args.K), ("F", args.F))
             if v is not None}
-    default_run = args.workload == workloads.C2.name and not over
+    default_run = args.workload == workloads.C5.name and not over
     if over:
         w = dataclasses.replace(w, **over)
     if not default_run:
         # a profiling run of another configuration: the timed loop only
-        args.no_fp64 = args.no_serving = args.no_sphere_rule = args.no_tree = True
+        args.no_fp64 = args.no_serving = args.no_sphere_rule = args.no_tree = args.no_secondary = True
     pos, q, lo, L = workloads.make_system(w)
     dev = torch.device("cuda:0")
     x = torch.tensor(pos, device=dev)
@@ -389,7 +415,7 @@ def main():
     en = torch.zeros(1, dtype=torch.float64, device=dev)
     pot = torch.zeros(w.n, dtype=torch.float64, device=dev)
     f = torch.zeros((w.n, 3), dtype=torch.float64, device=dev)
-    plan = hs.Plan(hs.Params.from_workload(w, precision=hs.FP32C), lo, L)
+    stream = torch.cuda.current_stream()
     if args.profile_pass:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -397,112 +423,127 @@ def main():
         dst.copy_(src)           # plain copy kernel: 512 MiB read + 512 MiB written
         torch.cuda.synchronize()
         del src, dst
+        plan = hs.Plan(hs.Params.from_workload(w, precision=hs.FP32C), lo, L)
         for _ in range(args.warmup + args.steps):
             plan.compute_device(x, qq, en, pot, f)
         torch.cuda.synchronize()
+        plan.close()
         print(json.dumps({"profile_pass": True, "copy_bytes": 512 * 1024 * 1024, "steps": args.warmup + args.steps}))
         return
 
     progress(f"{w.name}: {args.warmup} warm-up + {args.steps} timed steps")
-    for _ in range(args.warmup):
-        plan.compute_device(x, qq, en, pot, f)
-    torch.cuda.synchronize()
-    if plan.device_status() != 0:
-        raise SystemExit("device-side validation failed")
-    plan.set_timing(True)
-    stream = torch.cuda.current_stream()
-    # one event between consecutive steps (no synchronisation inside the
-    # timed region): mean, median and p90 of the per-step device times
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    evs[0].record(stream)
-    for i in range(args.steps):
-        plan.compute_device(x, qq, en, pot, f)
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall1 = time.perf_counter()
-    ms = evs[0].elapsed_time(evs[-1]) / args.steps
-    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tm = plan.timing()
-    info = plan.info()
-    plan.set_timing(False)
-    calls = max(1, tm["calls"])
-    near_ms = tm["near_ms"] / calls
-    near_flop = FLOP_PER_NEAR_PAIR * info["near_pairs"]
-    achieved = near_flop / (near_ms * 1e-3) / 1e12
+    r = timed_loop(hs, w, lo, L, x, qq, en, pot, f, args.steps, args.warmup, stream)
+    ms = r["ms"]
+    info = r["info"]
     e32 = en.item()
     f32 = f.cpu().numpy()
-
     out = {
         "metric": "particle-steps/s (E+F) at 1e-5 rel force err; pair-int/s % FP32 peak; p50/p99",
         "value": w.n / (ms * 1e-3),
         "unit": "particle-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms,
-        "ms_per_step_median": float(np.median(per_step)),
-        "ms_per_step_p90": float(np.percentile(per_step, 90)),
-        "wall_ms_per_step": (wall1 - wall0) * 1e3 / args.steps,
+        "ms_per_step": ms, "ms_per_step_median": r["median"], "ms_per_step_p90": r["p90"],
+        "wall_ms_per_step": r["wall_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "box": list(w.box), "p": w.p, "F": w.F, "K": w.K,
-                   "lambda": w.lam,
+                   "lambda": w.lam, "charges": w.charges,
                    "near_set": "images inside the sphere" if w.near_rule == 1 else
-                               ("27 cells" if w.geometry == 0 else f"9 cells x {2 * w.M + 1} layers"),
-                   "precision": "fp32-compensated", "parallelism": "single-gpu"},
+                               ("27 cells by the treecode" if w.near_rule == 2 else
+                                ("27 cells" if w.geometry == 0 else f"9 cells x {2 * w.M + 1} layers")),
+                   "precision": "fp32-compensated (FP64 potential accumulation, FP64 fit and energy)",
+                   "parallelism": "single-gpu"},
         "pair_interactions_per_s": (info["near_pairs"] + info["check_pairs"] + info["surface_pairs"]) / (ms * 1e-3),
         "pairs_per_step": {"near_set": info["near_pairs"], "check_points": info["check_pairs"],
                            "sphere_sources": info["surface_pairs"]},
-        "stage_ms": {"step": tm["step_ms"] / calls, "near": near_ms, "check": tm["check_ms"] / calls,
-                     "sphere": tm["sphere_ms"] / calls},
-        "roofline": {
-            "kernel": "k_pair<float,particles> (near-set sums)",
-            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic("k_pair_float_particles", w.name),
-            "flop_per_launch": near_flop, "pairs_per_launch": info["near_pairs"],
-        },
+        "stage_ms": r["stage_ms"],
+        "roofline": roofline(w, r),
     }
     progress(f"timed: {ms:.3f} ms per step")
     if not args.no_fp64:
-        progress("FP64 path")
-        p64 = hs.Plan(hs.Params.from_workload(w, precision=hs.FP64), lo, L)
-        p64.compute_device(x, qq, en, pot, f)
-        torch.cuda.synchronize()
-        k64 = 3
-        ev0.record(stream)
-        for _ in range(k64):
-            p64.compute_device(x, qq, en, pot, f)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms64 = ev0.elapsed_time(ev1) / k64
-        e64 = en.item()
-        f64 = f.cpu().numpy()
-        out["fp64_gpu"] = {
-            "ms_per_step": ms64, "speedup_fp32c_over_fp64": ms64 / ms,
-            "rel_energy_err": abs(e32 - e64) / abs(e64),
-            "rel_rms_force_err": float(np.sqrt(((f32 - f64) ** 2).sum() / (f64 ** 2).sum())),
-            "max_force_err_rel_to_max": float(np.abs(f32 - f64).max() / np.abs(f64).max()),
-        }
-        p64.close()
-    plan.close()
-    if not args.no_sphere_rule:
-        progress("sphere near set (50,000 ions, then the slab)")
-        out["sphere_near_set"] = sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
-                                                   None if args.no_fp64 else f64)
-        out["sphere_near_set_slab"] = slab_near_sets_bench(hs, workloads)
+        progress("FP64 path on the same system")
+        out["fp64_gpu"], _, _ = fp64_leg(hs, w, lo, L, x, qq, en, pot, f, e32, f32, ms, stream)
+        progress(f"fp64: rel energy err {out['fp64_gpu']['rel_energy_err']:.2e}")
     if not args.no_tree:
-        progress("treecode (50,000 and 999,999 ions)")
-        out["tree_near_set"] = tree_rule_bench(hs, workloads, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
-                                               None if args.no_fp64 else e64, None if args.no_fp64 else f64)
+        progress("treecode on the same system")
+        params = hs.Params.from_workload(w, precision=hs.FP32C)
+        params.near_rule = 2
+        out["tree_near_set_large"] = tree_entry(hs, params, w, lo, L, x, qq, en, pot, f, stream, ms, 5)
+    del x, qq, pot, f
+    torch.cuda.empty_cache()
+    if not args.no_secondary:
+        progress("50,000-ion system (27 cells)")
+        out["c2_50000"] = c2_bench(hs, workloads, args)
     if not args.no_serving:
         progress("serving mix")
         out["serving"] = serving_bench(hs, workloads)
     if not args.no_cpu_baseline:
-        progress("CPU oracle (bounded: a sample, then one full step if it fits 30 s)")
+        progress("CPU oracle (bounded: a sample scaled to the step, or one full step if it fits 30 s)")
         out["cpu_baseline"] = cpu_baseline(w, pos, q, lo, L)
     print(json.dumps(out), flush=True)
+
+
+def tree_entry(hs, params, w, lo, L, x, qq, en, pot, f, stream, ms_cells, steps, e64=None, f64=None):
+    """The 27-cell sums by the treecode (near_rule=2) on the same arrays:
+    time per step and, when given, the error against the FP64 27-cell
+    result."""
+    import numpy as np
+    import torch
+    plan = hs.Plan(params, lo, L)
+    for _ in range(2):
+        plan.compute_device(x, qq, en, pot, f)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.compute_device(x, qq, en, pot, f)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    plan.close()
+    ms = ev0.elapsed_time(ev1) / steps
+    o = {"near_rule": 2, "tree_order": params.tree_order, "tree_theta": params.tree_theta,
+         "precision": "fp32-compensated", "ms_per_step": ms, "particle_steps_per_s": w.n / (ms * 1e-3),
+         "speedup_vs_27_cells": ms_cells / ms}
+    if e64 is not None:
+        fs = f.cpu().numpy()
+        o["rel_energy_err_vs_27_cells_fp64"] = abs(en.item() - e64) / abs(e64)
+        o["rel_rms_force_err_vs_27_cells_fp64"] = float(np.sqrt(((fs - f64) ** 2).sum() / (f64 ** 2).sum()))
+    return o
+
+
+def c2_bench(hs, workloads, args, steps=20):
+    """The 50,000-ion system (27 cells, FP32 compensated): step time and the
+    far kernel's roofline position, the FP64 path, the sphere near set, the
+    treecode, and the slab's near sets."""
+    import dataclasses
+    import torch
+    w = workloads.C2
+    pos, q, lo, L = workloads.make_system(w)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(pos, device=dev)
+    qq = torch.tensor(q, device=dev)
+    en = torch.zeros(1, dtype=torch.float64, device=dev)
+    pot = torch.zeros(w.n, dtype=torch.float64, device=dev)
+    f = torch.zeros((w.n, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    r = timed_loop(hs, w, lo, L, x, qq, en, pot, f, steps, 3, stream)
+    ms = r["ms"]
+    e32, f32 = en.item(), f.cpu().numpy()
+    out = {"workload": w.name, "n": w.n, "ms_per_step": ms, "particle_steps_per_s": w.n / (ms * 1e-3),
+           "stage_ms": r["stage_ms"], "roofline": roofline(w, r)}
+    e64 = f64 = None
+    if not args.no_fp64:
+        out["fp64_gpu"], e64, f64 = fp64_leg(hs, w, lo, L, x, qq, en, pot, f, e32, f32, ms, stream, steps=3)
+    if not args.no_sphere_rule:
+        out["sphere_near_set"] = sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms, f64)
+        out["sphere_near_set_slab"] = slab_near_sets_bench(hs, workloads)
+    if not args.no_tree:
+        params = hs.Params.from_workload(w, precision=hs.FP32C)
+        params.near_rule = 2
+        out["tree_near_set"] = tree_entry(hs, params, w, lo, L, x, qq, en, pot, f, stream, ms, 10, e64, f64)
+        out["tree_near_set"]["order12"] = tree_entry(hs, dataclasses.replace(params, tree_order=12), w, lo, L,
+                                                     x, qq, en, pot, f, stream, ms, 10, e64, f64)
+    return out
 
 
 if __name__ == "__main__":

@@ -18,6 +18,13 @@ constexpr int kWave = 64;               // wavefront width on CDNA
 constexpr int kTPL = HSMA_TPL;          // targets per lane
 constexpr int kGroup = kWave * kTPL;    // targets per wave (one "target group")
 constexpr int kTile = 64;               // sources per tile
+// Waves per block of the far particle sums: consecutive target groups on
+// the same chunk of sources, kept in step by a barrier per source tile so
+// that the tile's scalar loads are served once from the CU's scalar cache.
+#ifndef HSMA_FAR_WAVES
+#define HSMA_FAR_WAVES 4
+#endif
+constexpr int kFarWaves = HSMA_FAR_WAVES;
 
 // Particles per call: 32-bit particle indices with headroom; the sphere
 // near set and the treecode pack a tile index into 20 bits (2^20 tiles).

@@ -523,7 +523,7 @@ __device__ __forceinline__ double gap2_of(double dlx, double dly, double dlz, do
   __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? (NEAR ? 6 : HSMA_WAVES_PER_EU) : 4)))
 
 template <typename Real, bool NEAR, bool PARTICLES>
-__global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ cgroups,
+__global__ __launch_bounds__(kWave * kFarWaves) HSMA_PAIR_ATTR void k_pair(const double4* __restrict__ tgt, const Group* __restrict__ cgroups,
                                              const CheckSched* __restrict__ csched, int ncg, int cbase,
                                              PartSched ps,
                                              const Desc* __restrict__ desc,
@@ -548,14 +548,17 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       part_i = c;
       nparts = ps.nnear;
     } else {
-      const int c = blockIdx.x / ps.ngroups;
-      gi = blockIdx.x - c * ps.ngroups;
+      // kFarWaves waves per block: consecutive groups, the same chunk (see
+      // the far loop)
+      const int ngb = (ps.ngroups + kFarWaves - 1) / kFarWaves;
+      const int c = blockIdx.x / ngb;
+      gi = (blockIdx.x - c * ngb) * kFarWaves + (int)(threadIdx.x / kWave);
       const int f0 = c * ps.chunk;
       w = Work{gi, f0, min(ps.F, f0 + ps.chunk), c};
       part_i = c;
       nparts = ps.nch;
     }
-    g = Group{gi * kGroup, min(kGroup, ps.n - gi * kGroup), 0, ps.ndesc};
+    g = Group{gi * kGroup, max(0, min(kGroup, ps.n - gi * kGroup)), 0, ps.ndesc};
   } else {
     // checks: cbase offsets the launch index (a launch may cover a subset
     // of the groups: its far waves, or its groups for the near pass)
@@ -591,7 +594,12 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   // every tile goes through the far kernel (a face check group spans a whole
   // face, so its box overlaps many tiles)
   const double rc2 = PARTICLES ? sp->rc2 : (sizeof(Real) == 8 ? -1.0 : sp->rc2c);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x % kWave;
+  // the far particle kernel runs kFarWaves waves per block in step (a block
+  // barrier per source tile), so that the block's waves read each tile from
+  // the scalar cache together; a wave past the last group only keeps step
+  constexpr bool kStep = PARTICLES && !NEAR;
+  const bool active = g.count > 0;
   bool valid[kTPL];
   Real ox[kTPL], oy[kTPL], oz[kTPL];
   double mnx = INFINITY, mny = INFINITY, mnz = INFINITY, mxx = -INFINITY, mxy = -INFINITY, mxz = -INFINITY;
@@ -600,7 +608,7 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   for (int j = 0; j < kTPL; ++j) {
     const int l = j * kWave + lane;
     valid[j] = l < g.count;
-    tp[j] = tgt[g.first + (valid[j] ? l : 0)];
+    tp[j] = tgt[valid[j] ? g.first + l : 0];
     if (valid[j]) {
       mnx = fmin(mnx, tp[j].x); mxx = fmax(mxx, tp[j].x);
       mny = fmin(mny, tp[j].y); mxy = fmax(mxy, tp[j].y);
@@ -610,8 +618,10 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
   mnx = wave_min(mnx); mxx = wave_max(mxx);
   mny = wave_min(mny); mxy = wave_max(mxy);
   mnz = wave_min(mnz); mxz = wave_max(mxz);
-  const double cgx = 0.5 * (mnx + mxx), cgy = 0.5 * (mny + mxy), cgz = 0.5 * (mnz + mxz);
-  const double hgx = 0.5 * (mxx - mnx), hgy = 0.5 * (mxy - mny), hgz = 0.5 * (mxz - mnz);
+  const double cgx = active ? 0.5 * (mnx + mxx) : 0.0, cgy = active ? 0.5 * (mny + mxy) : 0.0,
+               cgz = active ? 0.5 * (mnz + mxz) : 0.0;
+  const double hgx = active ? 0.5 * (mxx - mnx) : 0.0, hgy = active ? 0.5 * (mxy - mny) : 0.0,
+               hgz = active ? 0.5 * (mxz - mnz) : 0.0;
   // potential: FP64 accumulator per target (the pair terms are summed into
   // it in FP64, so the sum adds no rounding of its own); field: Real
   double ph[kTPL];
@@ -813,6 +823,8 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
       Desc ds{};
       bool img_far = false;
       for (int f = f0; f < f1; ++f) {
+        if constexpr (kStep) __syncthreads();
+        if (!active) continue;
         const unsigned e = cv.list[f];
         const int di = (int)(e >> kTileBits), tile = (int)(e & tmask);
         if (di != cur) {
@@ -908,6 +920,8 @@ __global__ __launch_bounds__(64) HSMA_PAIR_ATTR void k_pair(const double4* __res
                                  __dadd_rn(hgx, hbox.x), __dadd_rn(hgy, hbox.y), __dadd_rn(hgz, hbox.z)) >= rc2;
     if constexpr (!NEAR) {
       for (int tile = t0; tile < t1; ++tile) {
+        if constexpr (kStep) __syncthreads();
+        if (!active) continue;
         unsigned long long cm = ~0ull;
         if (cull) {
           cm = cull[(long)di * ntiles + tile];
@@ -2481,7 +2495,9 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
     if (host.prm.near_rule == 2) {                                                                                  \
       if ((s = launch_tree<false>(st, comp, slot, err)) != HSMA_OK) return s;                                       \
     } else {                                                                                                        \
-      hipLaunchKernelGGL((k_pair<Real, false, true>), dim3(psched_.nch * psched_.ngroups), dim3(64), 0, st,         \
+      hipLaunchKernelGGL((k_pair<Real, false, true>),                                                              \
+                         dim3(psched_.nch * ((psched_.ngroups + kFarWaves - 1) / kFarWaves)), dim3(kWave * kFarWaves), \
+                         0, st,                                                                                     \
                          (const double4*)d_pos64, (const Group*)nullptr, (const CheckSched*)nullptr, 0, 0, psched_,    \
                          (const Desc*)d_desc_part, ntiles_, (const double4*)d_tile_c, (const float4*)d_tile_h,      \
                          (const S*)SRC, (const double4*)d_pos64, (const StepParams*)d_sp, cv, (Real*)d_part, comp, \
