@@ -138,6 +138,28 @@ hsma_status hsma_compute_device(hsma_plan* plan, void* stream, int64_t n, const 
                                 const double* d_q, double* d_energy, double* d_potential,
                                 double* d_force);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving or MD loops, harnesses that forbid allocation): the same step as
+ * hsma_compute_device, with its per-call working memory (sort keys, tiles,
+ * partial sums) taken from a static device array of 48 MiB that the library
+ * holds on every GPU it runs on until the process ends, instead of from an
+ * allocation.  The call makes no device or host allocation.  The plan must
+ * have been created on the current device (plan creation allocates the
+ * plan's constants and looks up the array's address).
+ * Limits: 1 <= n <= 16384 particles, else HSMA_ERR_INVALID_ARG; a plan whose
+ * parameters need more working memory for n than the array holds is also
+ * refused with HSMA_ERR_INVALID_ARG and a message giving both sizes.
+ * Sharing: every call on a GPU uses that GPU's one array, which keeps the
+ * last call's contents; calls that overlap on one GPU (different streams,
+ * plans or threads, without ordering between them) race and give wrong
+ * results.  Calls of one plan are ordered by the plan itself.
+ * The work decomposition differs from hsma_compute_device's (fewer, longer
+ * waves), so FP32C results agree with it to the FP32C tolerances, FP64
+ * results to rounding.  Validation and outputs as hsma_compute_device.    */
+hsma_status hsma_compute_device_noalloc(hsma_plan* plan, void* stream, int64_t n, const double* d_xyz,
+                                        const double* d_q, double* d_energy, double* d_potential,
+                                        double* d_force);
+
 /* Waits for the plan's last device call and returns the status that its
  * device-side validation recorded (OK, NOT_NEUTRAL or OUT_OF_DOMAIN).      */
 hsma_status hsma_plan_device_status(hsma_plan* plan);

@@ -99,8 +99,12 @@ hsma_status hsma_plan_create(const hsma_params* params, const double box_lo[3], 
 
 void hsma_plan_destroy(hsma_plan* plan) {
   if (!plan) return;
-  if (plan->dev.last_stream) (void)hipStreamSynchronize(plan->dev.last_stream);
-  (void)hipDeviceSynchronize();
+  // the plan's own work only: every call records ev_done at its end, and a
+  // call on another stream first waits for the previous call's ev_done, so
+  // ev_done completes after all of the plan's work (other streams and other
+  // plans on the device are not waited for)
+  std::string err;
+  (void)plan->dev.wait_done(err);
   delete plan;
 }
 
@@ -118,14 +122,30 @@ hsma_status hsma_compute_device(hsma_plan* plan, void* stream, int64_t n, const 
   } catch (...) {
     return fail(HSMA_ERR_DEVICE, "unexpected exception");
   }
-  plan->dev.last_stream = (hipStream_t)stream;
+  if (s != HSMA_OK) return fail(s, msg);
+  return HSMA_OK;
+}
+
+hsma_status hsma_compute_device_noalloc(hsma_plan* plan, void* stream, int64_t n, const double* d_xyz,
+                                        const double* d_q, double* d_energy, double* d_potential, double* d_force) {
+  if (!plan || !d_xyz || !d_q) return fail(HSMA_ERR_INVALID_ARG, "NULL argument");
+  std::string msg;
+  hsma_status s;
+  try {
+    s = plan->dev.run_noalloc((hipStream_t)stream, n, d_xyz, d_q, d_energy, d_potential, d_force, msg);
+  } catch (...) {
+    return fail(HSMA_ERR_DEVICE, "unexpected exception");
+  }
   if (s != HSMA_OK) return fail(s, msg);
   return HSMA_OK;
 }
 
 hsma_status hsma_plan_device_status(hsma_plan* plan) {
   if (!plan) return fail(HSMA_ERR_INVALID_ARG, "NULL plan");
-  if (hipStreamSynchronize(plan->dev.last_stream) != hipSuccess) return fail(HSMA_ERR_DEVICE, "stream sync failed");
+  {
+    std::string err;
+    if (plan->dev.wait_done(err) != HSMA_OK) return fail(HSMA_ERR_DEVICE, "waiting for the plan's last call: " + err);
+  }
   int st = 0;
   if (hipMemcpy(&st, plan->dev.d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(HSMA_ERR_DEVICE, "status read failed");

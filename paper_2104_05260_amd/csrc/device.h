@@ -31,10 +31,13 @@ struct DevicePlan {
   hipStream_t side_near = nullptr;  // near pass of a step, forked from the call's stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join_near = nullptr;
 
-  // tuning of the work decomposition
+  // tuning of the work decomposition (the no-allocation entry point runs
+  // with smaller targets so that its partial sums fit the static scratch)
   int part_target = 32768;     // waves per particle pair launch (about)
   int check_target = 2048;     // minimum waves per check pair launch (about)
   int check_target_max = 65536;
+  int near_target = kNearWaves;  // near-pass waves per launch (about)
+  int tree_target = kTreeWaves;  // treecode waves per launch (about)
   long long check_pairs_per_item = 100000;
   double close_factor = 0.1;   // close-pair radius / typical tile extent (FP32 path)
 
@@ -58,7 +61,10 @@ struct DevicePlan {
   int* d_status = nullptr;
   double* d_energy_scratch = nullptr;
 
-  // per-size arena
+  // per-size arena: one device allocation (d_arena) carved into the
+  // buffers below; the no-allocation entry point carves the same layout
+  // from the library's static scratch instead
+  void* d_arena = nullptr;
   int64_t cap_n = 0, cur_n = -1;
   size_t part_cap = 0, cpart_cap = 0, work_cap = 0, cwork_cap = 0;
   uint32_t* d_key[2] = {nullptr, nullptr};
@@ -113,7 +119,6 @@ struct DevicePlan {
   int tree_cwaves_ = 0, tree_csplit_ = 1;  // treecode at the check targets (0: direct check sums)
   int tree_cgroup0_ = 0;                    // first check group summed by the treecode
   int tree_cbase_ = 0;                      // direct check waves before the treecode's
-  hipStream_t last_stream = nullptr;
 
   void* h_stage = nullptr;       // pinned staging of the check schedule
   size_t stage_bytes = 0;
@@ -149,6 +154,26 @@ struct DevicePlan {
   hsma_status init(std::string& err);
   // Allocates the per-size arena for any particle count up to nmax.
   hsma_status reserve(int64_t nmax, std::string& err);
+  // Bytes of the per-size arena for particle counts up to nmax under the
+  // current decomposition targets; with base != nullptr also points the
+  // arena buffers into [base, base + result).
+  size_t carve(int64_t nmax, char* base);
+  // Ordering of the plan's calls: each call waits for the previous call's
+  // work (ev_done, recorded at its end on its stream) when it runs on
+  // another stream, so calls on different streams never share the arena
+  // at the same time, and ev_done covers all of the plan's work.
+  hipEvent_t ev_done = nullptr;
+  bool done_recorded = false;
+  hipStream_t done_stream = nullptr;
+  hsma_status order_after_previous(hipStream_t st, std::string& err);
+  hsma_status mark_done(hipStream_t st, std::string& err);
+  // Waits for all work enqueued by the plan.
+  hsma_status wait_done(std::string& err);
+  // The device's static scratch (address from hipGetSymbolAddress at
+  // plan creation) and the step run on it without any allocation.
+  void* scratch = nullptr;
+  hsma_status run_noalloc(hipStream_t st, int64_t n, const double* d_xyz, const double* d_q, double* d_energy,
+                          double* d_pot, double* d_force, std::string& err);
   void capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_bytes, size_t& nwork, size_t& ncwork) const;
   // element size of the check-partial buffer: 8 bytes when any check sum
   // runs in FP64 (FP64 path; face rows of the sphere near set), else 4.
@@ -157,6 +182,7 @@ struct DevicePlan {
     return (host.prm.precision == HSMA_FP64 || host.prm.near_rule == 1) ? sizeof(double) : sizeof(float);
   }
   hsma_status prepare(int64_t n, hipStream_t st, std::string& err);
+  hsma_status set_step_params(hipStream_t st, std::string& err);
   hsma_status run(hipStream_t st, int64_t n, const double* d_xyz, const double* d_q, double* d_energy,
                   double* d_pot, double* d_force, std::string& err);
   void free_arena();

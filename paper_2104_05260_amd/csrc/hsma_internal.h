@@ -70,6 +70,18 @@ struct PartSched {
 constexpr int kTreeWaves = 65536;  // treecode waves per launch (about, at least one per (image entry, group))
 constexpr int kTreeMaxSplit = 8;
 
+// No-allocation entry point: a static device array of kScratchBytes per
+// GPU holds the per-size arena of one call of at most kNoAllocMaxN
+// particles, with these decomposition targets (fewer, longer waves and
+// fewer partial slots than the allocating path).
+constexpr size_t kScratchBytes = (size_t)48 << 20;
+constexpr int64_t kNoAllocMaxN = 16384;
+constexpr int kNoAllocPartTarget = 2048;
+constexpr int kNoAllocCheckTarget = 1024;
+constexpr int kNoAllocCheckTargetMax = 2048;
+constexpr int kNoAllocNearTarget = 1024;
+constexpr int kNoAllocTreeTarget = 4096;
+
 // Treecode over the tiles (near rule 2): level 0 holds the tiles in sorted
 // (Hilbert) order; node i of level l >= 1 groups nodes 8i .. 8i + 7 of
 // level l - 1, so it covers tiles [8^l i, 8^l (i + 1)).  Nodes of levels

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "device.h"
@@ -2022,6 +2023,37 @@ static hsma_status upload(T** dst, const std::vector<T>& v, std::string& err) {
   return HSMA_OK;
 }
 
+// The no-allocation entry point's scratch: one static array per GPU (each
+// device that loads the library holds its own copy until the process ends).
+// Host code never uses the symbol itself as an address: scratch_address()
+// looks up the device address once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+static hsma_status scratch_address(int dev, void** out, std::string& err) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device index out of range for the scratch table";
+    return HSMA_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      err = "hipGetSymbolAddress returned no address for the scratch array";
+      return HSMA_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HSMA_OK;
+}
+
 hsma_status DevicePlan::init(std::string& err) {
   HIPCHK(hipGetDevice(&device));
   // side stream of the step (default priority) and its fork/join events
@@ -2058,36 +2090,39 @@ hsma_status DevicePlan::init(std::string& err) {
   HIPCHK(hipMemset(d_status, 0, sizeof(int)));
   HIPCHK(hipMalloc((void**)&d_energy_scratch, sizeof(double)));
   HIPCHK(hipMalloc(&d_sp, sizeof(StepParams)));
+  // pinned staging of the check schedule (its size depends only on the
+  // plan), its upload event and the call-ordering event
+  stage_bytes = sizeof(CheckSched) * std::max<size_t>(1, host.check_groups.size()) + 64;
+  HIPCHK(hipHostMalloc(&h_stage, stage_bytes));
+  HIPCHK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
+  hsma_status ss = scratch_address(device, &scratch, err);
+  if (ss != HSMA_OK) return ss;
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::order_after_previous(hipStream_t st, std::string& err) {
+  if (done_recorded && st != done_stream) HIPCHK(hipStreamWaitEvent(st, ev_done, 0));
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::mark_done(hipStream_t st, std::string& err) {
+  HIPCHK(hipEventRecord(ev_done, st));
+  done_recorded = true;
+  done_stream = st;
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::wait_done(std::string& err) {
+  if (done_recorded) HIPCHK(hipEventSynchronize(ev_done));
   return HSMA_OK;
 }
 
 void DevicePlan::free_arena() {
-  void* ps[] = {d_key[0], d_key[1], d_val[0], d_val[1], d_hist, d_pos_w, d_pos64, d_src32, d_src64, d_tile_c,
-                d_tile_h, d_perm, d_red, d_epart, d_part, d_cpart, d_csched, d_cull, d_clist, d_ccount,
-                d_tnode, d_tbox, d_tmom64, d_tmom32};
-  for (void* p : ps)
-    if (p) (void)hipFree(p);
-  d_key[0] = d_key[1] = nullptr;
-  d_val[0] = d_val[1] = nullptr;
-  d_hist = nullptr;
-  d_pos_w = d_pos64 = nullptr;
-  d_src32 = nullptr;
-  d_src64 = nullptr;
-  d_tile_c = nullptr;
-  d_tile_h = nullptr;
-  d_perm = nullptr;
-  d_red = d_epart = nullptr;
-  d_part = d_cpart = nullptr;
-  d_csched = nullptr;
-  d_cull = nullptr;
-  d_clist = nullptr;
-  d_ccount = nullptr;
-  d_tnode = d_tbox = nullptr;
-  d_tmom64 = nullptr;
-  d_tmom32 = nullptr;
   if (stage_ev) (void)hipEventSynchronize(stage_ev);  // an upload may still read the staging
-  if (h_stage) (void)hipHostFree(h_stage);
-  h_stage = nullptr;
+  if (d_arena) (void)hipFree(d_arena);
+  d_arena = nullptr;
+  (void)carve(0, nullptr);
   cap_n = 0;
   cur_n = -1;
   arena_bytes = 0;
@@ -2099,6 +2134,8 @@ DevicePlan::~DevicePlan() {
   free_arena();
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   if (stage_ev) (void)hipEventDestroy(stage_ev);
+  if (h_stage) (void)hipHostFree(h_stage);
+  if (ev_done) (void)hipEventDestroy(ev_done);
   void* us[] = {d_unit_desc_part, d_unit_desc_check, d_unit_check_pos, d_unit_Praw, d_unit_SQ, d_unit_SD, d_unit_ysurf};
   for (void* p : us)
     if (p) (void)hipFree(p);
@@ -2118,7 +2155,7 @@ DevicePlan::~DevicePlan() {
 // Particle schedule for n particles: chunks sized so that a launch has
 // about `target` waves (and at least 2 tiles per chunk: small systems get
 // many short waves rather than a few long ones).
-static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree) {
+static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree, int near_target, int tree_target) {
   PartSched ps{};
   ps.n = (int)n;
   ps.split = 1;
@@ -2135,9 +2172,9 @@ static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree) {
   ps.nch = (ps.F + ps.chunk - 1) / ps.chunk;
   if (tree) {
     // treecode: `split` waves per (image entry, group), each on a share of
-    // one image, so that the launch has about kTreeWaves waves
+    // one image, so that the launch has about tree_target waves
     const long long base = (long long)ndesc * ps.ngroups;
-    ps.split = (int)std::min<long long>(kTreeMaxSplit, std::max<long long>(1, (kTreeWaves + base - 1) / base));
+    ps.split = (int)std::min<long long>(kTreeMaxSplit, std::max<long long>(1, (tree_target + base - 1) / base));
     ps.chunk = ntiles;
     ps.nch = ndesc * ps.split;
   }
@@ -2146,10 +2183,10 @@ static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree) {
     return ps;
   }
   // near pass: up to kMaxNearSplit waves per group, so that the launch has
-  // about kNearWaves waves, at most one per near candidate (image entry,
+  // about near_target waves, at most one per near candidate (image entry,
   // tile)
   ps.nnear = (int)std::min<long long>({(long long)kMaxNearSplit, (long long)ndesc * ntiles,
-                                       std::max<long long>(1, (kNearWaves + ps.ngroups - 1) / ps.ngroups)});
+                                       std::max<long long>(1, (near_target + ps.ngroups - 1) / ps.ngroups)});
   return ps;
 }
 
@@ -2185,16 +2222,67 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
   const size_t sph = 1024 + (size_t)ngroups * ((size_t)host.prm.F / kSphereChunkMax + 2);
   const size_t ncg = host.check_groups.size();
   // far slots <= part_target + ngroups; near slots <= min(kMaxNearSplit
-  // ngroups, kNearWaves + ngroups)
-  const size_t nearb = std::min<size_t>((size_t)kMaxNearSplit * ngroups, (size_t)kNearWaves + ngroups);
+  // ngroups, near_target + ngroups)
+  const size_t nearb = std::min<size_t>((size_t)kMaxNearSplit * ngroups, (size_t)near_target + ngroups);
   // far slots: treecode one per image entry and group
   const size_t farb = std::max<size_t>((size_t)part_target + ngroups,
-                                       host.prm.near_rule == 2 ? kTreeWaves + host.desc_particles.size() * ngroups : 0);
+                                       host.prm.near_rule == 2 ? tree_target + host.desc_particles.size() * ngroups : 0);
   part_bytes = rb * 5 * (size_t)kGroup * (farb + nearb + sph + 1);
   const size_t rbc = cpart_elem();
   cpart_bytes = rbc * 5 * (size_t)kGroup * ((size_t)check_target_max + 2 * ncg + 2);
   nwork = farb + nearb + 2;
   ncwork = (size_t)check_target_max + 2 * ncg + 2;
+}
+
+size_t DevicePlan::carve(int64_t nmax, char* base) {
+  size_t off = 0;
+  // next buffer of `bytes`, 256-byte aligned; null when nothing is carved
+  auto take = [&](auto** ptr, size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    *ptr = (base && bytes) ? reinterpret_cast<std::remove_pointer_t<decltype(ptr)>>(base + off) : nullptr;
+    off += bytes;
+  };
+  const int64_t cn = nmax > 0 ? std::max<int64_t>(nmax, 64) : 0;
+  const int64_t cnt = (cn + kTile - 1) / kTile;
+  const int64_t cpad = cnt * kTile;
+  const int64_t crs = (cn + kRsBlock - 1) / kRsBlock;
+  size_t part_bytes = 0, cpart_bytes = 0, nwork = 0, ncwork = 0;
+  if (cn > 0) capacity_bounds(cn, part_bytes, cpart_bytes, nwork, ncwork);
+  const size_t ncg = std::max<size_t>(1, host.check_groups.size());
+  const size_t ncull = (cn > 0 && host.prm.near_rule == 1) ? host.desc_particles.size() * (size_t)cnt : 0;
+  // tree nodes: the level counts only grow with the tile count
+  const size_t tnodes = (cn > 0 && host.prm.near_rule == 2) ? (size_t)tree_levels((int)cnt).nodes : 0;
+  take(&d_key[0], sizeof(uint32_t) * cn);
+  take(&d_key[1], sizeof(uint32_t) * cn);
+  take(&d_val[0], sizeof(int) * cn);
+  take(&d_val[1], sizeof(int) * cn);
+  take(&d_hist, sizeof(uint32_t) * 256 * crs);
+  take(&d_pos_w, sizeof(double4) * cn);
+  take(&d_pos64, sizeof(double4) * cpad);
+  take(&d_src32, sizeof(float4) * cpad);
+  take(&d_src64, sizeof(double4) * cpad);
+  take(&d_tile_c, sizeof(double4) * cnt);
+  take(&d_tile_h, sizeof(float4) * cnt);
+  take(&d_perm, sizeof(int) * cpad);
+  take(&d_red, sizeof(double) * 3 * ((cn + 255) / 256));
+  take(&d_epart, sizeof(double) * ((cn + kWave - 1) / kWave));
+  take(&d_part, part_bytes);
+  take(&d_cpart, cpart_bytes);
+  take(&d_csched, cn > 0 ? sizeof(CheckSched) * ncg : 0);
+  take(&d_cull, sizeof(unsigned long long) * ncull);
+  take(&d_clist, sizeof(unsigned) * ncull);
+  take(&d_ccount, ncull ? sizeof(int) : 0);
+  take(&d_tnode, sizeof(double4) * tnodes);
+  take(&d_tbox, sizeof(double4) * 2 * tnodes);
+  take(&d_tmom64, sizeof(double) * kTreeMomStride * tnodes);
+  take(&d_tmom32, sizeof(float) * kTreeMomStride * tnodes);
+  if (base) {
+    part_cap = part_bytes;
+    cpart_cap = cpart_bytes;
+    work_cap = nwork;
+    cwork_cap = ncwork;
+  }
+  return (off + 255) & ~(size_t)255;
 }
 
 hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
@@ -2207,57 +2295,11 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   last_key = GraphKey();
   free_arena();
   const int64_t cn = std::max<int64_t>(nmax, 64);
-  const int64_t cnt = ((cn + kTile - 1) / kTile);
-  const int64_t cpad = cnt * kTile;
-  const int64_t crs = (cn + kRsBlock - 1) / kRsBlock;
-  size_t part_bytes, cpart_bytes, nwork, ncwork;
-  capacity_bounds(cn, part_bytes, cpart_bytes, nwork, ncwork);
-  const size_t ncg = std::max<size_t>(1, host.check_groups.size());
-  HIPCHK(hipMalloc((void**)&d_key[0], sizeof(uint32_t) * cn));
-  HIPCHK(hipMalloc((void**)&d_key[1], sizeof(uint32_t) * cn));
-  HIPCHK(hipMalloc((void**)&d_val[0], sizeof(int) * cn));
-  HIPCHK(hipMalloc((void**)&d_val[1], sizeof(int) * cn));
-  HIPCHK(hipMalloc((void**)&d_hist, sizeof(uint32_t) * 256 * crs));
-  HIPCHK(hipMalloc((void**)&d_pos_w, sizeof(double4) * cn));
-  HIPCHK(hipMalloc((void**)&d_pos64, sizeof(double4) * cpad));
-  HIPCHK(hipMalloc((void**)&d_src32, sizeof(float4) * cpad));
-  HIPCHK(hipMalloc((void**)&d_src64, sizeof(double4) * cpad));
-  HIPCHK(hipMalloc((void**)&d_tile_c, sizeof(double4) * cnt));
-  HIPCHK(hipMalloc((void**)&d_tile_h, sizeof(float4) * cnt));
-  HIPCHK(hipMalloc((void**)&d_perm, sizeof(int) * cpad));
-  HIPCHK(hipMalloc((void**)&d_red, sizeof(double) * 3 * ((cn + 255) / 256)));
-  HIPCHK(hipMalloc((void**)&d_epart, sizeof(double) * ((cn + kWave - 1) / kWave)));
-  HIPCHK(hipMalloc(&d_part, part_bytes));
-  HIPCHK(hipMalloc(&d_cpart, cpart_bytes));
-  HIPCHK(hipMalloc((void**)&d_csched, sizeof(CheckSched) * ncg));
-  const size_t ncull = host.prm.near_rule == 1 ? host.desc_particles.size() * (size_t)cnt : 0;
-  if (ncull) {
-    HIPCHK(hipMalloc((void**)&d_cull, sizeof(unsigned long long) * ncull));
-    HIPCHK(hipMalloc((void**)&d_clist, sizeof(unsigned) * ncull));
-    HIPCHK(hipMalloc((void**)&d_ccount, sizeof(int)));
-  }
-  // tree nodes: the level counts only grow with the tile count
-  const size_t tnodes = host.prm.near_rule == 2 ? (size_t)tree_levels((int)cnt).nodes : 0;
-  if (tnodes) {
-    HIPCHK(hipMalloc((void**)&d_tnode, sizeof(double4) * tnodes));
-    HIPCHK(hipMalloc((void**)&d_tbox, sizeof(double4) * 2 * tnodes));
-    HIPCHK(hipMalloc((void**)&d_tmom64, sizeof(double) * kTreeMomStride * tnodes));
-    HIPCHK(hipMalloc((void**)&d_tmom32, sizeof(float) * kTreeMomStride * tnodes));
-  }
-  HIPCHK(hipHostMalloc(&h_stage, sizeof(CheckSched) * ncg + 64));
-  if (!stage_ev) HIPCHK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
-  stage_bytes = sizeof(CheckSched) * ncg + 64;
+  const size_t bytes = carve(cn, nullptr);
+  HIPCHK(hipMalloc(&d_arena, bytes));
+  (void)carve(cn, (char*)d_arena);
   cap_n = cn;
-  part_cap = part_bytes;
-  cpart_cap = cpart_bytes;
-  work_cap = nwork;
-  cwork_cap = ncwork;
-  arena_bytes = sizeof(uint32_t) * cn * 2 + sizeof(int) * cn * 2 + sizeof(uint32_t) * 256 * crs +
-                sizeof(double4) * (cn + 2 * cpad + cnt) + sizeof(float4) * (cpad + cnt) + sizeof(int) * cpad +
-                sizeof(double) * 3 * ((cn + 255) / 256) + sizeof(double) * ((cn + kWave - 1) / kWave) + part_bytes +
-                cpart_bytes + sizeof(CheckSched) * ncg +
-                (sizeof(unsigned long long) + sizeof(unsigned)) * ncull +
-                (3 * sizeof(double4) + kTreeMomStride * (sizeof(double) + sizeof(float))) * tnodes;
+  arena_bytes = bytes;
   cur_n = -1;
   return HSMA_OK;
 }
@@ -2268,7 +2310,8 @@ hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   hsma_status s = reserve(n, err);
   if (s != HSMA_OK) return s;
   const int ntiles = (int)((n + kTile - 1) / kTile);
-  const PartSched ps = part_schedule(n, (int)host.desc_particles.size(), part_target, host.prm.near_rule == 2);
+  const PartSched ps = part_schedule(n, (int)host.desc_particles.size(), part_target, host.prm.near_rule == 2,
+                                     near_target, tree_target);
   // check work: about check_pairs_per_item pairs per wave, enough waves to
   // fill the chip when there is that much work
   long long cpairs = 0;
@@ -2599,31 +2642,19 @@ hsma_status DevicePlan::enqueue_step(hipStream_t st, int n, const double* d_xyz,
   return HSMA_OK;
 }
 
-hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, const double* d_q, double* d_energy,
-                            double* d_pot, double* d_force, std::string& err) {
-  if (n64 > (int64_t)0x3fffffff) {
-    err = "too many particles for one call";
-    return HSMA_ERR_INVALID_ARG;
-  }
-  if (host.prm.near_rule == 1 && (n64 + kTile - 1) / kTile > (int64_t)1 << kTileBits) {
-    err = "too many particles for the sphere near set (at most 2^26)";
-    return HSMA_ERR_INVALID_ARG;
-  }
-  if (host.prm.near_rule == 2 && (n64 + kTile - 1) / kTile > (int64_t)1 << 20) {
-    err = "too many particles for the treecode (at most 2^26)";
-    return HSMA_ERR_INVALID_ARG;
-  }
-  hsma_status s = prepare(n64, st, err);
-  if (s != HSMA_OK) return s;
-  const int n = (int)n64;
+// Writes the step-parameter block (box, close-pair radii, sphere radius)
+// on stream st when it changed since the last write (same stream order as
+// the kernels that read it).
+hsma_status DevicePlan::set_step_params(hipStream_t st, std::string& err) {
   const bool fp64 = host.prm.precision == HSMA_FP64;
+  const int64_t n = std::max<int64_t>(1, cur_n);
   const double3 lo = make_double3(host.lo[0], host.lo[1], host.lo[2]);
   const double3 L = make_double3(host.L[0], host.L[1], host.L[2]);
   const double3 hbox = make_double3(0.5 * host.L[0], 0.5 * host.L[1], 0.5 * host.L[2]);
   // close-pair radius: a tenth of a typical tile extent (FP32 path); the
   // FP64 path needs the near pass only to drop the self pair
   const double vol = host.L[0] * host.L[1] * host.L[2];
-  const double ext = std::cbrt(kTile * vol / std::max(1, n));
+  const double ext = std::cbrt(kTile * vol / (double)n);
   const double rc = fp64 ? 1e-9 * ext : close_factor * ext;
   // the step-parameter block is rewritten only when it changes (same
   // stream order as the kernels that read it)
@@ -2638,6 +2669,30 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
     std::memcpy(sp_host, spv, sizeof(spv));
     sp_valid = true;
   }
+  return HSMA_OK;
+}
+
+hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, const double* d_q, double* d_energy,
+                            double* d_pot, double* d_force, std::string& err) {
+  if (n64 > (int64_t)0x3fffffff) {
+    err = "too many particles for one call";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  if (host.prm.near_rule == 1 && (n64 + kTile - 1) / kTile > (int64_t)1 << kTileBits) {
+    err = "too many particles for the sphere near set (at most 2^26)";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  if (host.prm.near_rule == 2 && (n64 + kTile - 1) / kTile > (int64_t)1 << 20) {
+    err = "too many particles for the treecode (at most 2^26)";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  hsma_status s = order_after_previous(st, err);
+  if (s != HSMA_OK) return s;
+  s = prepare(n64, st, err);
+  if (s != HSMA_OK) return s;
+  s = set_step_params(st, err);
+  if (s != HSMA_OK) return s;
+  const int n = (int)n64;
   // Graph replay: a step depends only on (n, buffers, stream) once the box
   // scalars live in d_sp.  It is captured on the second consecutive call
   // with the same key and replayed afterwards.
@@ -2675,6 +2730,7 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   } else {
     if ((s = enqueue_step(st, n, d_xyz, d_q, d_energy, d_pot, d_force, err)) != HSMA_OK) return s;
   }
+  if ((s = mark_done(st, err)) != HSMA_OK) return s;
   last_key = key;
   const long long nd = (long long)host.desc_particles.size();
   near_pairs = (long long)n * nd * n - n;
@@ -2686,11 +2742,78 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
 }
 
 
+// One step whose per-size arena lives in the device's static scratch: no
+// device or host allocation.  The decomposition uses the no-allocation
+// targets, and the heap arena (if any) is carved back afterwards.  Every
+// call on a device shares that device's scratch.
+hsma_status DevicePlan::run_noalloc(hipStream_t st, int64_t n, const double* d_xyz, const double* d_q,
+                                    double* d_energy, double* d_pot, double* d_force, std::string& err) {
+  if (n < 1 || n > kNoAllocMaxN) {
+    err = "the no-allocation entry point takes 1 to " + std::to_string(kNoAllocMaxN) + " particles";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  if (!scratch) {
+    err = "no scratch address on this device";
+    return HSMA_ERR_DEVICE;
+  }
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != device) {
+    err = "the current device is not the plan's device";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  const int saved[5] = {part_target, check_target, check_target_max, near_target, tree_target};
+  const int64_t saved_cap = cap_n;
+  auto restore = [&]() {
+    part_target = saved[0];
+    check_target = saved[1];
+    check_target_max = saved[2];
+    near_target = saved[3];
+    tree_target = saved[4];
+    (void)carve(d_arena ? saved_cap : 0, (char*)d_arena);
+    cap_n = d_arena ? saved_cap : 0;
+    cur_n = -1;
+    gkey = GraphKey();
+    last_key = GraphKey();
+  };
+  part_target = kNoAllocPartTarget;
+  check_target = kNoAllocCheckTarget;
+  check_target_max = kNoAllocCheckTargetMax;
+  near_target = kNoAllocNearTarget;
+  tree_target = kNoAllocTreeTarget;
+  const size_t need = carve(n, nullptr);
+  if (need > kScratchBytes) {
+    restore();
+    err = "this plan needs " + std::to_string(need) + " bytes of scratch for " + std::to_string(n) +
+          " particles; the no-allocation scratch holds " + std::to_string(kScratchBytes);
+    return HSMA_ERR_INVALID_ARG;
+  }
+  (void)carve(n, (char*)scratch);
+  cap_n = std::max<int64_t>(n, 64);  // prepare() must not reserve a heap arena
+  cur_n = -1;
+  const bool timed = timing;
+  timing = false;
+  hsma_status s = order_after_previous(st, err);
+  if (s == HSMA_OK) s = prepare(n, st, err);
+  if (s == HSMA_OK) s = set_step_params(st, err);
+  if (s == HSMA_OK) s = enqueue_step(st, (int)n, d_xyz, d_q, d_energy, d_pot, d_force, err);
+  if (s == HSMA_OK) s = mark_done(st, err);
+  timing = timed;
+  restore();
+  if (s != HSMA_OK) return s;
+  const long long nd = (long long)host.desc_particles.size();
+  near_pairs = (long long)n * nd * n - n;
+  long long cp = 0;
+  for (const Group& g : host.check_groups) cp += (long long)g.count * g.ndesc * n;
+  check_pairs = cp;
+  sphere_pairs = (long long)n * host.prm.F;
+  return HSMA_OK;
+}
+
 hsma_status DevicePlan::sphere_sources(long long& inside, std::string& err) const {
   inside = 0;
   if (!d_cull || cur_n <= 0) return HSMA_OK;
-  if (last_stream) HIPCHK(hipStreamSynchronize(last_stream));
-  else HIPCHK(hipDeviceSynchronize());
+  if (done_recorded) HIPCHK(hipEventSynchronize(ev_done));
   const size_t nd = host.desc_particles.size();
   std::vector<unsigned long long> m(nd * (size_t)ntiles_);
   HIPCHK(hipMemcpy(m.data(), d_cull, sizeof(unsigned long long) * m.size(), hipMemcpyDeviceToHost));

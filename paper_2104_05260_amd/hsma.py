@@ -145,6 +145,7 @@ def load_library():
     lib.hsma_plan_destroy.argtypes = [vp]
     lib.hsma_compute.argtypes = [vp, i64, d, d, d, d, d]
     lib.hsma_compute_device.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.hsma_compute_device_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     lib.hsma_plan_device_status.argtypes = [vp]
     lib.hsma_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
     lib.hsma_last_error.restype = ctypes.c_char_p
@@ -166,7 +167,8 @@ def load_library():
         getattr(lib, name).restype = ctypes.c_int
     lib.hsma_debug_hilbert_key.argtypes = [ctypes.c_uint32] * 3
     lib.hsma_debug_hilbert_key.restype = ctypes.c_uint32
-    for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_plan_device_status",
+    for name in ("hsma_plan_create", "hsma_compute", "hsma_compute_device", "hsma_compute_device_noalloc",
+                 "hsma_plan_device_status",
                  "hsma_plan_get_info", "hsma_debug_solid_harmonics", "hsma_plan_set_timing", "hsma_plan_get_timing", "hsma_plan_set_graph", "hsma_debug_host_plan_create"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -273,6 +275,20 @@ class Plan:
         ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
         _check(self._lib.hsma_compute_device(self._p, ctypes.c_void_p(stream), n, ptr(xyz), ptr(q),
                                              ptr(energy), ptr(potential), ptr(force)))
+
+    def compute_device_noalloc(self, xyz, q, energy=None, potential=None, force=None, stream=None):
+        """As compute_device, through hsma_compute_device_noalloc (per-call
+        working memory from the library's static scratch; n <= 16384)."""
+        import torch
+        n = xyz.shape[0]
+        for t in (xyz, q, energy, potential, force):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError("device arguments must be contiguous float64 GPU tensors")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _check(self._lib.hsma_compute_device_noalloc(self._p, ctypes.c_void_p(stream), n, ptr(xyz), ptr(q),
+                                                     ptr(energy), ptr(potential), ptr(force)))
 
     def device_status(self) -> int:
         st = self._lib.hsma_plan_device_status(self._p)
