@@ -99,13 +99,17 @@ typedef struct hsma_params {
   double coulomb_k;    /* prefactor of q_i q_j / r (default 1)                */
   int tree_order;      /* near rule 2: multipole order, 4, 6, 8, 10 or 12     */
   double tree_theta;   /* near rule 2: opening parameter, 0 < theta <= 0.75   */
+  int lsq_solver;      /* least-squares pseudo-inverse of Eq. 6, built once per
+                          plan: 0 host Householder QR (FP64); 1 CholeskyQR2
+                          on the device (FP64, Gram matrices on the matrix
+                          cores; the plan's device must be current)          */
 } hsma_params;
 
 typedef struct hsma_plan hsma_plan;
 
 /* Fills *p with defaults: 3D, FP32C, lambda 1.5, p 10, K 2(p+1)^2, F 800,
  * Fw 0, surface rule 0, near rule 0, M 10, gammas 0, nz 80, coulomb_k 1,
- * tree order 8, tree theta 0.5.                                           */
+ * tree order 8, tree theta 0.5, lsq solver 0.                             */
 void hsma_params_default(hsma_params* p);
 
 /* Builds the per-geometry plan: check points, sphere quadrature, harmonic
@@ -196,13 +200,15 @@ hsma_status hsma_plan_set_timing(hsma_plan* plan, int enable);
 hsma_status hsma_plan_get_timing(hsma_plan* plan, hsma_timing* out);
 
 /* Step graphs (default off).  When on, a device call on a non-NULL stream
- * that repeats the previous call's particle count, buffers and stream is
- * captured once into a HIP graph (on that second call) and replayed on
- * later calls, so a repeated step costs one graph launch instead of ~20
- * kernel launches.  Positions, charges and box may change between calls:
- * the graph reads them from the buffers and from a device parameter block
- * written by an ordinary launch before each replay.  Results are identical
- * to eager execution.  Timing (hsma_plan_set_timing) forces eager launches. */
+ * whose (particle count, buffers, stream) repeats one of the plan's recent
+ * calls is captured into a HIP graph (on that second call) and replayed on
+ * later calls with the same key, so a repeated step costs one graph launch
+ * instead of ~20 kernel launches.  Up to 8 captured steps are kept per plan
+ * (least recently used out), so replicas that alternate on one plan all
+ * replay.  Positions, charges and box may change between calls: the graph
+ * reads them from the buffers and from a device parameter block written by
+ * an ordinary launch before each replay.  Results are identical to eager
+ * execution.  Timing (hsma_plan_set_timing) forces eager launches.        */
 hsma_status hsma_plan_set_graph(hsma_plan* plan, int enable);
 
 /* Thread-local description of the last error on this thread.               */

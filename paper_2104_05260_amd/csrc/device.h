@@ -145,8 +145,12 @@ struct DevicePlan {
   double sp_host[12] = {0};     // last values written to d_sp
   bool sp_valid = false;
   bool use_graph = false;
-  hipGraphExec_t gexec = nullptr;
-  GraphKey gkey, last_key;
+  // captured steps, most recently used first, and the keys of recent eager
+  // calls (a key seen again is captured)
+  static constexpr int kGraphCache = 8, kGraphSeen = 16;
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+  std::vector<GraphKey> seen_keys;
+  void drop_graphs();
   long long graph_replays = 0;
   hsma_status enqueue_step(hipStream_t st, int n, const double* d_xyz, const double* d_q, double* d_energy,
                            double* d_pot, double* d_force, std::string& err);
@@ -158,6 +162,9 @@ struct DevicePlan {
   // current decomposition targets; with base != nullptr also points the
   // arena buffers into [base, base + result).
   size_t carve(int64_t nmax, char* base);
+  // Uses [base, base + carve(nmax)) as the arena (owned by the caller, e.g.
+  // a server slot shared by several plans that never run at once).
+  void attach_arena(void* base, int64_t nmax);
   // Ordering of the plan's calls: each call waits for the previous call's
   // work (ev_done, recorded at its end on its stream) when it runs on
   // another stream, so calls on different streams never share the arena

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -146,9 +147,31 @@ struct HostPlan {
   std::vector<double> SQ, SD;
 };
 
-// Builds the plan; returns HSMA_OK or an error with *msg set.
+// Pseudo-inverse of the fitting matrix M (rows x cols, row-major): P = R^-1
+// Q^T (cols x rows) and a condition estimate (max / min |R_ii|); false when
+// M is rank deficient.
+typedef std::function<bool(const std::vector<double>& M, int rows, int cols, std::vector<double>& P, double& cond)>
+    PinvFn;
+
+// One matrix of a grouped device factorisation (device_pinv_batch).
+struct LsqJob {
+  const std::vector<double>* M = nullptr;  // rows x cols, row-major
+  int rows = 0, cols = 0;
+  std::vector<double>* P = nullptr;        // out: cols x rows
+  std::vector<double> Rdiag;                // out: diagonal of R
+  double cond = 0;                          // out
+  bool ok = false;                          // out: full column rank
+};
+
+// CholeskyQR2 of every job's M on the current device (FP64; Gram matrices
+// on the matrix cores, all jobs in the same launches); synchronous.
+hsma_status device_pinv_batch(std::vector<LsqJob>& jobs, std::string& err);
+
+// Builds the plan; returns HSMA_OK or an error with *msg set.  pinv: the
+// pseudo-inverse to use (nullptr: by prm.lsq_solver, host Householder QR or
+// device CholeskyQR2).
 hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const double L[3],
-                            HostPlan& out, std::string& msg);
+                            HostPlan& out, std::string& msg, const PinvFn* pinv = nullptr);
 
 // Real solid harmonics (scaled coordinates xi = r / R): values (nb) and,
 // if grad != nullptr, gradients w.r.t. xi (nb x 3).  Ordering: degree

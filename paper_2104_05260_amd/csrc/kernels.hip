@@ -2129,7 +2129,7 @@ void DevicePlan::free_arena() {
 }
 
 DevicePlan::~DevicePlan() {
-  if (gexec) (void)hipGraphExecDestroy(gexec);
+  drop_graphs();
   if (d_sp) (void)hipFree(d_sp);
   free_arena();
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -2285,14 +2285,26 @@ size_t DevicePlan::carve(int64_t nmax, char* base) {
   return (off + 255) & ~(size_t)255;
 }
 
+// Destroys the captured steps (their kernels hold arena addresses); waits
+// for the plan's last call first, which may be a replay.
+void DevicePlan::drop_graphs() {
+  if (!graphs.empty() && done_recorded) (void)hipEventSynchronize(ev_done);
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  graphs.clear();
+  seen_keys.clear();
+}
+
+void DevicePlan::attach_arena(void* base, int64_t nmax) {
+  drop_graphs();
+  const int64_t cn = std::max<int64_t>(nmax, 64);
+  arena_bytes = carve(cn, (char*)base);
+  cap_n = cn;
+  cur_n = -1;
+}
+
 hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
   if (nmax <= cap_n) return HSMA_OK;
-  if (gexec) {
-    (void)hipGraphExecDestroy(gexec);
-    gexec = nullptr;
-  }
-  gkey = GraphKey();
-  last_key = GraphKey();
+  drop_graphs();
   free_arena();
   const int64_t cn = std::max<int64_t>(nmax, 64);
   const size_t bytes = carve(cn, nullptr);
@@ -2306,7 +2318,6 @@ hsma_status DevicePlan::reserve(int64_t nmax, std::string& err) {
 
 hsma_status DevicePlan::prepare(int64_t n, hipStream_t st, std::string& err) {
   if (n == cur_n) return HSMA_OK;
-  gkey = GraphKey();  // a captured step used the schedule of another size
   hsma_status s = reserve(n, err);
   if (s != HSMA_OK) return s;
   const int ntiles = (int)((n + kTile - 1) / kTile);
@@ -2694,17 +2705,27 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
   if (s != HSMA_OK) return s;
   const int n = (int)n64;
   // Graph replay: a step depends only on (n, buffers, stream) once the box
-  // scalars live in d_sp.  It is captured on the second consecutive call
-  // with the same key and replayed afterwards.
+  // scalars live in d_sp and the check schedule of n has been uploaded
+  // (prepare, above, outside any graph).  A key seen among the recent calls
+  // is captured on its second call and replayed afterwards; up to
+  // kGraphCache captured steps are kept (least recently used out), so
+  // replicas that alternate on one plan all replay.
   const GraphKey key{n, d_xyz, d_q, d_energy, d_pot, d_force, st};
   const bool graphable = use_graph && !timing && st != nullptr;
-  if (graphable && gexec && key == gkey) {
-    HIPCHK(hipGraphLaunch(gexec, st));
+  int hit = -1;
+  if (graphable)
+    for (size_t i = 0; i < graphs.size(); ++i)
+      if (graphs[i].first == key) hit = (int)i;
+  if (hit >= 0) {
+    std::rotate(graphs.begin(), graphs.begin() + hit, graphs.begin() + hit + 1);  // most recent first
+    HIPCHK(hipGraphLaunch(graphs[0].second, st));
     ++graph_replays;
-  } else if (graphable && key == last_key) {
-    if (gexec) {
-      (void)hipGraphExecDestroy(gexec);
-      gexec = nullptr;
+  } else if (graphable && std::find(seen_keys.begin(), seen_keys.end(), key) != seen_keys.end()) {
+    if (graphs.size() >= (size_t)kGraphCache) {
+      // the evicted step may still run: wait for the plan's previous call
+      HIPCHK(hipEventSynchronize(ev_done));
+      (void)hipGraphExecDestroy(graphs.back().second);
+      graphs.pop_back();
     }
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hsma_status es = enqueue_step(st, n, d_xyz, d_q, d_energy, d_pot, d_force, err);
@@ -2718,20 +2739,23 @@ hsma_status DevicePlan::run(hipStream_t st, int64_t n64, const double* d_xyz, co
       err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ce);
       return HSMA_ERR_DEVICE;
     }
-    hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) {
-      gexec = nullptr;
       err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ie);
       return HSMA_ERR_DEVICE;
     }
-    gkey = key;
-    HIPCHK(hipGraphLaunch(gexec, st));
+    graphs.insert(graphs.begin(), std::make_pair(key, exec));
+    HIPCHK(hipGraphLaunch(exec, st));
   } else {
     if ((s = enqueue_step(st, n, d_xyz, d_q, d_energy, d_pot, d_force, err)) != HSMA_OK) return s;
+    if (graphable) {
+      seen_keys.insert(seen_keys.begin(), key);
+      if (seen_keys.size() > (size_t)kGraphSeen) seen_keys.pop_back();
+    }
   }
   if ((s = mark_done(st, err)) != HSMA_OK) return s;
-  last_key = key;
   const long long nd = (long long)host.desc_particles.size();
   near_pairs = (long long)n * nd * n - n;
   long long cp = 0;
@@ -2772,9 +2796,7 @@ hsma_status DevicePlan::run_noalloc(hipStream_t st, int64_t n, const double* d_x
     tree_target = saved[4];
     (void)carve(d_arena ? saved_cap : 0, (char*)d_arena);
     cap_n = d_arena ? saved_cap : 0;
-    cur_n = -1;
-    gkey = GraphKey();
-    last_key = GraphKey();
+    cur_n = -1;  // the next allocating call uploads its schedule again
   };
   part_target = kNoAllocPartTarget;
   check_target = kNoAllocCheckTarget;

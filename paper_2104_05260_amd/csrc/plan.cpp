@@ -356,7 +356,7 @@ double image_strength(int l, double gu, double gl, bool upper) {
 }  // namespace
 
 hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const double L[3], HostPlan& P,
-                            std::string& msg) {
+                            std::string& msg, const PinvFn* pinv) {
   P = HostPlan();
   P.prm = prm;
   for (int k = 0; k < 3; ++k) {
@@ -367,6 +367,36 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
       return HSMA_ERR_INVALID_ARG;
     }
   }
+  if (prm.lsq_solver != 0 && prm.lsq_solver != 1) {
+    msg = "lsq_solver must be 0 (host QR) or 1 (device CholeskyQR2)";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  // the least-squares pseudo-inverse: given, host Householder QR, or the
+  // device's CholeskyQR2 (FP64 matrix cores)
+  auto solve_pinv = [&](const std::vector<double>& M, int rows, int cols, std::vector<double>& Pi, double& cond,
+                        std::string& m) -> hsma_status {
+    bool ok = false;
+    if (pinv) {
+      ok = (*pinv)(M, rows, cols, Pi, cond);
+    } else if (prm.lsq_solver == 1) {
+      std::vector<LsqJob> jobs(1);
+      jobs[0].M = &M;
+      jobs[0].rows = rows;
+      jobs[0].cols = cols;
+      jobs[0].P = &Pi;
+      const hsma_status ds = device_pinv_batch(jobs, m);
+      if (ds != HSMA_OK) return ds;
+      ok = jobs[0].ok;
+      cond = jobs[0].cond;
+    } else {
+      ok = pseudo_inverse(M, rows, cols, Pi, cond);
+    }
+    if (!ok) {
+      m = "least-squares matrix is rank deficient";
+      return HSMA_ERR_RANK;
+    }
+    return HSMA_OK;
+  };
   const bool slab = prm.geometry == HSMA_GEOM_2D;
   if (prm.geometry != HSMA_GEOM_3D && !slab) {
     msg = "geometry must be HSMA_GEOM_3D or HSMA_GEOM_2D";
@@ -580,9 +610,9 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     // check targets on the interfaces, in 8x8 blocks for spatially compact groups
     // (filled below together with the face pairs)
     std::vector<double> Pinv;
-    if (!pseudo_inverse(M, P.nrows, nb, Pinv, P.cond)) {
-      msg = "least-squares matrix is rank deficient";
-      return HSMA_ERR_RANK;
+    {
+      const hsma_status ls = solve_pinv(M, P.nrows, nb, Pinv, P.cond, msg);
+      if (ls != HSMA_OK) return ls;
     }
     // ---- targets: face pairs grouped by axis, then the two interface grids
     const int ncheck = nface + 2 * ngrid;
@@ -630,9 +660,9 @@ hsma_status build_host_plan(const hsma_params& prm, const double lo[3], const do
     }
   } else {
     std::vector<double> Pinv;
-    if (!pseudo_inverse(M, P.nrows, nb, Pinv, P.cond)) {
-      msg = "least-squares matrix is rank deficient";
-      return HSMA_ERR_RANK;
+    {
+      const hsma_status ls = solve_pinv(M, P.nrows, nb, Pinv, P.cond, msg);
+      if (ls != HSMA_OK) return ls;
     }
     const int ncheck = nface;
     P.Praw.assign(size_t(nb) * 2 * ncheck, 0.0);

@@ -1,49 +1,77 @@
-// Continuous-batching request server (see include/hsma_server.h).
+// Continuous-batching request server (see include/hsma_server.h): the HIP
+// backend of the scheduling core in server_core.h, plan classes, and the C
+// interface.
 #include <hip/hip_runtime.h>
 
-#include <chrono>
+#include <algorithm>
+#include <atomic>
 #include <cmath>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <memory>
 #include <mutex>
-#include <thread>
-#include <unordered_map>
+#include <string>
 #include <vector>
 
 #include "../../include/hsma_server.h"
 #include "device.h"
+#include "server_core.h"
 
 namespace {
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
+using hsma::serve::now_s;
 
-struct Req {
-  uint64_t id = 0;
-  int64_t n = 0;
-  std::vector<double> xyz, q;
-  double lo[3] = {0, 0, 0};
-  double scale = 1;
-  double* pot = nullptr;
-  double* force = nullptr;
-  hsma_result res{};
-  bool done = false;
+// A plan class: parameters and a unit box (box_len / box_len[0]); the host
+// plan is built for the unit box and re-targeted per request.
+struct PlanClass {
+  hsma_params prm{};
+  double unit[3] = {1, 1, 1};
+  hsma::HostPlan host;
 };
 
-// One device slot: a plan (constants + arena) re-targeted per request, its
-// own stream, device input/output buffers and pinned host staging.
+bool same_params(const hsma_params& a, const hsma_params& b) {
+  return a.geometry == b.geometry && a.precision == b.precision && a.lambda == b.lambda && a.p == b.p &&
+         a.K == b.K && a.F == b.F && a.Fw == b.Fw && a.surface_rule == b.surface_rule &&
+         a.near_rule == b.near_rule && a.M == b.M && a.gamma_up == b.gamma_up && a.gamma_low == b.gamma_low &&
+         a.nz == b.nz && a.coulomb_k == b.coulomb_k && a.tree_order == b.tree_order &&
+         a.tree_theta == b.tree_theta && a.lsq_solver == b.lsq_solver;
+}
+
+// What a request carries besides the core's fields.
+struct Payload {
+  bool device = false;
+  std::vector<double> xyz, q;        // host requests: copies of the inputs
+  const double* d_xyz = nullptr;     // device requests: the caller's buffers
+  const double* d_q = nullptr;
+  double* pot = nullptr;             // outputs (host or device)
+  double* force = nullptr;
+  double* energy = nullptr;          // device requests: device energy or NULL
+  hipEvent_t ready = nullptr;
+  double lo[3] = {0, 0, 0};
+  double scale = 1;
+};
+
+typedef hsma::serve::Request<Payload> Req;
+
+// One device slot: a stream, one arena shared by the slot's plans (one per
+// plan class it has run; only one runs at a time), device input/output
+// buffers for host requests and pinned staging.
 struct Slot {
-  std::unique_ptr<hsma::DevicePlan> plan;
   hipStream_t stream = nullptr;
-  hipEvent_t done_ev = nullptr;
-  double* d_io = nullptr;   // xyz (3 cap) | q (cap) | pot (cap) | force (3 cap) | energy
-  double* h_io = nullptr;   // pinned mirror, plus one int status at the end
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  std::vector<std::unique_ptr<hsma::DevicePlan>> plans;  // by class index
+  double* d_io = nullptr;  // xyz (3 cap) | q (cap) | pot (cap) | force (3 cap) | energy
+  double* h_io = nullptr;  // pinned mirror, then energy and one int status
   int64_t cap = 0;
-  std::shared_ptr<Req> req;  // running request
-  hsma_status enqueue_status = HSMA_OK;
+  bool replayed = false;
+};
+
+struct GpuBackend;
+typedef hsma::serve::Core<GpuBackend, Payload> CoreT;
+
+struct CallbackCtx {
+  CoreT* core = nullptr;
+  int slot = 0;
 };
 
 }  // namespace
@@ -51,119 +79,245 @@ struct Slot {
 struct hsma_server {
   hsma_server_cfg cfg{};
   int device = 0;
-  std::vector<Slot> slots;
   int64_t bytes_per_slot = 0;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Req>> pending;
-  std::unordered_map<uint64_t, std::shared_ptr<Req>> tickets;
-  uint64_t next_id = 1;
-  bool stop = false;
-  int waiters = 0;
-  std::condition_variable cv_idle;
-  std::thread th;
+  std::vector<Slot> slots;
+  std::vector<CallbackCtx> cb;
+  std::mutex class_mu;  // guards classes (submit threads add, the scheduler reads)
+  std::vector<std::unique_ptr<PlanClass>> classes;
+  std::unique_ptr<GpuBackend> backend;
+  std::unique_ptr<CoreT> core;
+  std::atomic<int64_t> graph_replays{0};  // written by the scheduler thread
 
-  void loop();
-  hsma_status dispatch(Slot& s, const std::shared_ptr<Req>& r, std::string& err);
-  void complete(Slot& s);
+  const PlanClass* cls(int i) {
+    std::lock_guard<std::mutex> lk(class_mu);
+    return classes[(size_t)i].get();
+  }
+  hsma_status find_or_create_class(const hsma_params& prm, const double box_len[3], int* idx, double* scale,
+                                   std::string& err);
 };
 
-hsma_status hsma_server::dispatch(Slot& s, const std::shared_ptr<Req>& r, std::string& err) {
-  const int64_t n = r->n, cap = s.cap;
-  double* h = s.h_io;
-  std::memcpy(h, r->xyz.data(), sizeof(double) * 3 * n);
-  std::memcpy(h + 3 * cap, r->q.data(), sizeof(double) * n);
-  double* d_xyz = s.d_io;
-  double* d_q = s.d_io + 3 * cap;
-  double* d_pot = s.d_io + 4 * cap;
-  double* d_force = s.d_io + 5 * cap;
-  double* d_e = s.d_io + 8 * cap;
-  hipError_t e;
-  if ((e = hipMemcpyAsync(d_xyz, h, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s.stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(d_q, h + 3 * cap, sizeof(double) * n, hipMemcpyHostToDevice, s.stream)) != hipSuccess) {
-    err = std::string("copy in: ") + hipGetErrorString(e);
-    return HSMA_ERR_DEVICE;
+namespace {
+
+// Unit box of a box: box / box[0] (box[0] is the scale).
+void unit_box(const double L[3], double u[3]) {
+  for (int k = 0; k < 3; ++k) u[k] = L[k] / L[0];
+}
+
+// The slot's plan for class c, created on first use: the class's host plan,
+// its constants on the device, the slot's arena carved for max_n particles
+// (grown, and the other plans re-carved, when this class needs more).
+hsma_status slot_plan(hsma_server* sv, Slot& s, int c, hsma::DevicePlan** out, std::string& err) {
+  if ((int)s.plans.size() <= c) s.plans.resize((size_t)c + 1);
+  if (!s.plans[c]) {
+    std::unique_ptr<hsma::DevicePlan> p(new hsma::DevicePlan());
+    p->host = sv->cls(c)->host;
+    hsma_status st = p->init(err);
+    if (st != HSMA_OK) return st;
+    if ((st = p->init_scalable(err)) != HSMA_OK) return st;
+    p->use_graph = true;
+    const size_t need = p->carve(s.cap, nullptr);
+    if (need > s.arena_bytes) {
+      if (s.arena) (void)hipFree(s.arena);
+      s.arena = nullptr;
+      s.arena_bytes = 0;
+      if (hipMalloc(&s.arena, need) != hipSuccess) {
+        err = "slot arena allocation failed";
+        return HSMA_ERR_OOM;
+      }
+      s.arena_bytes = need;
+      for (auto& q : s.plans)
+        if (q) q->attach_arena(s.arena, s.cap);
+    }
+    p->attach_arena(s.arena, s.cap);
+    s.plans[c] = std::move(p);
   }
-  hsma_status st = s.plan->set_box(r->lo, r->scale, s.stream, err);
+  *out = s.plans[c].get();
+  return HSMA_OK;
+}
+
+void on_done(void* data) {
+  CallbackCtx* c = static_cast<CallbackCtx*>(data);
+  c->core->notify_complete(c->slot);
+}
+
+struct GpuBackend {
+  hsma_server* sv;
+  explicit GpuBackend(hsma_server* s) : sv(s) {}
+  int slots() const { return (int)sv->slots.size(); }
+
+  hsma_status launch(int si, Req& r, std::string& err) {
+    Slot& s = sv->slots[si];
+    hsma::DevicePlan* plan = nullptr;
+    hsma_status st = slot_plan(sv, s, r.cls, &plan, err);
+    if (st != HSMA_OK) return st;
+    const int64_t n = r.n, cap = s.cap;
+    Payload& p = r.payload;
+    double* h = s.h_io;
+    const double* x = p.d_xyz;
+    const double* q = p.d_q;
+    double* pot = p.pot;
+    double* force = p.force;
+    double* d_e = s.d_io + 8 * cap;
+    hipError_t e;
+#define SVCHK(call, what)                                         \
+  do {                                                            \
+    if ((e = (call)) != hipSuccess) {                             \
+      err = std::string(what) + ": " + hipGetErrorString(e);      \
+      return e == hipErrorOutOfMemory ? HSMA_ERR_OOM : HSMA_ERR_DEVICE; \
+    }                                                             \
+  } while (0)
+    if (!p.device) {
+      std::memcpy(h, p.xyz.data(), sizeof(double) * 3 * n);
+      std::memcpy(h + 3 * cap, p.q.data(), sizeof(double) * n);
+      x = s.d_io;
+      q = s.d_io + 3 * cap;
+      pot = p.pot ? s.d_io + 4 * cap : nullptr;
+      force = p.force ? s.d_io + 5 * cap : nullptr;
+      SVCHK(hipMemcpyAsync(s.d_io, h, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s.stream), "copy in");
+      SVCHK(hipMemcpyAsync(s.d_io + 3 * cap, h + 3 * cap, sizeof(double) * n, hipMemcpyHostToDevice, s.stream),
+            "copy in");
+    } else if (p.ready) {
+      SVCHK(hipStreamWaitEvent(s.stream, p.ready, 0), "wait for the inputs' event");
+    }
+    if ((st = plan->set_box(p.lo, p.scale, s.stream, err)) != HSMA_OK) return st;
+    const long long replays0 = plan->graph_replays;
+    if ((st = plan->run(s.stream, n, x, q, d_e, pot, force, err)) != HSMA_OK) return st;
+    s.replayed = plan->graph_replays != replays0;
+    // energy and device status to the pinned staging; host outputs too
+    SVCHK(hipMemcpyAsync(h + 8 * cap, d_e, sizeof(double), hipMemcpyDeviceToHost, s.stream), "copy out");
+    SVCHK(hipMemcpyAsync(h + 8 * cap + 1, plan->d_status, sizeof(int), hipMemcpyDeviceToHost, s.stream), "copy out");
+    if (!p.device) {
+      if (p.pot) SVCHK(hipMemcpyAsync(h + 4 * cap, pot, sizeof(double) * n, hipMemcpyDeviceToHost, s.stream), "copy out");
+      if (p.force)
+        SVCHK(hipMemcpyAsync(h + 5 * cap, force, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s.stream), "copy out");
+    } else if (p.energy) {
+      SVCHK(hipMemcpyAsync(p.energy, d_e, sizeof(double), hipMemcpyDeviceToDevice, s.stream), "copy out");
+    }
+    SVCHK(hipLaunchHostFunc(s.stream, on_done, &sv->cb[si]), "completion callback");
+#undef SVCHK
+    return HSMA_OK;
+  }
+
+  void complete(int si, Req& r) {
+    Slot& s = sv->slots[si];
+    const int64_t cap = s.cap;
+    const double* h = s.h_io;
+    Payload& p = r.payload;
+    if (!p.device) {
+      if (p.pot) std::memcpy(p.pot, h + 4 * cap, sizeof(double) * r.n);
+      if (p.force) std::memcpy(p.force, h + 5 * cap, sizeof(double) * 3 * r.n);
+    }
+    int status = 0;
+    std::memcpy(&status, h + 8 * cap + 1, sizeof(int));
+    r.res.energy = h[8 * cap];
+    r.res.status = (hsma_status)status;
+    r.res.replayed = s.replayed ? 1 : 0;
+    r.res.plan_class = r.cls;
+    if (s.replayed) ++sv->graph_replays;
+  }
+};
+
+}  // namespace
+
+hsma_status hsma_server::find_or_create_class(const hsma_params& prm, const double box_len[3], int* idx,
+                                              double* scale, std::string& err) {
+  for (int k = 0; k < 3; ++k)
+    if (!(box_len[k] > 0) || !std::isfinite(box_len[k])) {
+      err = "box lengths must be finite and positive";
+      return HSMA_ERR_INVALID_ARG;
+    }
+  double u[3];
+  unit_box(box_len, u);
+  *scale = box_len[0];
+  std::lock_guard<std::mutex> lk(class_mu);
+  for (size_t i = 0; i < classes.size(); ++i) {
+    const PlanClass& c = *classes[i];
+    if (same_params(c.prm, prm) && c.unit[0] == u[0] && c.unit[1] == u[1] && c.unit[2] == u[2]) {
+      *idx = (int)i;
+      return HSMA_OK;
+    }
+  }
+  if (prm.near_rule < 0 || prm.near_rule > 2 || cfg.max_n > hsma::max_particles(prm.near_rule)) {
+    err = "the server's max_n is above the particles one call can take with this near rule";
+    return HSMA_ERR_INVALID_ARG;
+  }
+  std::unique_ptr<PlanClass> c(new PlanClass());
+  c->prm = prm;
+  for (int k = 0; k < 3; ++k) c->unit[k] = u[k];
+  const double lo0[3] = {0, 0, 0};
+  const hsma_status st = hsma::build_host_plan(prm, lo0, c->unit, c->host, err);
   if (st != HSMA_OK) return st;
-  st = s.plan->run(s.stream, n, d_xyz, d_q, d_e, r->pot ? d_pot : nullptr, r->force ? d_force : nullptr, err);
+  classes.push_back(std::move(c));
+  *idx = (int)classes.size() - 1;
+  return HSMA_OK;
+}
+
+namespace {
+
+// Host plans of several classes; the least-squares factorisations of those
+// with lsq_solver 1 run together on the device (one grouped launch sequence):
+// a first pass records each class's fitting matrix, the grouped device
+// CholeskyQR2 factors them all, a second pass builds each plan with its
+// pseudo-inverse.
+hsma_status build_classes(const std::vector<hsma_class>& in, std::vector<std::unique_ptr<PlanClass>>& out,
+                          std::string& err) {
+  const size_t nc = in.size();
+  std::vector<std::vector<double>> Ms(nc), Ps(nc);
+  std::vector<hsma::LsqJob> jobs;
+  std::vector<int> job_of(nc, -1);
+  const double lo0[3] = {0, 0, 0};
+  for (size_t i = 0; i < nc; ++i) {
+    if (in[i].params.lsq_solver != 1) continue;
+    double u[3];
+    if (!(in[i].box_len[0] > 0)) {
+      err = "box lengths must be finite and positive";
+      return HSMA_ERR_INVALID_ARG;
+    }
+    unit_box(in[i].box_len, u);
+    int rows = 0, cols = 0;
+    const hsma::PinvFn record = [&](const std::vector<double>& M, int r, int c, std::vector<double>& P, double& cond) {
+      Ms[i] = M;
+      rows = r;
+      cols = c;
+      P.assign((size_t)r * c, 0.0);
+      cond = 1.0;
+      return true;
+    };
+    hsma::HostPlan tmp;
+    const hsma_status st = hsma::build_host_plan(in[i].params, lo0, u, tmp, err, &record);
+    if (st != HSMA_OK) return st;
+    job_of[i] = (int)jobs.size();
+    hsma::LsqJob j;
+    j.rows = rows;
+    j.cols = cols;
+    jobs.push_back(j);
+  }
+  for (size_t i = 0; i < nc; ++i)
+    if (job_of[i] >= 0) {
+      jobs[job_of[i]].M = &Ms[i];
+      jobs[job_of[i]].P = &Ps[i];
+    }
+  hsma_status st = hsma::device_pinv_batch(jobs, err);
   if (st != HSMA_OK) return st;
-  int* h_status = (int*)(h + 8 * cap + 1);
-  if ((e = hipMemcpyAsync(h + 8 * cap, d_e, sizeof(double), hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(h_status, s.plan->d_status, sizeof(int), hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
-      (r->pot && (e = hipMemcpyAsync(h + 4 * cap, d_pot, sizeof(double) * n, hipMemcpyDeviceToHost, s.stream)) != hipSuccess) ||
-      (r->force && (e = hipMemcpyAsync(h + 5 * cap, d_force, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s.stream)) != hipSuccess) ||
-      (e = hipEventRecord(s.done_ev, s.stream)) != hipSuccess) {
-    err = std::string("copy out: ") + hipGetErrorString(e);
-    return HSMA_ERR_DEVICE;
+  for (size_t i = 0; i < nc; ++i) {
+    std::unique_ptr<PlanClass> c(new PlanClass());
+    c->prm = in[i].params;
+    unit_box(in[i].box_len, c->unit);
+    const int jb = job_of[i];
+    const hsma::PinvFn provide = [&](const std::vector<double>& M, int r, int cc, std::vector<double>& P, double& cond) {
+      if (M.size() != Ms[i].size() || (size_t)r * cc != Ps[i].size()) return false;
+      P = Ps[i];
+      cond = jobs[jb].cond;
+      return jobs[jb].ok;
+    };
+    st = hsma::build_host_plan(in[i].params, lo0, c->unit, c->host, err, jb >= 0 ? &provide : nullptr);
+    if (st != HSMA_OK) return st;
+    out.push_back(std::move(c));
   }
   return HSMA_OK;
 }
 
-void hsma_server::complete(Slot& s) {
-  std::shared_ptr<Req> r = s.req;
-  const int64_t cap = s.cap;
-  const double* h = s.h_io;
-  if (r->pot) std::memcpy(r->pot, h + 4 * cap, sizeof(double) * r->n);
-  if (r->force) std::memcpy(r->force, h + 5 * cap, sizeof(double) * 3 * r->n);
-  r->res.energy = h[8 * cap];
-  r->res.status = (hsma_status) * (const int*)(h + 8 * cap + 1);
-  r->res.t_done = now_s();
-  s.req.reset();
-  std::lock_guard<std::mutex> lk(mu);
-  r->done = true;
-  cv_done.notify_all();
-}
-
-void hsma_server::loop() {
-  (void)hipSetDevice(device);
-  for (;;) {
-    // admit queued requests into free slots, in arrival order
-    std::vector<std::pair<size_t, std::shared_ptr<Req>>> admit;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      bool running = false;
-      for (const Slot& s : slots) running |= (bool)s.req;
-      if (!running && pending.empty()) {
-        if (stop) break;
-        cv_work.wait_for(lk, std::chrono::milliseconds(20));
-        continue;
-      }
-      for (size_t i = 0; i < slots.size() && !pending.empty(); ++i) {
-        if (slots[i].req) continue;
-        admit.emplace_back(i, pending.front());
-        slots[i].req = pending.front();
-        pending.pop_front();
-      }
-    }
-    for (auto& a : admit) {
-      Slot& s = slots[a.first];
-      a.second->res.t_start = now_s();
-      a.second->res.slot = (int)a.first;
-      std::string err;
-      hsma_status st = dispatch(s, a.second, err);
-      if (st != HSMA_OK) {
-        (void)hipStreamSynchronize(s.stream);
-        a.second->res.status = st;
-        a.second->res.t_done = now_s();
-        s.req.reset();
-        std::lock_guard<std::mutex> lk(mu);
-        a.second->done = true;
-        cv_done.notify_all();
-      }
-    }
-    // retire finished requests
-    bool any = false;
-    for (Slot& s : slots) {
-      if (!s.req) continue;
-      if (hipEventQuery(s.done_ev) == hipSuccess) {
-        complete(s);
-        any = true;
-      }
-    }
-    if (!any && admit.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
-  }
-}
+}  // namespace
 
 extern "C" {
 
@@ -174,47 +328,77 @@ hsma_status hsma_server_create(const hsma_server_cfg* cfg, hsma_server** out) {
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "max_n and max_slots must be positive");
   if (cfg->max_n > hsma::max_particles(cfg->params.near_rule))
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "max_n is above the particles one call can take");
-  std::unique_ptr<hsma_server> sv(new hsma_server());
-  sv->cfg = *cfg;
-  std::string msg;
-  hsma::HostPlan hp;
-  const double lo0[3] = {0, 0, 0};
-  hsma_status st = hsma::build_host_plan(cfg->params, lo0, cfg->box_len, hp, msg);
-  if (st != HSMA_OK) return hsma::set_last_error(st, msg);
+  if (cfg->n_classes < 0 || (cfg->n_classes > 0 && !cfg->classes))
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "classes: NULL list or negative count");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return hsma::set_last_error(HSMA_ERR_NO_DEVICE, "no HIP device");
+  std::unique_ptr<hsma_server> sv(new hsma_server());
+  sv->cfg = *cfg;
+  sv->cfg.classes = nullptr;  // not kept
   (void)hipGetDevice(&sv->device);
+  std::string msg;
+  // the default class and the declared ones (grouped factorisation)
+  std::vector<hsma_class> decl(1);
+  decl[0].params = cfg->params;
+  for (int k = 0; k < 3; ++k) decl[0].box_len[k] = cfg->box_len[k];
+  for (int i = 0; i < cfg->n_classes; ++i) {
+    if (cfg->max_n > hsma::max_particles(cfg->classes[i].params.near_rule))
+      return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "max_n is above the particles one call can take");
+    decl.push_back(cfg->classes[i]);
+  }
+  hsma_status st;
+  try {
+    st = build_classes(decl, sv->classes, msg);
+  } catch (const std::bad_alloc&) {
+    return hsma::set_last_error(HSMA_ERR_OOM, "host allocation failed");
+  }
+  if (st != HSMA_OK) return hsma::set_last_error(st, msg);
+  // slot size: the per-class arenas share one buffer (the largest), the
+  // plan constants add up
+  size_t arena = 0, consts = 0;
+  for (const auto& c : sv->classes) {
+    hsma::DevicePlan probe;
+    probe.host = c->host;
+    arena = std::max(arena, probe.carve(cfg->max_n, nullptr));
+    const hsma::HostPlan& hp = c->host;
+    consts += sizeof(double) * 2 * (hp.Praw.size() + hp.SQ.size() * 2 + hp.ysurf.size() * 2) +
+              sizeof(hsma::Desc) * 2 * (hp.desc_particles.size() + hp.desc_check.size()) +
+              sizeof(double4) * 2 * hp.check_axis.size();
+  }
+  const int64_t io_bytes = (int64_t)sizeof(double) * (8 * cfg->max_n + 2);
+  sv->bytes_per_slot = (int64_t)arena + (int64_t)consts + io_bytes;
   size_t freeb = 0, totalb = 0;
   (void)hipMemGetInfo(&freeb, &totalb);
   const int64_t budget = cfg->hbm_budget > 0 ? cfg->hbm_budget : (int64_t)(freeb / 2);
-  for (int i = 0; i < cfg->max_slots; ++i) {
-    Slot s;
-    s.plan.reset(new hsma::DevicePlan());
-    s.plan->host = hp;
-    if ((st = s.plan->init(msg)) != HSMA_OK) return hsma::set_last_error(st, msg);
-    if ((st = s.plan->init_scalable(msg)) != HSMA_OK) return hsma::set_last_error(st, msg);
-    if ((st = s.plan->reserve(cfg->max_n, msg)) != HSMA_OK) return hsma::set_last_error(st, msg);
-    s.plan->use_graph = true;  // repeated sizes in a slot replay a captured step
+  const int nslots = (int)std::min<int64_t>(cfg->max_slots, budget / std::max<int64_t>(1, sv->bytes_per_slot));
+  if (nslots < 1) return hsma::set_last_error(HSMA_ERR_OOM, "HBM budget smaller than one slot");
+  sv->slots.resize(nslots);
+  sv->cb.resize(nslots);
+  for (int i = 0; i < nslots; ++i) {
+    Slot& s = sv->slots[i];
     s.cap = cfg->max_n;
-    const int64_t io_bytes = (int64_t)sizeof(double) * (8 * s.cap + 2);
-    const int64_t plan_bytes = (int64_t)(sizeof(double) * 2 * (hp.Praw.size() + hp.SQ.size() * 2 + hp.ysurf.size() * 2) +
-                                         sizeof(hsma::Desc) * 2 * (hp.desc_particles.size() + hp.desc_check.size()) +
-                                         sizeof(double4) * 2 * hp.check_axis.size());
-    const int64_t per = (int64_t)s.plan->arena_bytes + io_bytes + plan_bytes;
-    if (i == 0) sv->bytes_per_slot = per;
-    if ((int64_t)(i + 1) * per > budget) {
-      if (i == 0) return hsma::set_last_error(HSMA_ERR_OOM, "HBM budget smaller than one slot");
-      break;
-    }
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess ||
         hipMalloc((void**)&s.d_io, sizeof(double) * (8 * s.cap + 2)) != hipSuccess ||
-        hipHostMalloc((void**)&s.h_io, sizeof(double) * (8 * s.cap + 2)) != hipSuccess)
+        hipHostMalloc((void**)&s.h_io, sizeof(double) * (8 * s.cap + 2)) != hipSuccess ||
+        hipMalloc(&s.arena, arena) != hipSuccess) {
+      hsma_server* raw = sv.release();
+      hsma_server_destroy(raw);
       return hsma::set_last_error(HSMA_ERR_OOM, "slot allocation failed");
-    sv->slots.push_back(std::move(s));
+    }
+    s.arena_bytes = arena;
+    // the default class's plan in every slot up front (first requests do
+    // not pay for its upload)
+    hsma::DevicePlan* p = nullptr;
+    if ((st = slot_plan(sv.get(), s, 0, &p, msg)) != HSMA_OK) {
+      hsma_server* raw = sv.release();
+      hsma_server_destroy(raw);
+      return hsma::set_last_error(st, msg);
+    }
   }
-  hsma_server* raw = sv.get();
-  raw->th = std::thread([raw] { raw->loop(); });
+  sv->backend.reset(new GpuBackend(sv.get()));
+  sv->core.reset(new CoreT(*sv->backend, cfg->queue_capacity));
+  for (int i = 0; i < nslots; ++i) sv->cb[i] = CallbackCtx{sv->core.get(), i};
+  sv->core->start();
   *out = sv.release();
   return HSMA_OK;
 }
@@ -226,90 +410,99 @@ hsma_status hsma_server_get_slots(const hsma_server* s, int* nslots, int64_t* by
   return HSMA_OK;
 }
 
+hsma_status hsma_server_get_stats(const hsma_server* s, hsma_server_stats* out) {
+  if (!s || !out || !s->core) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  hsma_server* m = const_cast<hsma_server*>(s);
+  out->completed = s->core->completed();
+  out->affinity_hits = s->core->affinity_hits();
+  out->slots = (int)s->slots.size();
+  {
+    std::lock_guard<std::mutex> lk(m->class_mu);
+    out->classes = (int)s->classes.size();
+  }
+  out->graph_replays = m->graph_replays.load();
+  return HSMA_OK;
+}
+
 hsma_status hsma_server_submit(hsma_server* s, const hsma_request* req, uint64_t* ticket) {
   if (!s || !req || !ticket || !req->xyz || !req->q) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
   if (req->n < 1) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n must be >= 1");
   if (req->n > s->cfg.max_n) return hsma::set_last_error(HSMA_ERR_OOM, "request larger than a slot (max_n)");
-  if (!(req->scale > 0) || !std::isfinite(req->scale)) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "scale must be > 0");
+  if (req->flags & ~HSMA_REQ_DEVICE) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "unknown request flags");
+  const hsma_params& prm = req->params ? *req->params : s->cfg.params;
   double L[3];
-  for (int k = 0; k < 3; ++k) L[k] = s->cfg.box_len[k] * req->scale;
-  std::string msg;
-  hsma_status st = hsma::validate_host_input(s->cfg.params, req->box_lo, L, req->n, req->xyz, req->q, msg);
-  if (st != HSMA_OK) return hsma::set_last_error(st, msg);
-  auto r = std::make_shared<Req>();
-  r->n = req->n;
-  r->xyz.assign(req->xyz, req->xyz + 3 * req->n);
-  r->q.assign(req->q, req->q + req->n);
-  for (int k = 0; k < 3; ++k) r->lo[k] = req->box_lo[k];
-  r->scale = req->scale;
-  r->pot = req->potential;
-  r->force = req->force;
-  r->res.status = HSMA_OK;
-  r->res.slot = -1;
-  r->res.t_submit = now_s();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return hsma::set_last_error(HSMA_ERR_CANCELLED, "server is shutting down");
-    if (s->cfg.queue_capacity > 0 && (int)s->pending.size() >= s->cfg.queue_capacity)
-      return hsma::set_last_error(HSMA_ERR_BUSY, "request queue is full");
-    r->id = s->next_id++;
-    s->tickets[r->id] = r;
-    s->pending.push_back(r);
-    *ticket = r->id;
+  const bool given = req->box_len[0] != 0 || req->box_len[1] != 0 || req->box_len[2] != 0;
+  if (given) {
+    for (int k = 0; k < 3; ++k) L[k] = req->box_len[k];
+  } else {
+    if (!(req->scale > 0) || !std::isfinite(req->scale))
+      return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "scale must be > 0");
+    for (int k = 0; k < 3; ++k) L[k] = s->cfg.box_len[k] * req->scale;
   }
-  s->cv_work.notify_one();
+  std::string msg;
+  auto r = std::make_shared<Req>();
+  hsma_status st;
+  try {
+    st = s->find_or_create_class(prm, L, &r->cls, &r->payload.scale, msg);
+    if (st != HSMA_OK) return hsma::set_last_error(st, msg);
+    Payload& p = r->payload;
+    p.device = (req->flags & HSMA_REQ_DEVICE) != 0;
+    for (int k = 0; k < 3; ++k) p.lo[k] = req->box_lo[k];
+    p.pot = req->potential;
+    p.force = req->force;
+    if (p.device) {
+      p.d_xyz = req->xyz;
+      p.d_q = req->q;
+      p.energy = req->energy;
+      p.ready = (hipEvent_t)req->ready_event;
+    } else {
+      st = hsma::validate_host_input(prm, req->box_lo, L, req->n, req->xyz, req->q, msg);
+      if (st != HSMA_OK) return hsma::set_last_error(st, msg);
+      p.xyz.assign(req->xyz, req->xyz + 3 * req->n);
+      p.q.assign(req->q, req->q + req->n);
+    }
+  } catch (const std::bad_alloc&) {
+    return hsma::set_last_error(HSMA_ERR_OOM, "host allocation failed");
+  }
+  r->n = req->n;
+  r->system = req->system_id;
+  r->res.status = HSMA_OK;
+  st = s->core->submit(r, ticket, msg);
+  if (st != HSMA_OK) return hsma::set_last_error(st, msg);
   return HSMA_OK;
 }
 
 hsma_status hsma_server_wait(hsma_server* s, uint64_t ticket, hsma_result* out) {
   if (!s || !out) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
-  std::shared_ptr<Req> r;
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->tickets.find(ticket);
-  if (it == s->tickets.end()) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "unknown ticket");
-  r = it->second;
-  ++s->waiters;
-  s->cv_done.wait(lk, [&] { return r->done; });
-  *out = r->res;
-  s->tickets.erase(ticket);
-  if (--s->waiters == 0) s->cv_idle.notify_all();
-  if (out->status != HSMA_OK) hsma::set_last_error(out->status, "request failed");
-  return out->status;
+  std::string msg;
+  const hsma_status st = s->core->wait(ticket, out, msg);
+  if (st != HSMA_OK) hsma::set_last_error(st, msg);
+  return st;
 }
 
 void hsma_server_shutdown(hsma_server* s) {
-  if (!s) return;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-    for (auto& r : s->pending) {
-      r->res.status = HSMA_ERR_CANCELLED;
-      r->res.t_done = now_s();
-      r->done = true;
-    }
-    s->pending.clear();
-    s->cv_done.notify_all();
-  }
-  s->cv_work.notify_all();
-  if (s->th.joinable()) s->th.join();
+  if (!s || !s->core) return;
+  s->core->shutdown();
 }
 
 void hsma_server_destroy(hsma_server* s) {
   if (!s) return;
-  hsma_server_shutdown(s);
-  {
-    // threads already blocked in hsma_server_wait leave before the memory goes
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_idle.wait(lk, [&] { return s->waiters == 0; });
+  if (s->core) {
+    s->core->shutdown();
+    s->core->wait_idle();  // threads blocked in hsma_server_wait leave first
   }
   for (Slot& sl : s->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-    sl.plan.reset();
+    std::string err;
+    for (auto& p : sl.plans)
+      if (p) (void)p->wait_done(err);
+    sl.plans.clear();
+    if (sl.arena) (void)hipFree(sl.arena);
     if (sl.d_io) (void)hipFree(sl.d_io);
     if (sl.h_io) (void)hipHostFree(sl.h_io);
-    if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
+  s->core.reset();
   delete s;
 }
 

@@ -39,7 +39,7 @@ class _CParams(ctypes.Structure):
         ("surface_rule", ctypes.c_int), ("near_rule", ctypes.c_int), ("M", ctypes.c_int),
         ("gamma_up", ctypes.c_double),
         ("gamma_low", ctypes.c_double), ("nz", ctypes.c_int), ("coulomb_k", ctypes.c_double),
-        ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double),
+        ("tree_order", ctypes.c_int), ("tree_theta", ctypes.c_double), ("lsq_solver", ctypes.c_int),
     ]
 
 
@@ -56,20 +56,36 @@ class _CTiming(ctypes.Structure):
                 ("near_ms", ctypes.c_double), ("sphere_ms", ctypes.c_double)]
 
 
+class _CClass(ctypes.Structure):
+    _fields_ = [("params", _CParams), ("box_len", ctypes.c_double * 3)]
+
+
 class _CServerCfg(ctypes.Structure):
     _fields_ = [("params", _CParams), ("box_len", ctypes.c_double * 3), ("max_n", ctypes.c_int64),
-                ("max_slots", ctypes.c_int), ("hbm_budget", ctypes.c_int64), ("queue_capacity", ctypes.c_int)]
+                ("max_slots", ctypes.c_int), ("hbm_budget", ctypes.c_int64), ("queue_capacity", ctypes.c_int),
+                ("n_classes", ctypes.c_int), ("classes", ctypes.POINTER(_CClass))]
+
+
+REQ_DEVICE = 1
 
 
 class _CRequest(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("q", ctypes.c_void_p),
-                ("box_lo", ctypes.c_double * 3), ("scale", ctypes.c_double), ("potential", ctypes.c_void_p),
-                ("force", ctypes.c_void_p)]
+                ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double * 3), ("scale", ctypes.c_double),
+                ("params", ctypes.POINTER(_CParams)), ("potential", ctypes.c_void_p), ("force", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p), ("flags", ctypes.c_int), ("system_id", ctypes.c_uint64),
+                ("ready_event", ctypes.c_void_p)]
 
 
 class _CResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("energy", ctypes.c_double), ("t_submit", ctypes.c_double),
-                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("slot", ctypes.c_int)]
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("slot", ctypes.c_int),
+                ("replayed", ctypes.c_int), ("plan_class", ctypes.c_int)]
+
+
+class _CServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("affinity_hits", ctypes.c_int64),
+                ("classes", ctypes.c_int), ("slots", ctypes.c_int)]
 
 
 @dataclass
@@ -90,6 +106,7 @@ class Params:
     coulomb_k: float = 1.0
     tree_order: int = 8
     tree_theta: float = 0.5
+    lsq_solver: int = 0
 
     @staticmethod
     def from_workload(w, precision: Optional[int] = None) -> "Params":
@@ -100,7 +117,7 @@ class Params:
     def _c(self) -> _CParams:
         return _CParams(self.geometry, self.precision, self.lam, self.p, self.K, self.F, self.Fw,
                         self.surface_rule, self.near_rule, self.M, self.gamma_up, self.gamma_low, self.nz,
-                        self.coulomb_k, self.tree_order, self.tree_theta)
+                        self.coulomb_k, self.tree_order, self.tree_theta, self.lsq_solver)
 
 
 _lib = None
@@ -161,6 +178,8 @@ def load_library():
     lib.hsma_server_submit.argtypes = [vp, ctypes.POINTER(_CRequest), ctypes.POINTER(ctypes.c_uint64)]
     lib.hsma_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(_CResult)]
     lib.hsma_server_get_slots.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
+    lib.hsma_server_get_stats.argtypes = [vp, ctypes.POINTER(_CServerStats)]
+    lib.hsma_server_get_stats.restype = ctypes.c_int
     lib.hsma_server_destroy.argtypes = [vp]
     lib.hsma_server_shutdown.argtypes = [vp]
     for name in ("hsma_server_create", "hsma_server_submit", "hsma_server_wait", "hsma_server_get_slots"):
@@ -329,10 +348,11 @@ class Plan:
 
 
 class Server:
-    """Continuous-batching server for one plan class (hsma_server_*)."""
+    """Continuous-batching server (hsma_server_*): requests with their own
+    parameters and boxes (plan classes), host or device-resident."""
 
     def __init__(self, params: Params, box_len, max_n: int, max_slots: int = 8, hbm_budget: int = 0,
-                 queue_capacity: int = 0):
+                 queue_capacity: int = 0, classes=()):
         lib = load_library()
         self._lib = lib
         self._s = ctypes.c_void_p()
@@ -344,6 +364,13 @@ class Server:
         cfg.max_slots = int(max_slots)
         cfg.hbm_budget = int(hbm_budget)
         cfg.queue_capacity = int(queue_capacity)
+        arr = (_CClass * max(1, len(classes)))()
+        for i, (pp, bl) in enumerate(classes):
+            arr[i].params = pp._c()
+            for k in range(3):
+                arr[i].box_len[k] = float(bl[k])
+        cfg.n_classes = len(classes)
+        cfg.classes = ctypes.cast(arr, ctypes.POINTER(_CClass)) if classes else None
         _check(lib.hsma_server_create(ctypes.byref(cfg), ctypes.byref(self._s)))
         self._keep = {}
 
@@ -352,7 +379,21 @@ class Server:
         _check(self._lib.hsma_server_get_slots(self._s, ctypes.byref(n), ctypes.byref(b)))
         return n.value, b.value
 
-    def submit(self, xyz, q, box_lo, scale: float, potential: bool = True, force: bool = True) -> int:
+    def stats(self) -> dict:
+        st = _CServerStats()
+        _check(self._lib.hsma_server_get_stats(self._s, ctypes.byref(st)))
+        return {f[0]: getattr(st, f[0]) for f in _CServerStats._fields_}
+
+    @staticmethod
+    def _box(r, box_lo, scale, box_len):
+        for k in range(3):
+            r.box_lo[k] = float(box_lo[k])
+            r.box_len[k] = float(box_len[k]) if box_len is not None else 0.0
+        r.scale = float(scale) if scale is not None else 0.0
+
+    def submit(self, xyz, q, box_lo, scale: float = None, potential: bool = True, force: bool = True,
+               box_len=None, params: Params = None, system_id: int = 0) -> int:
+        """Host arrays in; results returned by wait()."""
         x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
         qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
         n = x.shape[0]
@@ -362,14 +403,41 @@ class Server:
         r.n = n
         r.xyz = x.ctypes.data
         r.q = qq.ctypes.data
-        for k in range(3):
-            r.box_lo[k] = float(box_lo[k])
-        r.scale = float(scale)
+        self._box(r, box_lo, scale, box_len)
+        cp = params._c() if params is not None else None
+        r.params = ctypes.pointer(cp) if cp is not None else None
         r.potential = pot.ctypes.data if pot is not None else None
         r.force = f.ctypes.data if f is not None else None
+        r.system_id = int(system_id)
         t = ctypes.c_uint64()
         _check(self._lib.hsma_server_submit(self._s, ctypes.byref(r), ctypes.byref(t)))
         self._keep[t.value] = (x, qq, pot, f)
+        return t.value
+
+    def submit_device(self, xyz, q, box_lo, scale: float = None, potential=None, force=None, energy=None,
+                      box_len=None, params: Params = None, system_id: int = 0, ready_event=None) -> int:
+        """Device-resident request: torch float64 tensors on the GPU, read and
+        written in place by the step (HSMA_REQ_DEVICE)."""
+        import torch
+        for t in (xyz, q, potential, force, energy):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError("device arguments must be contiguous float64 GPU tensors")
+        r = _CRequest()
+        r.n = xyz.shape[0]
+        r.xyz = xyz.data_ptr()
+        r.q = q.data_ptr()
+        self._box(r, box_lo, scale, box_len)
+        cp = params._c() if params is not None else None
+        r.params = ctypes.pointer(cp) if cp is not None else None
+        r.potential = potential.data_ptr() if potential is not None else None
+        r.force = force.data_ptr() if force is not None else None
+        r.energy = energy.data_ptr() if energy is not None else None
+        r.flags = REQ_DEVICE
+        r.system_id = int(system_id)
+        r.ready_event = ready_event.cuda_event if ready_event is not None else None
+        t = ctypes.c_uint64()
+        _check(self._lib.hsma_server_submit(self._s, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (xyz, q, potential, force)
         return t.value
 
     def wait(self, ticket: int) -> dict:

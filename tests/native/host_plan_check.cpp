@@ -10,6 +10,15 @@
 
 #include "../../paper_2104_05260_amd/csrc/hsma_internal.h"
 
+// The device least-squares solver lives in the HIP library; this host-only
+// build has no device, as hsma_plan_create would report without one.
+namespace hsma {
+hsma_status device_pinv_batch(std::vector<LsqJob>&, std::string& err) {
+  err = "no device in the host-only build";
+  return HSMA_ERR_NO_DEVICE;
+}
+}  // namespace hsma
+
 namespace {
 
 int failures = 0;

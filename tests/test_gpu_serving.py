@@ -169,3 +169,180 @@ def test_served_treecode():
              f"potential max rel {dp:.2e}")
         assert abs(b["energy"] - ref.energy) <= 1e-6 * abs(ref.energy) + 1e-7 * S
         assert df <= 1e-5 and dp <= 5e-5
+
+
+def _noncubic_params(prec=1, lsq=0):
+    # lambda 1.3: the sphere must stay inside the near cells of the shortest edge
+    return hs.Params(precision=prec, p=10, K=242, F=800, lam=1.3, lsq_solver=lsq)
+
+
+def _noncubic_system(n, L, seed):
+    box = (L, 1.2 * L, 0.9 * L)
+    pos, q, lo, _ = workloads.small_system(n, box, seed)
+    return pos + 0.7, q, lo + 0.7, box
+
+
+def test_two_class_mix_bitwise_and_oracle():
+    """Per-request parameters and box shapes through one server: p = 8 in
+    cubic boxes (the server's default class) and p = 10 in 1 : 1.2 : 0.9
+    boxes, two plan classes; every result is the same alone and in the mix
+    and agrees with the oracle (FP64 path, 1e-10)."""
+    _, cubic = mix(count=3, seed0=2400, n_lo=400, n_hi=1600)
+    other = [_noncubic_system(n, (n / 0.05) ** (1 / 3), 2500 + n) for n in (700, 1300)]
+    nmax = max([len(q) for _, _, q, _, _ in cubic] + [len(q) for _, q, _, _ in other])
+    prm_b = _noncubic_params(prec=0)
+
+    def submit_all(sv):
+        t = [sv.submit(pos, q, lo, L) for _, pos, q, lo, L in cubic]
+        t += [sv.submit(pos, q, lo, box_len=box, params=prm_b) for pos, q, lo, box in other]
+        return t
+
+    with hs.Server(params(0), UNIT, max_n=nmax, max_slots=4) as sv:
+        alone = [sv.wait(t) for t in submit_all(sv)]
+        together_t = submit_all(sv)
+        together = [sv.wait(t) for t in together_t]
+        st = sv.stats()
+    note(f"   server stats {st}; classes of the results {[r['plan_class'] for r in together]}")
+    assert st["classes"] == 2
+    assert [r["plan_class"] for r in together] == [0, 0, 0, 1, 1]
+    for a, b in zip(alone, together):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["energy"] == b["energy"] and np.array_equal(a["force"], b["force"])
+    refs = [ohsma.hsma3d(pos, q, lo, np.array([L, L, L]), 8, 162, 512, 1.5) for _, pos, q, lo, L in cubic]
+    refs += [ohsma.hsma3d(pos, q, lo, np.array(box), 10, 242, 800, 1.3) for pos, q, lo, box in other]
+    qs = [q for _, _, q, _, _ in cubic] + [q for _, q, _, _ in other]
+    for r, ref, q in zip(together, refs, qs):
+        S = 0.5 * np.abs(q * ref.potential).sum()
+        df = np.sqrt(((r["force"] - ref.force) ** 2).sum() / (ref.force ** 2).sum())
+        note(f"   n={len(q)} class {r['plan_class']}: dE/S {abs(r['energy'] - ref.energy) / S:.2e} force rel {df:.2e}")
+        assert abs(r["energy"] - ref.energy) <= 1e-10 * S and df <= 1e-10
+
+
+def test_device_resident_replicas_replay_graphs():
+    """Device-resident requests: positions and charges stay in HBM and the
+    outputs are written in place; the results equal the host requests'
+    bitwise.  Replicas resubmitted with their system ids return to their
+    slots, and from the third round on each step is a graph replay that
+    still reads the updated positions."""
+    import torch
+    dev = torch.device("cuda:0")
+    _, systems = mix(count=4, seed0=2600, n_lo=600, n_hi=2400)
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    reps = []
+    for _, pos, q, lo, L in systems:
+        n = len(q)
+        reps.append(dict(x=torch.tensor(pos, device=dev), q=torch.tensor(q, device=dev), lo=lo, L=L,
+                         pot=torch.zeros(n, dtype=torch.float64, device=dev),
+                         f=torch.zeros((n, 3), dtype=torch.float64, device=dev),
+                         e=torch.zeros(1, dtype=torch.float64, device=dev)))
+    rng = np.random.default_rng(5)
+    # the host-request references run on a second server, so that the
+    # replicas' slots see only their own systems
+    ref_sv = hs.Server(params(1), UNIT, max_n=nmax, max_slots=2)
+    with hs.Server(params(1), UNIT, max_n=nmax, max_slots=4) as sv:
+        for rnd in range(4):
+            torch.cuda.synchronize()  # the inputs are complete before submit
+            tickets = [sv.submit_device(r["x"], r["q"], r["lo"], r["L"], potential=r["pot"], force=r["f"],
+                                        energy=r["e"], system_id=i + 1) for i, r in enumerate(reps)]
+            res = [sv.wait(t) for t in tickets]
+            for i, (r, out) in enumerate(zip(reps, res)):
+                assert out["status"] == 0
+                if rnd >= 2:
+                    assert out["replayed"] == 1
+                # the same configuration as a host request: bitwise equal
+                href = ref_sv.wait(ref_sv.submit(r["x"].cpu().numpy(), r["q"].cpu().numpy(), r["lo"], r["L"]))
+                assert href["energy"] == out["energy"] == r["e"].item()
+                assert np.array_equal(href["force"], r["f"].cpu().numpy())
+                assert np.array_equal(href["potential"], r["pot"].cpu().numpy())
+            note(f"   round {rnd}: slots {[o['slot'] for o in res]} replayed {[o['replayed'] for o in res]}")
+            # move every replica on the device (as an MD or MC step would)
+            for r in reps:
+                r["x"] += torch.tensor(rng.normal(0, 0.01, tuple(r["x"].shape)), device=dev)
+        st = sv.stats()
+    ref_sv.close()
+    note(f"   stats {st}")
+    assert st["graph_replays"] >= 8 and st["affinity_hits"] >= 8
+
+
+@pytest.mark.parametrize("case", ["3d_p6", "3d_p10", "3d_p12_K800", "noncubic_p8", "slab_p10"])
+def test_device_lsq_matches_host_qr(case):
+    """The fit's pseudo-inverse from the device CholeskyQR2 (FP64 Gram
+    matrices on the matrix cores) against the host Householder QR: the
+    folded maps Praw agree to 1e-9 of their largest entry (condition numbers
+    up to 1e4), the condition estimates to 1e-6."""
+    box = (10.0, 10.0, 10.0)
+    if case == "3d_p6":
+        kw = dict(p=6, K=100, F=200, lam=1.5)
+    elif case == "3d_p10":
+        kw = dict(p=10, K=400, F=800, lam=1.5)
+    elif case == "3d_p12_K800":
+        kw = dict(p=12, K=800, F=1152, lam=1.5)
+    elif case == "noncubic_p8":
+        kw = dict(p=8, K=162, F=512, lam=1.3)
+        box = (10.0, 12.0, 9.0)
+    else:
+        kw = dict(geometry=1, p=10, K=400, F=800, lam=1.6, M=6, gamma_up=-0.94, gamma_low=-0.94, nz=40)
+        box = (40.0, 40.0, 20.0)
+    ph = hs.HostPlan(hs.Params(**kw, lsq_solver=0), (0, 0, 0), box)
+    pd = hs.HostPlan(hs.Params(**kw, lsq_solver=1), (0, 0, 0), box)
+    a, b = ph.get("Praw"), pd.get("Praw")
+    ca, cb = ph.get("scalars")[3], pd.get("scalars")[3]
+    err = np.abs(a - b).max() / np.abs(a).max()
+    note(f"   {case}: Praw rel diff {err:.2e}; cond host {ca:.4g} device {cb:.4g}")
+    assert err <= 1e-9 and abs(ca - cb) <= 1e-6 * ca
+
+
+def test_server_classes_grouped_device_lsq():
+    """Classes declared at server creation with the device solver: their
+    factorisations run together (grouped launches).  Results agree with
+    plans built by the host QR to 1e-10 (FP64 path)."""
+    decl = [(hs.Params(precision=0, p=6, K=100, F=200, lam=1.5, lsq_solver=1), (1.0, 1.0, 1.0)),
+            (hs.Params(precision=0, p=10, K=242, F=800, lam=1.3, lsq_solver=1), (1.0, 1.2, 0.9)),
+            (hs.Params(precision=0, p=8, K=200, F=512, lam=1.6, lsq_solver=1, geometry=1, M=6, gamma_up=-0.5,
+                       gamma_low=0.3, nz=40), (2.0, 2.0, 1.0))]
+    systems = [workloads.small_system(800, (20.0, 20.0, 20.0), 71),
+               workloads.small_system(900, (20.0, 24.0, 18.0), 72),
+               workloads.small_system(1000, (30.0, 30.0, 15.0), 73, geometry=1)]
+    boxes = [(20.0, 20.0, 20.0), (20.0, 24.0, 18.0), (30.0, 30.0, 15.0)]
+    with hs.Server(decl[0][0], decl[0][1], max_n=1000, max_slots=3, classes=decl[1:]) as sv:
+        assert sv.stats()["classes"] == 3
+        tickets = [sv.submit(pos, q, lo, box_len=box, params=prm)
+                   for (prm, _), (pos, q, lo, _), box in zip(decl, systems, boxes)]
+        res = [sv.wait(t) for t in tickets]
+        assert sv.stats()["classes"] == 3
+    for (prm, _), (pos, q, lo, _), box, r in zip(decl, systems, boxes, res):
+        import dataclasses
+        with hs.Plan(dataclasses.replace(prm, lsq_solver=0), lo, box) as plan:
+            e, pot, f = plan.compute(pos, q)
+        df = np.sqrt(((r["force"] - f) ** 2).sum() / (f ** 2).sum())
+        note(f"   class {r['plan_class']} n={len(q)}: energy {r['energy']:.15g} host-QR plan {e:.15g} force rel {df:.2e}")
+        assert r["status"] == 0 and abs(r["energy"] - e) <= 1e-10 * abs(e) and df <= 1e-10
+
+
+def test_served_parity_at_mix_sizes():
+    """Served FP32C results at the serving mix's largest sizes (about 20,000
+    and 12,000 ions) against the oracle at 96 sampled ions (its check sums
+    and fit use every ion), and the served FP32C energy against the served
+    FP64 energy to 1e-6."""
+    ws = [w for w in workloads.serving_systems(256) if w.n >= 12000][:2]
+    systems = []
+    for w in ws:
+        pos, q, lo, L = workloads.make_system(w)
+        systems.append((pos, q, lo, L[0]))
+    nmax = max(len(q) for _, q, _, _ in systems)
+    out = {}
+    for prec in (1, 0):
+        with hs.Server(params(prec), UNIT, max_n=nmax, max_slots=2) as sv:
+            tickets = [sv.submit(pos, q, lo, L) for pos, q, lo, L in systems]
+            out[prec] = [sv.wait(t) for t in tickets]
+    for (pos, q, lo, L), r32, r64 in zip(systems, out[1], out[0]):
+        sample = np.random.default_rng(len(q)).choice(len(q), 96, replace=False)
+        note(f"[serving] oracle at n={len(q)} (sampled)")
+        ref = ohsma.hsma3d(pos, q, lo, np.array([L, L, L]), 8, 162, 512, 1.5, targets=sample)
+        dp = np.abs(r32["potential"][sample] - ref.potential).max() / np.abs(ref.potential).max()
+        df = np.sqrt(((r32["force"][sample] - ref.force) ** 2).sum() / (ref.force ** 2).sum())
+        dp64 = np.abs(r64["potential"][sample] - ref.potential).max() / np.abs(ref.potential).max()
+        de = abs(r32["energy"] - r64["energy"]) / abs(r64["energy"])
+        note(f"   n={len(q)}: fp32c potential max rel {dp:.2e} force rms rel {df:.2e}; fp64 potential {dp64:.2e}; "
+             f"energy fp32c vs fp64 {de:.2e}")
+        assert dp <= 1e-5 and df <= 1e-5 and dp64 <= 1e-10 and de <= 1e-6

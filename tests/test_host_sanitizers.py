@@ -1,4 +1,4 @@
-"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU).
+"""Host code under the sanitizers (CPU).
 
 The library's host FP64 plan (plan.cpp: check points, image tables,
 pseudo-inverse, sphere maps, input validation) is compiled with g++ and the
@@ -32,5 +32,32 @@ def test_host_plan_under_asan_ubsan():
         run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
         assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
         assert "host plan checks passed" in run.stdout
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+@pytest.mark.parametrize("san", ["thread", "address,undefined"])
+def test_server_core_under_sanitizers(san):
+    """The serving core (queue, admission, completion, cancellation,
+    shutdown; paper_2104_05260_amd/csrc/server_core.h) driven on the CPU by a
+    fake backend that completes work from its own thread: 8 submitting and
+    waiting threads, launch failures, a full queue, shutdown with queued and
+    running requests, waiters blocked during destruction."""
+    tmp = tempfile.mkdtemp(prefix="hsma_core_")
+    try:
+        exe = os.path.join(tmp, "server_core_check")
+        cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", f"-fsanitize={san}",
+               "-fno-sanitize-recover=all", "-pthread",
+               "-I", os.path.join(ROOT, "paper_2104_05260_amd", "csrc"),
+               os.path.join(ROOT, "tests", "native", "server_core_check.cpp"), "-o", exe]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr[-3000:]
+        env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1")
+        for _ in range(3):
+            run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+            assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
+            assert "server core checks passed" in run.stdout
+            assert "WARNING" not in run.stderr
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
