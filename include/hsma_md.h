@@ -1,0 +1,75 @@
+/*
+ * hsma_md.h -- molecular dynamics on top of the HSMA hot path.
+ *
+ * Velocity-Verlet integration of charged soft spheres, the systems the
+ * paper integrates with HSMA as the electrostatics of an MD engine: the
+ * primitive electrolytes of Sec. 4.1 (ions as purely repulsive
+ * Lennard-Jones spheres, cut at the potential minimum) and, in the slab
+ * geometry, the ions between two dielectric interfaces of Sec. 4.3 (kept
+ * inside by repulsive Lennard-Jones walls).  Per step:
+ *   v += dt/2 F/m;  x += dt v (wrapped along the periodic axes);
+ *   F = F_Coulomb (the plan's step, F_i = q_i E_i) + F_LJ (pairs, walls);
+ *   v += dt/2 F/m;  thermo row.
+ * Everything runs on the device on the caller's buffers; the plan's step is
+ * replayed from a captured HIP graph after the first steps.
+ *
+ * Thermo row per step (4 doubles): E_Coulomb, E_LJ (pairs + walls),
+ * E_kinetic, and the pressure P = (2 E_kin + W_LJ + W_C) / (3 V) of the
+ * fully periodic geometry, with W_LJ = sum over pairs r_ij . F_ij and
+ * W_C = E_Coulomb: the HSMA energy is homogeneous of degree -1 under
+ * scaling of positions and box together (E(s r, s L) = E / s), so its
+ * volume derivative gives exactly that virial.  In the slab geometry the
+ * fourth value is the LJ part (2 E_kin + W_LJ) / (3 V) only.
+ *
+ * Layouts as in hsma.h: positions, velocities, forces n x 3 row-major FP64;
+ * charges and masses n FP64.  Positions must lie in the plan's box (slab: z
+ * strictly between the walls).  Units: those of the plan (its coulomb_k is
+ * the Coulomb prefactor, e.g. the Bjerrum length in units of kT).
+ */
+#ifndef HSMA_MD_H
+#define HSMA_MD_H
+
+#include <stdint.h>
+
+#include "hsma.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsma_md_params {
+  double dt;            /* time step                                            */
+  double lj_epsilon;    /* pair potential 4 eps [(sig/r)^12 - (sig/r)^6] + eps   */
+  double lj_sigma;      /*   for r < lj_rcut (shifted to 0 at the cut)           */
+  double lj_rcut;       /*   (0: 2^(1/6) sigma, purely repulsive)  must be below
+                             half the shortest periodic box edge                  */
+  double wall_epsilon;  /* slab: the same form in the distance to each wall      */
+  double wall_sigma;    /*   (wall_epsilon 0: no walls)                          */
+  double wall_rcut;     /*   (0: 2^(1/6) wall_sigma)                             */
+} hsma_md_params;
+
+typedef struct hsma_md hsma_md;
+
+/* A driver for n particles integrated with `plan` (which must outlive it).
+ * Errors: INVALID_ARG (n, parameters, a cut-off above half a box edge),
+ * OOM, DEVICE.                                                           */
+hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* params, int64_t n, hsma_md** out);
+
+/* Runs nsteps steps on `stream` (a hipStream_t; asynchronous).  d_f holds
+ * the forces at d_x on return; forces_valid = 1 says it already holds them
+ * on entry (from the previous call), else they are computed first.
+ * d_thermo: nsteps x 4 device doubles, or NULL.                          */
+hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, double* d_v, double* d_f,
+                        const double* d_q, const double* d_m, int forces_valid, double* d_thermo);
+
+/* Forces (Coulomb + LJ) at d_x into d_f, and one thermo row whose kinetic
+ * energy is taken from d_v (may be NULL: 0).                            */
+hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
+                           const double* d_q, const double* d_m, double* d_thermo_row);
+
+void hsma_md_destroy(hsma_md* md);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSMA_MD_H */

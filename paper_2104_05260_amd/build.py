@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsma.so")
-SOURCES = ["plan.cpp", "kernels.hip", "lsq.hip", "capi.cpp", "server.cpp"]
+SOURCES = ["plan.cpp", "kernels.hip", "lsq.hip", "md.hip", "capi.cpp", "server.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed FP32 (v_pk_*_f32) stays off: all FP32 arithmetic is scalar VALU

@@ -9,9 +9,6 @@
 
 #include "device.h"
 
-struct hsma_plan {
-  hsma::DevicePlan dev;
-};
 
 namespace {
 thread_local std::string g_err;

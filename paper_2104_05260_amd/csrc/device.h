@@ -197,3 +197,8 @@ struct DevicePlan {
 };
 
 }  // namespace hsma
+
+// The C interface's plan handle (include/hsma.h).
+struct hsma_plan {
+  hsma::DevicePlan dev;
+};

@@ -1,0 +1,319 @@
+// Velocity-Verlet molecular dynamics with HSMA electrostatics (see
+// include/hsma_md.h): the integration, short-range Lennard-Jones forces and
+// thermo kernels, and the C interface.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "../../include/hsma_md.h"
+#include "device.h"
+
+namespace hsma {
+namespace {
+
+constexpr int kMdBlock = 256;
+
+struct MdBox {
+  double lo[3], L[3];
+  int slab;  // z not periodic (walls at lo[2] and lo[2] + L[2])
+};
+
+struct MdLJ {
+  double eps, sig2, rc2, shift;     // pairs: 4 eps [(s/r)^12 - (s/r)^6] + shift, r < rc
+  double weps, wsig, wrc, wshift;   // walls, same form in the distance d to a wall
+};
+
+// v += dt/2 F/m; x += dt v; wrapped into [lo, lo + L) along periodic axes.
+__global__ __launch_bounds__(kMdBlock) void k_md_kick_drift(int n, double dt, double* __restrict__ x,
+                                                            double* __restrict__ v, const double* __restrict__ f,
+                                                            const double* __restrict__ m, MdBox box) {
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  if (i >= n) return;
+  const double h = 0.5 * dt / m[i];
+  for (int k = 0; k < 3; ++k) {
+    const double vk = v[3 * i + k] + h * f[3 * i + k];
+    v[3 * i + k] = vk;
+    double xk = x[3 * i + k] + dt * vk;
+    if (k < 2 || !box.slab) xk -= box.L[k] * floor((xk - box.lo[k]) / box.L[k]);
+    x[3 * i + k] = xk;
+  }
+}
+
+// Lennard-Jones forces added to f (pairs by the minimum image, every pair
+// in a fixed order per particle; walls in the slab), and per-block sums of
+// the energy (1/2 per pair side, walls in full) and of the pair virial
+// r . F (1/2 per side).  Sources staged through LDS in tiles of kMdBlock.
+__global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restrict__ x, MdBox box, MdLJ lj,
+                                                    double* __restrict__ f, double* __restrict__ part) {
+  __shared__ double sx[kMdBlock], sy[kMdBlock], sz[kMdBlock];
+  __shared__ double re[kMdBlock], rw[kMdBlock];
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  const bool ok = i < n;
+  double xi = 0, yi = 0, zi = 0;
+  if (ok) {
+    xi = x[3 * i];
+    yi = x[3 * i + 1];
+    zi = x[3 * i + 2];
+  }
+  double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
+  for (int j0 = 0; j0 < n; j0 += kMdBlock) {
+    const int j = j0 + threadIdx.x;
+    __syncthreads();
+    if (j < n) {
+      sx[threadIdx.x] = x[3 * j];
+      sy[threadIdx.x] = x[3 * j + 1];
+      sz[threadIdx.x] = x[3 * j + 2];
+    }
+    __syncthreads();
+    const int jn = min(kMdBlock, n - j0);
+    if (!ok) continue;
+    for (int jj = 0; jj < jn; ++jj) {
+      if (j0 + jj == i) continue;
+      double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
+      dx -= box.L[0] * rint(dx / box.L[0]);
+      dy -= box.L[1] * rint(dy / box.L[1]);
+      if (!box.slab) dz -= box.L[2] * rint(dz / box.L[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 >= lj.rc2) continue;
+      const double s2 = lj.sig2 / r2, s6 = s2 * s2 * s2;
+      const double fr = 24.0 * lj.eps * (2.0 * s6 * s6 - s6) / r2;  // F = fr d
+      fx += fr * dx;
+      fy += fr * dy;
+      fz += fr * dz;
+      e += 0.5 * (4.0 * lj.eps * (s6 * s6 - s6) + lj.shift);
+      w += 0.5 * fr * r2;
+    }
+    if (box.slab && lj.weps > 0.0 && j0 + kMdBlock >= n) {
+      // walls at z = lo and z = lo + L, once per particle (last tile)
+      const double dlo = zi - box.lo[2], dhi = box.lo[2] + box.L[2] - zi;
+      const double ds[2] = {dlo, dhi};
+      for (int s = 0; s < 2; ++s) {
+        const double d = ds[s];
+        if (d >= lj.wrc) continue;
+        const double sd = lj.wsig / d, s6 = sd * sd * sd * sd * sd * sd;
+        const double fd = 24.0 * lj.weps * (2.0 * s6 * s6 - s6) / d;  // away from the wall
+        fz += s == 0 ? fd : -fd;
+        e += 4.0 * lj.weps * (s6 * s6 - s6) + lj.wshift;
+      }
+    }
+  }
+  if (ok) {
+    f[3 * i] += fx;
+    f[3 * i + 1] += fy;
+    f[3 * i + 2] += fz;
+  }
+  re[threadIdx.x] = ok ? e : 0.0;
+  rw[threadIdx.x] = ok ? w : 0.0;
+  __syncthreads();
+  for (int o = kMdBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      re[threadIdx.x] += re[threadIdx.x + o];
+      rw[threadIdx.x] += rw[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = re[0];
+    part[2 * blockIdx.x + 1] = rw[0];
+  }
+}
+
+// v += dt/2 F/m (dt = 0: velocities unchanged), and per-block sums of the
+// kinetic energy 1/2 m v^2.
+__global__ __launch_bounds__(kMdBlock) void k_md_kick(int n, double dt, double* __restrict__ v,
+                                                      const double* __restrict__ f, const double* __restrict__ m,
+                                                      double* __restrict__ part) {
+  __shared__ double rk[kMdBlock];
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  double ke = 0.0;
+  if (i < n && v) {
+    const double h = 0.5 * dt / m[i];
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double vk = v[3 * i + k] + h * f[3 * i + k];
+      if (dt != 0.0) v[3 * i + k] = vk;
+      s += vk * vk;
+    }
+    ke = 0.5 * m[i] * s;
+  }
+  rk[threadIdx.x] = ke;
+  __syncthreads();
+  for (int o = kMdBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) rk[threadIdx.x] += rk[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = rk[0];
+}
+
+// Thermo row: E_C, E_LJ, E_kin, P (fixed-order sums of the block partials).
+__global__ __launch_bounds__(64) void k_md_thermo(int nblk, const double* __restrict__ lj_part,
+                                                  const double* __restrict__ ke_part,
+                                                  const double* __restrict__ e_coul, double volume, int slab,
+                                                  double* __restrict__ row) {
+  if (threadIdx.x != 0) return;
+  double elj = 0, wlj = 0, ke = 0;
+  for (int b = 0; b < nblk; ++b) {
+    elj += lj_part[2 * b];
+    wlj += lj_part[2 * b + 1];
+    ke += ke_part[b];
+  }
+  const double ec = *e_coul;
+  row[0] = ec;
+  row[1] = elj;
+  row[2] = ke;
+  row[3] = (2.0 * ke + wlj + (slab ? 0.0 : ec)) / (3.0 * volume);
+}
+
+}  // namespace
+}  // namespace hsma
+
+struct hsma_md {
+  hsma_plan* plan = nullptr;
+  hsma_md_params prm{};
+  int64_t n = 0;
+  hsma::MdBox box{};
+  hsma::MdLJ lj{};
+  int nblk = 0;
+  double* d_lj_part = nullptr;  // 2 x nblk
+  double* d_ke_part = nullptr;  // nblk
+  double* d_ecoul = nullptr;
+  double* d_row = nullptr;      // 4: thermo row when the caller passes none
+  hipEvent_t ev = nullptr;      // end of the driver's last call (its kernels follow the plan's)
+  bool recorded = false;
+};
+
+namespace {
+
+// F = F_Coulomb (the plan's step) + F_LJ at x; one thermo row (E_kin from v).
+hsma_status md_forces(hsma_md* md, hipStream_t st, const double* x, const double* v, double* f, const double* q,
+                      const double* m, double* row, std::string& err) {
+  const int n = (int)md->n;
+  hsma_status s = md->plan->dev.run(st, n, x, q, md->d_ecoul, nullptr, f, err);
+  if (s != HSMA_OK) return s;
+  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, x, md->box, md->lj, f,
+                     md->d_lj_part);
+  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, 0.0, const_cast<double*>(v),
+                     (const double*)f, m, md->d_ke_part);
+  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
+  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
+                     (const double*)md->d_ke_part, (const double*)md->d_ecoul, vol, md->box.slab,
+                     row ? row : md->d_row);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    err = std::string("md kernels: ") + hipGetErrorString(e);
+    return HSMA_ERR_DEVICE;
+  }
+  return HSMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* p, int64_t n, hsma_md** out) {
+  if (!plan || !p || !out) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (n < 2 || n > hsma::max_particles(plan->dev.host.prm.near_rule))
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range");
+  if (!(p->dt > 0) || !std::isfinite(p->dt) || !(p->lj_epsilon >= 0) || !(p->lj_sigma > 0) || !(p->lj_rcut >= 0) ||
+      !(p->wall_epsilon >= 0) || !(p->wall_rcut >= 0) || (p->wall_epsilon > 0 && !(p->wall_sigma > 0)))
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "invalid MD parameter");
+  std::unique_ptr<hsma_md> md(new (std::nothrow) hsma_md());
+  if (!md) return hsma::set_last_error(HSMA_ERR_OOM, "host allocation failed");
+  md->plan = plan;
+  md->prm = *p;
+  md->n = n;
+  const hsma::HostPlan& hp = plan->dev.host;
+  for (int k = 0; k < 3; ++k) {
+    md->box.lo[k] = hp.lo[k];
+    md->box.L[k] = hp.L[k];
+  }
+  md->box.slab = hp.prm.geometry == HSMA_GEOM_2D;
+  const double k6 = std::pow(2.0, 1.0 / 6.0);
+  const double rc = p->lj_rcut > 0 ? p->lj_rcut : k6 * p->lj_sigma;
+  const double half = 0.5 * std::min(hp.L[0], std::min(hp.L[1], md->box.slab ? INFINITY : hp.L[2]));
+  if (!(rc < half)) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "LJ cut-off must be below half a box edge");
+  const double sr6 = std::pow(p->lj_sigma / rc, 6.0);
+  md->lj.eps = p->lj_epsilon;
+  md->lj.sig2 = p->lj_sigma * p->lj_sigma;
+  md->lj.rc2 = rc * rc;
+  md->lj.shift = -4.0 * p->lj_epsilon * (sr6 * sr6 - sr6);
+  md->lj.weps = p->wall_epsilon;
+  md->lj.wsig = p->wall_sigma;
+  md->lj.wrc = p->wall_epsilon > 0 ? (p->wall_rcut > 0 ? p->wall_rcut : k6 * p->wall_sigma) : 0.0;
+  if (p->wall_epsilon > 0) {
+    const double w6 = std::pow(p->wall_sigma / md->lj.wrc, 6.0);
+    md->lj.wshift = -4.0 * p->wall_epsilon * (w6 * w6 - w6);
+  }
+  md->nblk = (int)((n + hsma::kMdBlock - 1) / hsma::kMdBlock);
+  if (hipMalloc((void**)&md->d_lj_part, sizeof(double) * 2 * md->nblk) != hipSuccess ||
+      hipMalloc((void**)&md->d_ke_part, sizeof(double) * md->nblk) != hipSuccess ||
+      hipMalloc((void**)&md->d_ecoul, sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&md->d_row, sizeof(double) * 4) != hipSuccess ||
+      hipEventCreateWithFlags(&md->ev, hipEventDisableTiming) != hipSuccess) {
+    hsma_md_destroy(md.release());
+    return hsma::set_last_error(HSMA_ERR_OOM, "device allocation failed");
+  }
+  plan->dev.use_graph = true;  // the Coulomb step replays from a captured graph
+  *out = md.release();
+  return HSMA_OK;
+}
+
+hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
+                           const double* d_q, const double* d_m, double* d_thermo_row) {
+  if (!md || !d_x || !d_f || !d_q || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  std::string err;
+  const hsma_status s = md_forces(md, (hipStream_t)stream, d_x, d_v, d_f, d_q, d_m, d_thermo_row, err);
+  if (s != HSMA_OK) return hsma::set_last_error(s, err);
+  if (hipEventRecord(md->ev, (hipStream_t)stream) != hipSuccess)
+    return hsma::set_last_error(HSMA_ERR_DEVICE, "hipEventRecord failed");
+  md->recorded = true;
+  return HSMA_OK;
+}
+
+hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, double* d_v, double* d_f,
+                        const double* d_q, const double* d_m, int forces_valid, double* d_thermo) {
+  if (!md || !d_x || !d_v || !d_f || !d_q || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (nsteps < 0) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "nsteps must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  std::string err;
+  hsma_status s;
+  if (!forces_valid && (s = md_forces(md, st, d_x, d_v, d_f, d_q, d_m, nullptr, err)) != HSMA_OK)
+    return hsma::set_last_error(s, err);
+  const int n = (int)md->n;
+  for (int step = 0; step < nsteps; ++step) {
+    hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, d_x, d_v,
+                       (const double*)d_f, d_m, md->box);
+    s = md->plan->dev.run(st, n, d_x, d_q, md->d_ecoul, nullptr, d_f, err);
+    if (s != HSMA_OK) return hsma::set_last_error(s, err);
+    hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, (const double*)d_x, md->box,
+                       md->lj, d_f, md->d_lj_part);
+    hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, d_v,
+                       (const double*)d_f, d_m, md->d_ke_part);
+    const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
+    hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
+                       (const double*)md->d_ke_part, (const double*)md->d_ecoul, vol, md->box.slab,
+                       d_thermo ? d_thermo + 4 * (size_t)step : md->d_row);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
+  if (hipEventRecord(md->ev, st) != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, "hipEventRecord failed");
+  md->recorded = true;
+  return HSMA_OK;
+}
+
+void hsma_md_destroy(hsma_md* md) {
+  if (!md) return;
+  if (md->recorded) (void)hipEventSynchronize(md->ev);  // after the plan's work on the same stream
+  void* ps[] = {md->d_lj_part, md->d_ke_part, md->d_ecoul, md->d_row};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  if (md->ev) (void)hipEventDestroy(md->ev);
+  delete md;
+}
+
+}  // extern "C"

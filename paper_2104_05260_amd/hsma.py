@@ -83,6 +83,12 @@ class _CResult(ctypes.Structure):
                 ("replayed", ctypes.c_int), ("plan_class", ctypes.c_int)]
 
 
+class _CMDParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("lj_epsilon", ctypes.c_double), ("lj_sigma", ctypes.c_double),
+                ("lj_rcut", ctypes.c_double), ("wall_epsilon", ctypes.c_double), ("wall_sigma", ctypes.c_double),
+                ("wall_rcut", ctypes.c_double)]
+
+
 class _CServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("affinity_hits", ctypes.c_int64),
                 ("classes", ctypes.c_int), ("slots", ctypes.c_int)]
@@ -179,6 +185,12 @@ def load_library():
     lib.hsma_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(_CResult)]
     lib.hsma_server_get_slots.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
     lib.hsma_server_get_stats.argtypes = [vp, ctypes.POINTER(_CServerStats)]
+    lib.hsma_md_create.argtypes = [vp, ctypes.POINTER(_CMDParams), i64, ctypes.POINTER(vp)]
+    lib.hsma_md_run.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    lib.hsma_md_forces.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hsma_md_destroy.argtypes = [vp]
+    for name in ("hsma_md_create", "hsma_md_run", "hsma_md_forces"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.hsma_server_get_stats.restype = ctypes.c_int
     lib.hsma_server_destroy.argtypes = [vp]
     lib.hsma_server_shutdown.argtypes = [vp]
@@ -458,6 +470,61 @@ class Server:
         if self._s:
             self._lib.hsma_server_destroy(self._s)
             self._s = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MD:
+    """Velocity-Verlet MD with HSMA electrostatics (hsma_md_*): device
+    tensors (float64, contiguous) are integrated in place."""
+
+    def __init__(self, plan: "Plan", n: int, dt: float, lj_epsilon: float = 1.0, lj_sigma: float = 1.0,
+                 lj_rcut: float = 0.0, wall_epsilon: float = 0.0, wall_sigma: float = 1.0, wall_rcut: float = 0.0):
+        lib = load_library()
+        self._lib = lib
+        self._plan = plan  # kept alive: the driver uses it
+        self._m = ctypes.c_void_p()
+        p = _CMDParams(dt, lj_epsilon, lj_sigma, lj_rcut, wall_epsilon, wall_sigma, wall_rcut)
+        _check(lib.hsma_md_create(plan._p, ctypes.byref(p), int(n), ctypes.byref(self._m)))
+
+    @staticmethod
+    def _ptr(t):
+        import torch
+        if t is None:
+            return None
+        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("device arguments must be contiguous float64 GPU tensors")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def run(self, x, v, f, q, m, nsteps: int, forces_valid: bool = False, thermo=None, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self._lib.hsma_md_run(self._m, ctypes.c_void_p(stream), int(nsteps), self._ptr(x), self._ptr(v),
+                                     self._ptr(f), self._ptr(q), self._ptr(m), 1 if forces_valid else 0,
+                                     self._ptr(thermo)))
+
+    def forces(self, x, v, f, q, m, thermo_row=None, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self._lib.hsma_md_forces(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v), self._ptr(f),
+                                        self._ptr(q), self._ptr(m), self._ptr(thermo_row)))
+
+    def close(self):
+        if self._m:
+            self._lib.hsma_md_destroy(self._m)
+            self._m = ctypes.c_void_p()
 
     def __enter__(self):
         return self

@@ -25,11 +25,10 @@ def test_library_exports_every_declared_symbol():
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     names = []
-    for h in ("hsma.h", "hsma_debug.h", "hsma_server.h"):
-        path = os.path.join(root, "include", h)
-        if not os.path.exists(path):
-            continue
-        src = open(path).read()
+    headers = sorted(f for f in os.listdir(os.path.join(root, "include")) if f.endswith(".h"))
+    assert {"hsma.h", "hsma_debug.h", "hsma_server.h", "hsma_md.h"} <= set(headers)
+    for h in headers:
+        src = open(os.path.join(root, "include", h)).read()
         names += re.findall(r"\b(hsma_[a-z_0-9]+)\s*\(", src)
     names = sorted(set(names))
     assert "hsma_compute" in names and "hsma_plan_create" in names
