@@ -67,6 +67,23 @@ hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, doub
 hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
                            const double* d_q, const double* d_m, double* d_thermo_row);
 
+/* A driver without a plan, for steps whose Coulomb forces come from
+ * elsewhere (e.g. a device request to hsma_server): geometry and box as in
+ * hsma_plan_create.  hsma_md_run and hsma_md_forces need a plan and refuse
+ * it (INVALID_ARG); the two halves of a step below work on any driver.   */
+hsma_status hsma_md_create_for_box(const hsma_md_params* params, int geometry, const double box_lo[3],
+                                   const double box_len[3], int64_t n, hsma_md** out);
+
+/* First half of a step: v += dt/2 F/m, x += dt v (wrapped).              */
+hsma_status hsma_md_drift(hsma_md* md, void* stream, double* d_x, double* d_v, const double* d_f,
+                          const double* d_m);
+
+/* Second half, once d_f holds the Coulomb forces at the new d_x and
+ * d_e_coulomb their energy (device scalar): F += F_LJ, v += dt/2 F/m, and
+ * one thermo row (device, 4 doubles, or NULL).                          */
+hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double* d_v, double* d_f,
+                           const double* d_m, const double* d_e_coulomb, double* d_thermo_row);
+
 void hsma_md_destroy(hsma_md* md);
 
 #ifdef __cplusplus

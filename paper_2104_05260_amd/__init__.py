@@ -5,6 +5,6 @@ HIP kernels of libhsma.so.  Importing works without a GPU; plan creation
 needs one (HSMA_ERR_NO_DEVICE otherwise).
 """
 from .hsma import (  # noqa: F401
-    HSMAError, Params, Plan, HostPlan, Server, MD, lib_path, load_library, solid_harmonics, hilbert_key,
+    HSMAError, Params, Plan, HostPlan, Server, MD, ReplicaEnsemble, lib_path, load_library, solid_harmonics, hilbert_key,
     STATUS, GEOM_3D, GEOM_2D, FP64, FP32C,
 )

@@ -214,11 +214,38 @@ hsma_status md_forces(hsma_md* md, hipStream_t st, const double* x, const double
 
 extern "C" {
 
+namespace {
+hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, const double lo[3],
+                      const double L[3], int64_t n, hsma_md** out);
+}
+
 hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* p, int64_t n, hsma_md** out) {
   if (!plan || !p || !out) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
   if (n < 2 || n > hsma::max_particles(plan->dev.host.prm.near_rule))
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range");
+  const hsma::HostPlan& hp = plan->dev.host;
+  const hsma_status s = md_create(plan, p, hp.prm.geometry, hp.lo, hp.L, n, out);
+  if (s == HSMA_OK) plan->dev.use_graph = true;  // the Coulomb step replays from a captured graph
+  return s;
+}
+
+hsma_status hsma_md_create_for_box(const hsma_md_params* p, int geometry, const double box_lo[3],
+                                   const double box_len[3], int64_t n, hsma_md** out) {
+  if (!p || !out || !box_lo || !box_len) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (n < 2 || n > ((int64_t)1 << 30) - 1) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range");
+  if (geometry != HSMA_GEOM_3D && geometry != HSMA_GEOM_2D)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "geometry must be HSMA_GEOM_3D or HSMA_GEOM_2D");
+  for (int k = 0; k < 3; ++k)
+    if (!(box_len[k] > 0) || !std::isfinite(box_len[k]) || !std::isfinite(box_lo[k]))
+      return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "box lengths must be finite and positive");
+  return md_create(nullptr, p, geometry, box_lo, box_len, n, out);
+}
+
+namespace {
+hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, const double lo[3],
+                      const double L[3], int64_t n, hsma_md** out) {
   if (!(p->dt > 0) || !std::isfinite(p->dt) || !(p->lj_epsilon >= 0) || !(p->lj_sigma > 0) || !(p->lj_rcut >= 0) ||
       !(p->wall_epsilon >= 0) || !(p->wall_rcut >= 0) || (p->wall_epsilon > 0 && !(p->wall_sigma > 0)))
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "invalid MD parameter");
@@ -227,15 +254,14 @@ hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* p, int64_t n, 
   md->plan = plan;
   md->prm = *p;
   md->n = n;
-  const hsma::HostPlan& hp = plan->dev.host;
   for (int k = 0; k < 3; ++k) {
-    md->box.lo[k] = hp.lo[k];
-    md->box.L[k] = hp.L[k];
+    md->box.lo[k] = lo[k];
+    md->box.L[k] = L[k];
   }
-  md->box.slab = hp.prm.geometry == HSMA_GEOM_2D;
+  md->box.slab = geometry == HSMA_GEOM_2D;
   const double k6 = std::pow(2.0, 1.0 / 6.0);
   const double rc = p->lj_rcut > 0 ? p->lj_rcut : k6 * p->lj_sigma;
-  const double half = 0.5 * std::min(hp.L[0], std::min(hp.L[1], md->box.slab ? INFINITY : hp.L[2]));
+  const double half = 0.5 * std::min(L[0], std::min(L[1], md->box.slab ? INFINITY : L[2]));
   if (!(rc < half)) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "LJ cut-off must be below half a box edge");
   const double sr6 = std::pow(p->lj_sigma / rc, 6.0);
   md->lj.eps = p->lj_epsilon;
@@ -258,14 +284,46 @@ hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* p, int64_t n, 
     hsma_md_destroy(md.release());
     return hsma::set_last_error(HSMA_ERR_OOM, "device allocation failed");
   }
-  plan->dev.use_graph = true;  // the Coulomb step replays from a captured graph
   *out = md.release();
+  return HSMA_OK;
+}
+}  // namespace
+
+hsma_status hsma_md_drift(hsma_md* md, void* stream, double* d_x, double* d_v, const double* d_f,
+                          const double* d_m) {
+  if (!md || !d_x || !d_v || !d_f || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, (hipStream_t)stream,
+                     (int)md->n, md->prm.dt, d_x, d_v, d_f, d_m, md->box);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
+  return HSMA_OK;
+}
+
+hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double* d_v, double* d_f,
+                           const double* d_m, const double* d_e_coulomb, double* d_thermo_row) {
+  if (!md || !d_x || !d_v || !d_f || !d_m || !d_e_coulomb)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int n = (int)md->n;
+  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, d_x, md->box, md->lj, d_f,
+                     md->d_lj_part);
+  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, d_v,
+                     (const double*)d_f, d_m, md->d_ke_part);
+  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
+  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
+                     (const double*)md->d_ke_part, d_e_coulomb, vol, md->box.slab,
+                     d_thermo_row ? d_thermo_row : md->d_row);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
+  if (hipEventRecord(md->ev, st) != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, "hipEventRecord failed");
+  md->recorded = true;
   return HSMA_OK;
 }
 
 hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
                            const double* d_q, const double* d_m, double* d_thermo_row) {
   if (!md || !d_x || !d_f || !d_q || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (!md->plan) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "this driver has no plan (hsma_md_create_for_box)");
   std::string err;
   const hsma_status s = md_forces(md, (hipStream_t)stream, d_x, d_v, d_f, d_q, d_m, d_thermo_row, err);
   if (s != HSMA_OK) return hsma::set_last_error(s, err);
@@ -279,6 +337,7 @@ hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, doub
                         const double* d_q, const double* d_m, int forces_valid, double* d_thermo) {
   if (!md || !d_x || !d_v || !d_f || !d_q || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
   if (nsteps < 0) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (!md->plan) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "this driver has no plan (hsma_md_create_for_box)");
   hipStream_t st = (hipStream_t)stream;
   std::string err;
   hsma_status s;

@@ -189,7 +189,11 @@ def load_library():
     lib.hsma_md_run.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     lib.hsma_md_forces.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hsma_md_destroy.argtypes = [vp]
-    for name in ("hsma_md_create", "hsma_md_run", "hsma_md_forces"):
+    lib.hsma_md_create_for_box.argtypes = [ctypes.POINTER(_CMDParams), ctypes.c_int, d, d, i64, ctypes.POINTER(vp)]
+    lib.hsma_md_drift.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.hsma_md_finish.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    for name in ("hsma_md_create", "hsma_md_run", "hsma_md_forces", "hsma_md_create_for_box", "hsma_md_drift",
+                 "hsma_md_finish"):
         getattr(lib, name).restype = ctypes.c_int
     lib.hsma_server_get_stats.restype = ctypes.c_int
     lib.hsma_server_destroy.argtypes = [vp]
@@ -488,14 +492,23 @@ class MD:
     """Velocity-Verlet MD with HSMA electrostatics (hsma_md_*): device
     tensors (float64, contiguous) are integrated in place."""
 
-    def __init__(self, plan: "Plan", n: int, dt: float, lj_epsilon: float = 1.0, lj_sigma: float = 1.0,
-                 lj_rcut: float = 0.0, wall_epsilon: float = 0.0, wall_sigma: float = 1.0, wall_rcut: float = 0.0):
+    def __init__(self, plan: Optional["Plan"], n: int, dt: float, lj_epsilon: float = 1.0, lj_sigma: float = 1.0,
+                 lj_rcut: float = 0.0, wall_epsilon: float = 0.0, wall_sigma: float = 1.0, wall_rcut: float = 0.0,
+                 geometry: int = GEOM_3D, box_lo=None, box_len=None):
+        """With a plan: hsma_md_create.  With plan None: a driver for the
+        box (hsma_md_create_for_box) whose Coulomb forces come from
+        elsewhere (drift / finish around a server request)."""
         lib = load_library()
         self._lib = lib
         self._plan = plan  # kept alive: the driver uses it
         self._m = ctypes.c_void_p()
         p = _CMDParams(dt, lj_epsilon, lj_sigma, lj_rcut, wall_epsilon, wall_sigma, wall_rcut)
-        _check(lib.hsma_md_create(plan._p, ctypes.byref(p), int(n), ctypes.byref(self._m)))
+        if plan is not None:
+            _check(lib.hsma_md_create(plan._p, ctypes.byref(p), int(n), ctypes.byref(self._m)))
+        else:
+            lo, L = _vec3(box_lo), _vec3(box_len)
+            _check(lib.hsma_md_create_for_box(ctypes.byref(p), int(geometry), _dp(lo), _dp(L), int(n),
+                                              ctypes.byref(self._m)))
 
     @staticmethod
     def _ptr(t):
@@ -521,6 +534,20 @@ class MD:
         _check(self._lib.hsma_md_forces(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v), self._ptr(f),
                                         self._ptr(q), self._ptr(m), self._ptr(thermo_row)))
 
+    def drift(self, x, v, f, m, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self._lib.hsma_md_drift(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v), self._ptr(f),
+                                       self._ptr(m)))
+
+    def finish(self, x, v, f, m, e_coulomb, thermo_row=None, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self._lib.hsma_md_finish(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v), self._ptr(f),
+                                        self._ptr(m), self._ptr(e_coulomb), self._ptr(thermo_row)))
+
     def close(self):
         if self._m:
             self._lib.hsma_md_destroy(self._m)
@@ -537,3 +564,65 @@ class MD:
             self.close()
         except Exception:
             pass
+
+
+class ReplicaEnsemble:
+    """MD replicas on the serving loop: every replica's state stays on the
+    device; per step each replica drifts (hsma_md_drift), its Coulomb forces
+    come from a device request to the server (in place, with its system id,
+    so its slot replays a captured step), then it finishes the step
+    (hsma_md_finish: LJ, kick, thermo).  Orchestration of C-ABI calls only."""
+
+    def __init__(self, server: "Server", replicas, dt: float, params: Params = None, **lj):
+        """replicas: list of dicts with device tensors x, v, q, m and box_lo,
+        box_len (3D boxes)."""
+        import torch
+        self.server = server
+        self.params = params
+        self.reps = []
+        for i, r in enumerate(replicas):
+            n = r["x"].shape[0]
+            dev = r["x"].device
+            md = MD(None, n, dt, box_lo=r["box_lo"], box_len=r["box_len"], **lj)
+            self.reps.append(dict(r, md=md, f=torch.zeros_like(r["x"]), e=torch.zeros(1, dtype=torch.float64, device=dev),
+                                  ev=torch.cuda.Event(), id=i + 1))
+        self.first = True
+
+    def _coulomb(self):
+        import torch
+        tickets = []
+        for r in self.reps:
+            r["ev"].record()
+            tickets.append(self.server.submit_device(r["x"], r["q"], r["box_lo"], box_len=r["box_len"],
+                                                     params=self.params, force=r["f"], energy=r["e"],
+                                                     system_id=r["id"], ready_event=r["ev"]))
+        return [self.server.wait(t) for t in tickets]
+
+    def step(self, thermo=None):
+        """One step of every replica; thermo: optional list of 4-double
+        device tensors, one per replica.  Returns the server results."""
+        if self.first:
+            res = self._coulomb()  # forces at the starting positions
+            for r in self.reps:
+                r["md"].finish(r["x"], torch_zero_v(r), r["f"], r["m"], r["e"])
+            self.first = False
+        for r in self.reps:
+            r["md"].drift(r["x"], r["v"], r["f"], r["m"])
+        res = self._coulomb()
+        for k, r in enumerate(self.reps):
+            r["md"].finish(r["x"], r["v"], r["f"], r["m"], r["e"], None if thermo is None else thermo[k])
+        return res
+
+    def close(self):
+        for r in self.reps:
+            r["md"].close()
+
+
+def torch_zero_v(r):
+    """Zero velocities of a replica's shape (the first force evaluation adds
+    the LJ forces without a kick: dt/2 F/m on zero velocities is discarded)."""
+    import torch
+    if "_z" not in r:
+        r["_z"] = torch.zeros_like(r["v"])
+    r["_z"].zero_()
+    return r["_z"]

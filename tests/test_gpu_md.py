@@ -231,3 +231,47 @@ def test_coulomb_virial_is_the_energy():
     p_ref = (2 * ke + wl + e1) / (3 * box.prod())
     note(f"   pressure {r[3]:.12g} reference {p_ref:.12g}")
     assert abs(r[0] - e1) <= 1e-10 * abs(e1) and abs(r[3] - p_ref) <= 1e-10 * abs(p_ref)
+
+
+def test_replica_ensemble_on_the_server():
+    """Four MD replicas on the serving loop (device-resident state, Coulomb
+    forces by device requests with system ids, drift and finish on the
+    device): trajectories and thermo rows equal each replica integrated by
+    its own plan to 1e-9 (FP64; the server re-targets a unit-box plan), and
+    the replicas' steps are replayed from captured graphs."""
+    import torch
+    dev = torch.device("cuda:0")
+    prm = hs.Params(precision=0, p=8, K=162, F=512, lam=1.5)
+    reps, refs = [], []
+    nsteps, dt = 10, 0.002
+    for i, L in enumerate((7.0, 7.1, 7.2, 7.3)):
+        box = np.array([L, L, L])
+        pos, q, v0, m = lattice_system((6, 6, 6), box, 50 + i, jitter=0.05)
+        reps.append(dict(x=torch.tensor(pos, device=dev), v=torch.tensor(v0, device=dev),
+                         q=torch.tensor(q, device=dev), m=torch.tensor(m, device=dev), box_lo=(0.0, 0.0, 0.0),
+                         box_len=tuple(box)))
+        # reference: the replica on its own plan
+        x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+        f = torch.zeros_like(x)
+        th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+        with hs.Plan(prm, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt) as md:
+            md.run(x, v, f, torch.tensor(q, device=dev), torch.tensor(m, device=dev), nsteps, thermo=th)
+            torch.cuda.synchronize()
+        refs.append((x.cpu().numpy(), th.cpu().numpy(), box))
+    with hs.Server(prm, (1.0, 1.0, 1.0), max_n=216, max_slots=4) as sv:
+        ens = hs.ReplicaEnsemble(sv, reps, dt)
+        rows = [[torch.zeros(4, dtype=torch.float64, device=dev) for _ in reps] for _ in range(nsteps)]
+        for s in range(nsteps):
+            res = ens.step(rows[s])
+            assert all(r["status"] == 0 for r in res)
+        torch.cuda.synchronize()
+        st = sv.stats()
+        ens.close()
+    note(f"   server stats {st}")
+    for k, (r, (xr, thr, box)) in enumerate(zip(reps, refs)):
+        dx = min_image_diff(r["x"].cpu().numpy(), xr, box) / box[0]
+        tg = np.array([[rows[s][k][c].item() for c in range(4)] for s in range(nsteps)])
+        dth = np.abs(tg - thr).max() / np.abs(thr).max()
+        note(f"   replica {k}: positions {dx:.2e} thermo {dth:.2e}")
+        assert dx <= 1e-9 and dth <= 1e-9
+    assert st["graph_replays"] >= 4 * (nsteps - 2)
