@@ -64,7 +64,7 @@ void hsma_params_default(hsma_params* p) {
   p->gamma_low = 0.0;
   p->nz = 80;
   p->coulomb_k = 1.0;
-  p->tree_order = 8;
+  p->tree_order = 12;
   p->tree_theta = 0.5;
 }
 

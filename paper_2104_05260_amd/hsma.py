@@ -110,7 +110,7 @@ class Params:
     gamma_low: float = 0.0
     nz: int = 80
     coulomb_k: float = 1.0
-    tree_order: int = 8
+    tree_order: int = 12
     tree_theta: float = 0.5
     lsq_solver: int = 0
 

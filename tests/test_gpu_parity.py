@@ -65,8 +65,12 @@ def fp32_energy_bar(E, S):
 # Treecode (near rule 2) against the oracle's exact 27-cell sums: the FP32
 # bars for energy and force, and 5e-5 on the largest potential error (the
 # truncation of the multipole expansions; measured up to 1.7e-5 at order
-# 8, theta 0.5 on the 50,000-ion system).
+# 8, theta 0.5 on the 50,000-ion system).  At the default order 12, theta
+# 0.5 the 3D benchmark systems meet the FP32C energy bar (4.5e-7 and
+# 1.5e-7); the slab stays at 1.6e-6 for every order and theta tried (and
+# with tighter check-target opening), so its treecode energy bar is 2e-6.
 TREE_POT = 5e-5
+TREE_SLAB_E = 2e-6
 
 
 def check(params, pos, q, lo, L, fp32=False, label="", pot_bar=1e-5, cancel_floor=True):
@@ -469,7 +473,7 @@ def test_c5_million_ions_sampled():
          f"force rms rel to fp64 direct {rel_rms(ft, f64):.2e}")
     assert dp < TREE_POT and df < 1e-5
     assert rel_rms(ft, f64) <= 1e-5
-    assert abs(et - e64) <= fp32_energy_bar(e64, S)
+    assert abs(et - e64) <= FP32C_E * abs(e64)
 
 
 @pytest.mark.parametrize("near_rule", [0, 1, 2])
@@ -519,7 +523,7 @@ def test_tree_ragged_3d(n):
     check(params, pos, q, lo, box, fp32=True, label=f"3d treecode n={n}", pot_bar=TREE_POT)
 
 
-@pytest.mark.parametrize("order,theta", [(4, 0.25), (6, 0.4), (10, 0.5), (12, 0.35)])
+@pytest.mark.parametrize("order,theta", [(4, 0.25), (6, 0.4), (8, 0.5), (10, 0.5), (12, 0.35)])
 def test_tree_orders(order, theta):
     """Every compiled expansion order; the error falls with the order and
     the opening parameter (order 12, theta 0.35 is within the FP32 floor)."""
@@ -560,7 +564,7 @@ def test_c3_slab_treecode_sampled():
     S = 0.5 * np.abs(q * pot64).sum()
     note(f"   energy tree {e:.12g} fp64 {e64:.12g} rel {abs(e - e64) / abs(e64):.2e}; dE/S {abs(e - e64) / S:.2e}; "
          f"force rms rel {rel_rms(f, f64):.2e}")
-    assert abs(e - e64) <= fp32_energy_bar(e64, S)
+    assert abs(e - e64) <= TREE_SLAB_E * abs(e64)
     assert rel_rms(f, f64) <= 1e-5
 
 
@@ -608,7 +612,7 @@ def test_c2_treecode_sampled():
     S = 0.5 * np.abs(q * pot64).sum()
     note(f"   energy tree {e:.12g} fp64 {e64:.12g} rel {abs(e - e64) / abs(e64):.2e}; dE/S {abs(e - e64) / S:.2e}; "
          f"force rms rel {rel_rms(f, f64):.2e}")
-    assert abs(e - e64) <= fp32_energy_bar(e64, S)
+    assert abs(e - e64) <= FP32C_E * abs(e64)
     assert rel_rms(f, f64) <= 1e-5
     assert np.abs(pot - pot64).max() <= TREE_POT * np.abs(pot64).max()
 
