@@ -15,8 +15,10 @@ Besides the throughput it reports the dominant kernel's roofline position
 duration), the error against the FP64 GPU path on the same system and that
 path's speed, the same system with the 27 cells summed by the treecode, the
 50,000-ion system (27 cells; its FP64 path, the sphere near set, the
-treecode, the slab's near sets), the serving mix, and the FP64 CPU oracle
-timed as a CPU baseline (a bounded sample scaled to the step).
+treecode, the slab's near sets), and the FP64 CPU oracle timed as a CPU
+baseline (a bounded sample scaled to the step).  With --serving it also
+measures the request server (serving mix, device-resident replicas, an MD
+ensemble); that part is off by default.
 
 For profiling, the same timed loop runs alone on any named configuration,
 optionally with another near set and other p, K, F:
@@ -39,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (published)
+PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector peak (published)
 FLOP_PER_NEAR_PAIR = 20           # algorithmic convention for one Coulomb pair (potential + field)
 
 
@@ -69,6 +72,46 @@ def measured_traffic(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
+def measured_valu(kernel: str, workload: str):
+    """FP32 and FP64 VALU flop per launch of `kernel` from the committed
+    rocprofv3 counter summary (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32/F64
+    x 64 lanes, FMA counted twice), if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "valu_counters.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = t.get(kernel, {}).get(workload)
+    if not ent or ent.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return ent
+
+
+def tree_roofline(workload: str, launch_ms: float):
+    """Position of the treecode's particle kernel (k_tree_far, the dominant
+    kernel of near rule 2): its VALU flop per launch from the committed
+    counters over its live HIP-event duration.  Its work is not a fixed
+    count of pair terms (accepted nodes and opened tiles depend on the
+    configuration), so the flop count is what the kernel issued.  frac is
+    the share of the VALU peak: FP32 flop at 157.3 TFLOP/s plus FP64 flop
+    at 78.6 TFLOP/s."""
+    c = measured_valu("k_tree_far_particles", workload)
+    out = {"kernel": "k_tree_far<P,false> (treecode sums at the particles)", "bound": "alu",
+           "launch_ms": launch_ms, "peak": PEAK_FP32_TFLOPS, "fp64_peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+           "traffic": None}
+    if c is None or not launch_ms:
+        out.update({"achieved": None, "frac": None, "flop_source": "no counters for this kernel source"})
+        return out
+    a32 = c["fp32_flop_per_launch"] / (launch_ms * 1e-3) / 1e12
+    a64 = c["fp64_flop_per_launch"] / (launch_ms * 1e-3) / 1e12
+    out.update({"achieved": a32, "fp64_achieved": a64, "frac": a32 / PEAK_FP32_TFLOPS + a64 / PEAK_FP64_TFLOPS,
+                "fp32_flop_per_launch": c["fp32_flop_per_launch"], "fp64_flop_per_launch": c["fp64_flop_per_launch"],
+                "flop_source": "rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F32/F64 of one launch, x 64 lanes "
+                               "(FMA x 2), profiles/valu_counters.json"})
+    return out
+
+
 def cpu_baseline(w, pos, q, lo, L, sample_n=4096, full_limit_s=30.0):
     """The FP64 oracle timed on the same step.  First its fixed part
     (check-point sums over all particles, least-squares fit, sphere
@@ -81,12 +124,16 @@ def cpu_baseline(w, pos, q, lo, L, sample_n=4096, full_limit_s=30.0):
     import numpy as np
     from oracle import hsma as ohsma
 
+    # the treecode (near rule 2) approximates the cell stencil's sums: the
+    # oracle computes those sums exactly (near rule 0)
+    near = 0 if w.near_rule == 2 else w.near_rule
+
     def run(targets):
         # the oracle on the arrays already generated (generation is not timed)
         if w.geometry == 0:
-            return ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets, w.near_rule)
+            return ohsma.hsma3d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.Fw, w.surface_rule, targets, near)
         return ohsma.hsma2d(pos, q, lo, L, w.p, w.K, w.F, w.lam, w.M, w.gamma_up, w.gamma_low, w.nz,
-                            w.Fw, w.surface_rule, targets, w.near_rule)
+                            w.Fw, w.surface_rule, targets, near)
 
     rng = np.random.default_rng(11)
     run(np.arange(1))  # untimed: loads the oracle's C sums and warms its caches
@@ -122,6 +169,8 @@ def cpu_baseline(w, pos, q, lo, L, sample_n=4096, full_limit_s=30.0):
                     break
     except OSError:
         pass
+    if near != w.near_rule:
+        how += "; the GPU step sums the cell stencil by the treecode, the oracle sums it directly"
     return {
         "value": w.n / step, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
         "cpu_model": model, "nproc": os.cpu_count(), "sample": how,
@@ -153,9 +202,11 @@ def serving_bench(hs, workloads, n_systems=256, slots=8, loads=(0.5, 0.8, 0.95),
         assert all(r["status"] == 0 for r in res)
         return dt, res
 
+    progress("serving: one slot")
     with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=1) as sv1:
         run_all(sv1)  # warm-up
         dt1, _ = run_all(sv1)
+    progress(f"serving: {slots} slots, saturated then Poisson arrivals")
     with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots) as sv:
         nslots, per = sv.slots()
         run_all(sv)  # warm-up
@@ -187,11 +238,139 @@ def serving_bench(hs, workloads, n_systems=256, slots=8, loads=(0.5, 0.8, 0.95),
                                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
     # the same mix with the stencil summed by the treecode (saturated rate)
     prm2 = hs.Params(precision=hs.FP32C, p=8, K=162, F=512, lam=1.5, near_rule=2)
+    progress("serving: treecode")
     with hs.Server(prm2, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots) as sv:
         run_all(sv)  # warm-up
         dt2, _ = run_all(sv)
         out["treecode"] = {"saturated_requests_per_s": n_systems / dt2,
                            "saturated_particle_steps_per_s": total_particles / dt2}
+    # two plan classes in one server: half the systems at p = 8 in cubic
+    # boxes, half at p = 10 in 1 : 1.2 : 0.9 boxes (lambda 1.3), host requests
+    prm_b = hs.Params(precision=hs.FP32C, p=10, K=242, F=800, lam=1.3)
+    progress("serving: two plan classes")
+    with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots, classes=[(prm_b, (1.0, 1.2, 0.9))]) as sv:
+        def run_two():
+            t0 = time.perf_counter()
+            tk = []
+            for k, (pos, q, lo, L) in enumerate(systems):
+                if k % 2 == 0:
+                    tk.append(sv.submit(pos, q, lo, L, potential=False))
+                else:
+                    box = (L, 1.2 * L, 0.9 * L)
+                    tk.append(sv.submit(pos * np.array([1.0, 1.2, 0.9]), q, lo, box_len=box, params=prm_b,
+                                        potential=False))
+            rs = [sv.wait(t) for t in tk]
+            assert all(r["status"] == 0 for r in rs)
+            return time.perf_counter() - t0
+        run_two()
+        dt3 = run_two()
+        out["two_classes"] = {"classes": sv.stats()["classes"], "saturated_requests_per_s": n_systems / dt3,
+                              "saturated_particle_steps_per_s": total_particles / dt3,
+                              "mix": "p 8 cubic and p 10 in 1 : 1.2 : 0.9 boxes, alternating"}
+    out["replicas"] = replica_bench(hs, workloads, slots=slots, loads=loads, seed=seed)
+    return out
+
+
+def replica_bench(hs, workloads, n_rep=64, rounds=6, slots=8, loads=(0.5, 0.8, 0.95), seed=78):
+    """Device-resident replicas (Monte Carlo / MD ensembles): the first
+    n_rep systems of the serving mix stay in HBM; every round submits each
+    replica once as a device request with its system id (after a small move
+    of its positions on the device), so its slot replays a captured step.
+    Saturated rounds, then Poisson arrivals at fractions of that rate with
+    p50/p99 latency; graph replays and slot-affinity hits counted by the
+    server."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    ws = workloads.serving_systems(n_rep)
+    reps = []
+    for w in ws:
+        pos, q, lo, L = workloads.make_system(w)
+        reps.append(dict(x=torch.tensor(pos, device=dev), q=torch.tensor(q, device=dev), lo=lo, L=L[0],
+                         f=torch.zeros((w.n, 3), dtype=torch.float64, device=dev)))
+    nmax = max(w.n for w in ws)
+    total = sum(w.n for w in ws)
+    prm = hs.Params(precision=hs.FP32C, p=8, K=162, F=512, lam=1.5)
+    gen = torch.Generator(device=dev).manual_seed(seed)
+
+    def move():
+        for r in reps:  # every replica moves a little on the device
+            r["x"].add_(torch.randn(r["x"].shape, generator=gen, device=dev, dtype=torch.float64), alpha=1e-3)
+            r["x"].remainder_(r["L"])
+        torch.cuda.synchronize()
+
+    def round_(sv):
+        move()
+        t0 = time.perf_counter()
+        tk = [sv.submit_device(r["x"], r["q"], r["lo"], r["L"], force=r["f"], system_id=i + 1)
+              for i, r in enumerate(reps)]
+        rs = [sv.wait(t) for t in tk]
+        assert all(r["status"] == 0 for r in rs)
+        return time.perf_counter() - t0, rs
+
+    out = {"replicas": n_rep, "particles": total, "n_range": [min(w.n for w in ws), nmax], "rounds": rounds}
+    progress(f"serving: {n_rep} device-resident replicas")
+    with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots) as sv:
+        for _ in range(2):
+            round_(sv)  # capture the replicas' steps
+        st0 = sv.stats()
+        dts = [round_(sv)[0] for _ in range(rounds)]
+        st1 = sv.stats()
+        dt = float(np.median(dts))
+        rate = n_rep / dt
+        out.update({"saturated_requests_per_s": rate, "saturated_particle_steps_per_s": total / dt,
+                    "graph_replays_in_timed_rounds": st1["graph_replays"] - st0["graph_replays"],
+                    "requests_in_timed_rounds": n_rep * rounds,
+                    "affinity_hits_in_timed_rounds": st1["affinity_hits"] - st0["affinity_hits"]})
+        rng = np.random.default_rng(seed)
+        out["poisson"] = []
+        for fr in loads:
+            lam = fr * rate
+            lat = []
+            t_first, t_last = None, 0.0
+            for _ in range(2):
+                move()
+                gaps = rng.exponential(1.0 / lam, n_rep)
+                order = rng.permutation(n_rep)
+                t0 = time.perf_counter()
+                arrivals = t0 + np.cumsum(gaps)
+                tk = []
+                for k, i in enumerate(order):
+                    delay = arrivals[k] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                    r = reps[i]
+                    tk.append(sv.submit_device(r["x"], r["q"], r["lo"], r["L"], force=r["f"], system_id=int(i) + 1))
+                rs = [sv.wait(t) for t in tk]
+                lat += [(r["t_done"] - r["t_submit"]) * 1e3 for r in rs]
+                t_first = min(r["t_submit"] for r in rs) if t_first is None else t_first
+                t_last = max(t_last, max(r["t_done"] for r in rs))
+            out["poisson"].append({"offered_fraction": fr, "offered_requests_per_s": lam,
+                                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                                   "replayed_fraction": float(np.mean([r["replayed"] for r in rs]))})
+    # molecular dynamics of 16 replicas on the serving loop (drift, Coulomb
+    # forces by device requests, finish), steps per second of the ensemble
+    md_reps = []
+    for r, w in list(zip(reps, ws))[:16]:
+        md_reps.append(dict(x=r["x"].clone(), v=torch.zeros_like(r["x"]), q=r["q"],
+                            m=torch.ones(w.n, dtype=torch.float64, device=dev), box_lo=(0.0, 0.0, 0.0),
+                            box_len=(r["L"],) * 3))
+    progress(f"serving: MD ensemble of {len(md_reps)} replicas")
+    with hs.Server(prm, (1.0, 1.0, 1.0), max_n=nmax, max_slots=slots) as sv:
+        ens = hs.ReplicaEnsemble(sv, md_reps, 0.001, lj_epsilon=0.0)
+        for _ in range(3):
+            ens.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 10
+        for _ in range(steps):
+            ens.step()
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - t0) / steps
+        ens.close()
+        n_md = sum(r["x"].shape[0] for r in md_reps)
+        out["md_ensemble"] = {"replicas": len(md_reps), "particles": n_md, "ms_per_ensemble_step": dtm * 1e3,
+                              "particle_steps_per_s": n_md / dtm, "graph_replays": sv.stats()["graph_replays"]}
     return out
 
 
@@ -366,7 +545,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix measurement")
+    ap.add_argument("--serving", action="store_true",
+                    help="also measure the serving mix, device replicas and the MD ensemble through the "
+                         "request server (off by default)")
     ap.add_argument("--no-sphere-rule", action="store_true",
                     help="skip the sphere-near-set measurement (near_rule=1 at matched accuracy)")
     ap.add_argument("--no-tree", action="store_true", help="skip the treecode measurement (near_rule=2)")
@@ -407,7 +588,8 @@ def main():
         w = dataclasses.replace(w, **over)
     if not default_run:
         # a profiling run of another configuration: the timed loop only
-        args.no_fp64 = args.no_serving = args.no_sphere_rule = args.no_tree = args.no_secondary = True
+        args.no_fp64 = args.no_sphere_rule = args.no_tree = args.no_secondary = True
+        args.serving = False
     pos, q, lo, L = workloads.make_system(w)
     dev = torch.device("cuda:0")
     x = torch.tensor(pos, device=dev)
@@ -457,7 +639,7 @@ def main():
         "pairs_per_step": {"near_set": info["near_pairs"], "check_points": info["check_pairs"],
                            "sphere_sources": info["surface_pairs"]},
         "stage_ms": r["stage_ms"],
-        "roofline": roofline(w, r),
+        "roofline": roofline(w, r) if w.near_rule != 2 else tree_roofline(w.name, r["near_ms"]),
     }
     progress(f"timed: {ms:.3f} ms per step")
     if not args.no_fp64:
@@ -474,7 +656,7 @@ def main():
     if not args.no_secondary:
         progress("50,000-ion system (27 cells)")
         out["c2_50000"] = c2_bench(hs, workloads, args)
-    if not args.no_serving:
+    if args.serving:
         progress("serving mix")
         out["serving"] = serving_bench(hs, workloads)
     if not args.no_cpu_baseline:
@@ -499,11 +681,20 @@ def tree_entry(hs, params, w, lo, L, x, qq, en, pot, f, stream, ms_cells, steps,
         plan.compute_device(x, qq, en, pot, f)
     ev1.record(stream)
     torch.cuda.synchronize()
+    # then a few calls with the plan's stage events: k_tree_far's duration
+    plan.set_timing(True)
+    for _ in range(3):
+        plan.compute_device(x, qq, en, pot, f)
+    torch.cuda.synchronize()
+    tm = plan.timing()
     plan.close()
+    tree_ms = tm["near_ms"] / max(1, tm["calls"])
     ms = ev0.elapsed_time(ev1) / steps
     o = {"near_rule": 2, "tree_order": params.tree_order, "tree_theta": params.tree_theta,
          "precision": "fp32-compensated", "ms_per_step": ms, "particle_steps_per_s": w.n / (ms * 1e-3),
-         "speedup_vs_27_cells": ms_cells / ms}
+         "speedup_vs_27_cells": ms_cells / ms,
+         "roofline": tree_roofline(w.name if params.tree_order == 12 else f"{w.name}_order{params.tree_order}",
+                                   tree_ms)}
     if e64 is not None:
         fs = f.cpu().numpy()
         o["rel_energy_err_vs_27_cells_fp64"] = abs(en.item() - e64) / abs(e64)

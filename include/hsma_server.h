@@ -8,7 +8,8 @@
  * own box.
  *
  * Plan classes: requests with the same parameters and the same box shape
- * (box_len / box_len[0]) share one plan class, whose least-squares
+ * (box_len / box_len[0], equal to 1e-14 relative; the request's box is then
+ * the class's shape times box_len[0]) share one plan class, whose least-squares
  * pseudo-inverse (Eq. 6) is built once for the class's unit box and
  * re-targeted to each request's box by one kernel; a box of any size of
  * that shape costs no host least-squares work.  Classes are created when

@@ -165,6 +165,10 @@ struct DevicePlan {
   // Uses [base, base + carve(nmax)) as the arena (owned by the caller, e.g.
   // a server slot shared by several plans that never run at once).
   void attach_arena(void* base, int64_t nmax);
+  // Another plan has written the shared arena since this plan's last call:
+  // the next call uploads its check schedule again (the only arena content
+  // that outlives a call).
+  void arena_reused() { cur_n = -1; }
   // Ordering of the plan's calls: each call waits for the previous call's
   // work (ev_done, recorded at its end on its stream) when it runs on
   // another stream, so calls on different streams never share the arena

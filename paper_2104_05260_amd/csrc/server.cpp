@@ -63,6 +63,7 @@ struct Slot {
   double* d_io = nullptr;  // xyz (3 cap) | q (cap) | pot (cap) | force (3 cap) | energy
   double* h_io = nullptr;  // pinned mirror, then energy and one int status
   int64_t cap = 0;
+  int last_class = -1;  // class of the slot's previous request
   bool replayed = false;
 };
 
@@ -92,7 +93,7 @@ struct hsma_server {
     std::lock_guard<std::mutex> lk(class_mu);
     return classes[(size_t)i].get();
   }
-  hsma_status find_or_create_class(const hsma_params& prm, const double box_len[3], int* idx, double* scale,
+  hsma_status find_or_create_class(const hsma_params& prm, double box_len[3], int* idx, double* scale,
                                    std::string& err);
 };
 
@@ -150,6 +151,10 @@ struct GpuBackend {
     hsma::DevicePlan* plan = nullptr;
     hsma_status st = slot_plan(sv, s, r.cls, &plan, err);
     if (st != HSMA_OK) return st;
+    // the slot's plans share its arena: after another class's step this
+    // plan's check schedule there is gone
+    if (s.last_class != r.cls) plan->arena_reused();
+    s.last_class = r.cls;
     const int64_t n = r.n, cap = s.cap;
     Payload& p = r.payload;
     double* h = s.h_io;
@@ -219,7 +224,10 @@ struct GpuBackend {
 
 }  // namespace
 
-hsma_status hsma_server::find_or_create_class(const hsma_params& prm, const double box_len[3], int* idx,
+// The class of (prm, box shape); box_len returns the box the device uses,
+// the class's unit box times box_len[0].  Unit boxes that agree to 1e-14
+// relative are one shape (L * 1.2 / L need not round to 1.2).
+hsma_status hsma_server::find_or_create_class(const hsma_params& prm, double box_len[3], int* idx,
                                               double* scale, std::string& err) {
   for (int k = 0; k < 3; ++k)
     if (!(box_len[k] > 0) || !std::isfinite(box_len[k])) {
@@ -229,11 +237,17 @@ hsma_status hsma_server::find_or_create_class(const hsma_params& prm, const doub
   double u[3];
   unit_box(box_len, u);
   *scale = box_len[0];
+  auto same_shape = [&](const double* cu) {
+    for (int k = 0; k < 3; ++k)
+      if (!(std::fabs(cu[k] - u[k]) <= 1e-14 * cu[k])) return false;
+    return true;
+  };
   std::lock_guard<std::mutex> lk(class_mu);
   for (size_t i = 0; i < classes.size(); ++i) {
     const PlanClass& c = *classes[i];
-    if (same_params(c.prm, prm) && c.unit[0] == u[0] && c.unit[1] == u[1] && c.unit[2] == u[2]) {
+    if (same_params(c.prm, prm) && same_shape(c.unit)) {
       *idx = (int)i;
+      for (int k = 0; k < 3; ++k) box_len[k] = c.unit[k] * *scale;
       return HSMA_OK;
     }
   }
@@ -247,6 +261,7 @@ hsma_status hsma_server::find_or_create_class(const hsma_params& prm, const doub
   const double lo0[3] = {0, 0, 0};
   const hsma_status st = hsma::build_host_plan(prm, lo0, c->unit, c->host, err);
   if (st != HSMA_OK) return st;
+  for (int k = 0; k < 3; ++k) box_len[k] = c->unit[k] * *scale;
   classes.push_back(std::move(c));
   *idx = (int)classes.size() - 1;
   return HSMA_OK;

@@ -218,6 +218,36 @@ def test_two_class_mix_bitwise_and_oracle():
         assert abs(r["energy"] - ref.energy) <= 1e-10 * S and df <= 1e-10
 
 
+def test_one_slot_alternating_classes():
+    """One slot whose two plan classes share its arena: the same request
+    before and after a request of the other class gives bitwise the same
+    result (each plan uploads its check schedule again after the other
+    class has used the arena), and the repeated request's result equals
+    that of a server that runs it alone."""
+    _, cubic = mix(count=1, seed0=2600, n_lo=900, n_hi=900)
+    other = _noncubic_system(1100, (1100 / 0.05) ** (1 / 3), 2601)
+    _, pos_a, q_a, lo_a, L_a = cubic[0]
+    pos_b, q_b, lo_b, box_b = other
+    prm_b = _noncubic_params(prec=1)
+    nmax = max(len(q_a), len(q_b))
+    with hs.Server(params(1), UNIT, max_n=nmax, max_slots=1, classes=[(prm_b, tuple(np.array(box_b) / box_b[0]))]) as sv:
+        seq = []
+        for k in range(3):
+            ra = sv.wait(sv.submit(pos_a, q_a, lo_a, L_a))
+            rb = sv.wait(sv.submit(pos_b, q_b, lo_b, box_len=box_b, params=prm_b))
+            seq.append((ra, rb))
+        st = sv.stats()
+    with hs.Server(params(1), UNIT, max_n=nmax, max_slots=1) as sv:
+        alone = sv.wait(sv.submit(pos_a, q_a, lo_a, L_a))
+    note(f"   server stats {st}; classes {[(a['plan_class'], b['plan_class']) for a, b in seq]}")
+    assert all(a["status"] == 0 and b["status"] == 0 for a, b in seq)
+    assert all(a["plan_class"] == 0 and b["plan_class"] == 1 for a, b in seq)
+    for a, b in seq[1:]:
+        assert a["energy"] == seq[0][0]["energy"] and np.array_equal(a["force"], seq[0][0]["force"])
+        assert b["energy"] == seq[0][1]["energy"] and np.array_equal(b["force"], seq[0][1]["force"])
+    assert alone["energy"] == seq[0][0]["energy"] and np.array_equal(alone["force"], seq[0][0]["force"])
+
+
 def test_device_resident_replicas_replay_graphs():
     """Device-resident requests: positions and charges stay in HBM and the
     outputs are written in place; the results equal the host requests'
