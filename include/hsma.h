@@ -115,9 +115,12 @@ typedef struct hsma_plan hsma_plan;
  * tree order 12, tree theta 0.5, lsq solver 0.                            */
 void hsma_params_default(hsma_params* p);
 
-/* Builds the per-geometry plan: check points, sphere quadrature, harmonic
- * basis, the least-squares pseudo-inverse (host FP64 Householder QR) and
- * the image tables; uploads them to the current HIP device.
+/* Builds the per-geometry plan (the set-up parts of Sec. 2.2 and the
+ * parameters of Sec. 3.2): check points on the box faces (and, in 2D, the
+ * interface grids), the sphere quadrature, the harmonic basis, the
+ * least-squares pseudo-inverse of Eq. 6 (host FP64 Householder QR, or the
+ * device's FP64 matrix cores with lsq_solver 1) and the image tables of
+ * Eqs. 3-4; uploads them to the current HIP device.
  * box_lo: lower box corner; box_len: edge lengths (all > 0).  In 2D the
  * dielectric interfaces are the planes z = box_lo[2] and z = box_lo[2] +
  * box_len[2].  Errors: INVALID_ARG, GEOMETRY, RANK, NO_DEVICE, OOM, DEVICE. */
@@ -130,14 +133,22 @@ void hsma_plan_destroy(hsma_plan* plan);
  * n <= 2^26 (2^20 tiles of 64) with near rules 1 and 2.  Larger counts fail
  * with INVALID_ARG before any buffer is read or any work is enqueued.      */
 
-/* Host-memory call (synchronous).  Validates the input on the host first:
+/* One step of the method (Sec. 2.2, Eqs. 3-6): near-set sums at the check
+ * points, the least-squares fit, the sphere charges and dipoles, the sums
+ * at the particles, then E = 1/2 sum q_i Phi_i and F_i = q_i E_i.
+ * Host-memory call (synchronous): xyz (n x 3) and q (n) are read, energy
+ * (1), potential (n) and force (n x 3) written, each output optional
+ * (NULL).  Validates the input on the host first:
  * n within the limits above, finite values, neutrality (NOT_NEUTRAL), slab
  * domain (OUT_OF_DOMAIN).  Positions outside the box are wrapped along
  * periodic axes.                                                          */
 hsma_status hsma_compute(hsma_plan* plan, int64_t n, const double* xyz, const double* q,
                          double* energy, double* potential, double* force);
 
-/* Device-memory call: enqueues the whole step on `stream` (a hipStream_t;
+/* The same step (Sec. 2.2, Eqs. 3-6) on device memory: d_xyz, d_q, d_energy,
+ * d_potential, d_force are device pointers in the layouts above (outputs
+ * optional), owned by the caller and in use until the stream reaches the
+ * end of the step.  Enqueues the whole step on `stream` (a hipStream_t;
  * NULL = default stream) and returns without waiting.  Validation runs on
  * the device; an invalid input makes every requested output NaN and is
  * reported by the next hsma_plan_device_status() on this plan.             */
