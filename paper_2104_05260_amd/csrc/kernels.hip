@@ -1311,14 +1311,20 @@ __global__ __launch_bounds__(512) void k_tree_m2m(int level, int order, TreeLeve
 
 // Potential and field (-grad) at X (relative to the node centre) of the
 // moments M (re, im of (n, m), m <= n <= P; P may be below the order the
-// moments were built to), FP32.  The irregular
-// harmonics T_n^m, n <= P + 1, are generated column by column and used at
-// once: T_n^m feeds the potential through M_n^m, d/dz through M_{n-1}^m,
-// and (d/dx + i d/dy) through M_{n-1}^{m-1} and M_{n-1}^{m+1}; the terms
-// of m >= 1 count twice in the potential and in d/dz (the conjugate
-// columns -m), so column 0 runs on its own.  The loops stay rolled: the
-// moments then come in a few at a time through scalar loads (fully
-// unrolled, the compiler would hold all of them at once).
+// moments were built to), FP32.  The irregular harmonics T_n^m, n <= P + 1,
+// are generated column by column and used at once: T_n^m feeds the
+// potential through M_n^m, d/dz through M_{n-1}^m, and (d/dx + i d/dy)
+// through M_{n-1}^{m-1} and M_{n-1}^{m+1}; the terms of m >= 1 count twice
+// in the potential and in d/dz (the conjugate columns -m), so column 0 runs
+// on its own.  Which terms a step (n, m) has depends only on where n sits
+// in its column, so the first steps and the last (n = P + 1: no potential
+// term) are peeled off and the steps in between run without branches: a
+// rolled loop with a branch per term spent more scalar instructions (loop
+// control, address arithmetic) than vector ones and waited on each
+// moment's load.  The loops stay rolled otherwise, so the moments come in
+// a few at a time through scalar loads (fully unrolled, the compiler would
+// hold all of them at once).  Every accumulator sees the same operations in
+// the same order as the plain definition.
 __device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, float X, float Y, float Z, double& phi,
                                           float& fx, float& fy, float& fz) {
   const float r2 = X * X + Y * Y + Z * Z;
@@ -1330,75 +1336,115 @@ __device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, fl
   // energy error at order 12 went from 1.2e-6 to 4.5e-7 for 1 % of the time)
   double phi0 = 0.0, phi1 = 0.0;
   float dz0 = 0.f, dz1 = 0.f, Wr = 0.f, Wi = 0.f;
-  // column m = 0: T_n^0 is real
+  // column m = 0: T_n^0 is real.  Step n: recursion (n >= 1), potential
+  // (n <= P), d/dz (n >= 1), and + M_{n-1}^1 conj(T_n^0) (n >= 2).  The
+  // factors 2n - 1 and (n - 1)^2 and the place in M are carried from step
+  // to step: pv points at M_{n-1}^0, and M_n^0 is 2n reals further.
   {
     float p = 0.f, t = ri;
+    auto step0 = [&](const float af, const float bf, const float* __restrict__ row, const float* __restrict__ pv,
+                     auto pot, auto wplus) {
+      const float a = af * zr;
+      const float b = bf * ri2;
+      const float nt = a * t - b * p;
+      p = t;
+      t = nt;
+      if constexpr (decltype(pot)::value) phi0 = fma((double)row[0], (double)t, phi0);  // M_n^0
+      dz0 = fmaf(pv[0], t, dz0);
+      if constexpr (decltype(wplus)::value) {
+        Wr = fmaf(pv[2], t, Wr);
+        Wi = fmaf(pv[3], t, Wi);
+      }
+    };
+    phi0 = fma((double)M[0], (double)t, phi0);  // n = 0
+    step0(1.f, 0.f, M + 2, M, std::true_type{}, std::false_type{});
+    float af = 3.f, bf = 1.f;
+    const float* __restrict__ pv = M + 2;  // M_1^0
 #pragma unroll 1
-    for (int n = 0; n <= P + 1; ++n) {
-      if (n > 0) {
-        const float a = (float)(2 * n - 1) * zr;
-        const float b = (float)((n - 1) * (n - 1)) * ri2;
-        const float nt = a * t - b * p;
-        p = t;
-        t = nt;
-      }
-      if (n <= P) phi0 = fma((double)M[n * (n + 1)], (double)t, phi0);
-      if (n >= 1) {
-        const float* __restrict__ prev = M + (n - 1) * n;  // (n - 1, 0)
-        dz0 = fmaf(prev[0], t, dz0);
-        if (n >= 2) {
-          // + M_{n-1}^1 conj(T_n^0)
-          Wr = fmaf(prev[2], t, Wr);
-          Wi = fmaf(prev[3], t, Wi);
-        }
-      }
+    for (int n = 2; n <= P; ++n) {
+      const float* __restrict__ nx = pv + 2 * n;  // M_n^0
+      step0(af, bf, nx, pv, std::true_type{}, std::true_type{});
+      pv = nx;
+      bf += af;
+      af += 2.f;
     }
+    step0(af, bf, pv, pv, std::false_type{}, std::true_type{});  // n = P + 1
   }
+  // columns m >= 1.  Step n of column m: recursion (n > m), potential
+  // (n <= P), d/dz (n - 1 >= m), - conj(M_{n-1}^{m-1}) T_n^m (always) and
+  // + M_{n-1}^{m+1} conj(T_n^m) (n - 1 >= m + 1).  The step's factors
+  // 2n - 1 and (n - 1)^2 - m^2 (small integers, exact in FP32) and its
+  // place in M are carried from step to step: pv points at M_{n-1}^{m-1}
+  // (then M_{n-1}^m, M_{n-1}^{m+1}), and M_n^{m-1} is 2n reals further.
   float sr = ri, si = 0.f;
-#pragma unroll 1
-  for (int m = 1; m <= P + 1; ++m) {
-    {
-      const float c = (float)(2 * m - 1);
-      const float nr = c * (wr * sr - wi * si), ni = c * (wr * si + wi * sr);
-      sr = nr;
-      si = ni;
+  float pr = 0.f, pi = 0.f, tr = 0.f, ti = 0.f;
+  auto stepm = [&](const float af, const float bf, const float* __restrict__ row, const float* __restrict__ pv,
+                   auto rec, auto pot, auto dz, auto wplus) {
+    if constexpr (decltype(rec)::value) {
+      const float a = af * zr;
+      const float b = bf * ri2;
+      const float nr = a * tr - b * pr, ni = a * ti - b * pi;
+      pr = tr;
+      pi = ti;
+      tr = nr;
+      ti = ni;
     }
-    float pr = 0.f, pi = 0.f, tr = sr, ti = si;
-#pragma unroll 1
-    for (int n = m; n <= P + 1; ++n) {
-      if (n > m) {
-        const float a = (float)(2 * n - 1) * zr;
-        const float b = (float)((n - 1) * (n - 1) - m * m) * ri2;
-        const float nr = a * tr - b * pr, ni = a * ti - b * pi;
-        pr = tr;
-        pi = ti;
-        tr = nr;
-        ti = ni;
-      }
-      if (n <= P) {
-        const float* __restrict__ row = M + n * (n + 1) + 2 * m;  // (n, m)
-        phi1 = fma((double)row[0], (double)tr, phi1);
-        phi1 = fma((double)row[1], (double)ti, phi1);
-      }
-      const float* __restrict__ prev = M + (n - 1) * n + 2 * m;  // (n - 1, m)
-      if (n - 1 >= m) {
-        dz1 = fmaf(prev[0], tr, dz1);
-        dz1 = fmaf(prev[1], ti, dz1);
-      }
-      // - conj(M_{n-1}^{m-1}) T_n^m
-      Wr = fmaf(-prev[-2], tr, Wr);
-      Wr = fmaf(-prev[-1], ti, Wr);
-      Wi = fmaf(-prev[-2], ti, Wi);
-      Wi = fmaf(prev[-1], tr, Wi);
-      if (m + 1 <= n - 1) {
-        // + M_{n-1}^{m+1} conj(T_n^m)
-        Wr = fmaf(prev[2], tr, Wr);
-        Wr = fmaf(prev[3], ti, Wr);
-        Wi = fmaf(prev[3], tr, Wi);
-        Wi = fmaf(-prev[2], ti, Wi);
-      }
+    if constexpr (decltype(pot)::value) {  // row: M_n^m
+      phi1 = fma((double)row[0], (double)tr, phi1);
+      phi1 = fma((double)row[1], (double)ti, phi1);
     }
+    if constexpr (decltype(dz)::value) {
+      dz1 = fmaf(pv[2], tr, dz1);
+      dz1 = fmaf(pv[3], ti, dz1);
+    }
+    Wr = fmaf(-pv[0], tr, Wr);
+    Wr = fmaf(-pv[1], ti, Wr);
+    Wi = fmaf(-pv[0], ti, Wi);
+    Wi = fmaf(pv[1], tr, Wi);
+    if constexpr (decltype(wplus)::value) {
+      Wr = fmaf(pv[4], tr, Wr);
+      Wr = fmaf(pv[5], ti, Wr);
+      Wi = fmaf(pv[5], tr, Wi);
+      Wi = fmaf(-pv[4], ti, Wi);
+    }
+  };
+  auto seed = [&](const int m) {
+    const float c = (float)(2 * m - 1);
+    const float nr = c * (wr * sr - wi * si), ni = c * (wr * si + wi * sr);
+    sr = nr;
+    si = ni;
+    pr = 0.f;
+    pi = 0.f;
+    tr = sr;
+    ti = si;
+  };
+  // M_n^m
+  auto at = [&](const int n, const int m) { return M + (n * (n + 1) + 2 * m); };
+  const std::false_type no{};
+  const std::true_type yes{};
+#pragma unroll 1
+  for (int m = 1; m < P; ++m) {
+    seed(m);
+    stepm(0.f, 0.f, at(m, m), at(m - 1, m - 1), no, yes, no, no);
+    stepm((float)(2 * m + 1), 0.f, at(m + 1, m), at(m, m - 1), yes, yes, yes, no);
+    float af = (float)(2 * m + 3), bf = (float)((m + 1) * (m + 1) - m * m);
+    const float* __restrict__ pv = at(m + 1, m - 1);
+#pragma unroll 1
+    for (int n = m + 2; n <= P; ++n) {
+      const float* __restrict__ nx = pv + 2 * n;  // M_n^{m-1}
+      stepm(af, bf, nx + 2, pv, yes, yes, yes, yes);
+      pv = nx;
+      bf += af;
+      af += 2.f;
+    }
+    stepm(af, bf, pv, pv, yes, no, yes, yes);  // n = P + 1
   }
+  // m = P: steps P and P + 1; m = P + 1: step P + 1 only
+  seed(P);
+  stepm(0.f, 0.f, at(P, P), at(P - 1, P - 1), no, yes, no, no);
+  stepm((float)(2 * P + 1), 0.f, at(P + 1, P), at(P, P - 1), yes, no, yes, no);
+  seed(P + 1);
+  stepm(0.f, 0.f, at(P, P), at(P, P), no, no, no, no);
   phi = phi0 + 2.0 * phi1;
   fx = -Wr;
   fy = -Wi;
