@@ -1737,13 +1737,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
       bey_bits = (bey_bits & ~(0xffull << sh)) | ((m_bey & 0xffull) << sh);
       far_bits = farp ? (far_bits | (1u << lc)) : (far_bits & ~(1u << lc));
     }
-    // next opened child: the deepest level with one left
-    int L = lc >= 1 ? lc : 1;
-    while (L <= top && ((open_bits >> (8 * L)) & 0xffull) == 0ull) ++L;
-    if (L > top) break;
-    const unsigned mk = (unsigned)((open_bits >> (8 * L)) & 0xffull);
-    const int k = __builtin_ctz(mk);
-    open_bits &= ~(1ull << (8 * L + k));
+    // next opened child: the deepest level with one left, i.e. the lowest
+    // set bit of open_bits from the byte of level max(lc, 1) on (no bit
+    // above level top is ever set)
+    const unsigned long long rest = open_bits & (~0ull << (8 * (lc >= 1 ? lc : 1)));
+    if (rest == 0ull) break;
+    const int bit = __builtin_ctzll(rest);
+    const int L = bit >> 3, k = bit & 7;
+    open_bits &= ~(1ull << bit);
     const int q = par >> (3 * (L - lc));  // the parent (level L + 1) of the level-L children
     farp = ((far_bits >> L) & 1u) || ((bey_bits >> (8 * L + k)) & 1ull);
     par = 8 * q + k;
