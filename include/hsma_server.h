@@ -22,7 +22,8 @@
  * once on that slot's stream, so requests that arrive while others run join
  * the device work without waiting for a batch boundary and the steps of
  * different systems overlap on the GPU.  A request carrying a system id is
- * preferably given the slot that last ran the same system and class; a slot
+ * preferably given a free slot among whose last 8 requests the same system
+ * and class ran (as many as a slot keeps captured steps for); a slot
  * that sees the same system again (same size, same buffers) replays the
  * step it captured in a HIP graph instead of launching it kernel by kernel.
  * Completion is signalled by a host callback enqueued after the step (no
@@ -109,7 +110,7 @@ typedef struct hsma_result {
 typedef struct hsma_server_stats {
   int64_t completed;      /* requests finished (any status)                       */
   int64_t graph_replays;  /* steps run as graph replays                           */
-  int64_t affinity_hits;  /* requests given the slot that last ran their system   */
+  int64_t affinity_hits;  /* requests given a slot that recently ran their system */
   int classes;            /* plan classes created                                 */
   int slots;
 } hsma_server_stats;

@@ -411,7 +411,9 @@ hsma_status hsma_server_create(const hsma_server_cfg* cfg, hsma_server** out) {
     }
   }
   sv->backend.reset(new GpuBackend(sv.get()));
-  sv->core.reset(new CoreT(*sv->backend, cfg->queue_capacity));
+  // affinity over as many recent systems per slot as a slot plan keeps
+  // captured steps
+  sv->core.reset(new CoreT(*sv->backend, cfg->queue_capacity, hsma::DevicePlan::kGraphCache));
   for (int i = 0; i < nslots; ++i) sv->cb[i] = CallbackCtx{sv->core.get(), i};
   sv->core->start();
   *out = sv.release();

@@ -52,12 +52,14 @@ class Core {
  public:
   typedef Request<Payload> Req;
 
-  Core(Backend& be, int queue_capacity) : be_(be), queue_capacity_(queue_capacity) {
+  // affinity_depth: how many of a slot's most recent (system, class) pairs
+  // count as still held by it (the backend's per-slot step cache)
+  Core(Backend& be, int queue_capacity, int affinity_depth = 8)
+      : be_(be), queue_capacity_(queue_capacity), affinity_depth_(affinity_depth < 1 ? 1 : affinity_depth) {
     const int ns = be_.slots();
     slot_req_.resize(ns);
     slot_done_.assign(ns, 0);
-    slot_system_.assign(ns, 0);
-    slot_class_.assign(ns, -1);
+    slot_hist_.resize(ns);
     slot_used_.assign(ns, 0);
   }
   Core(const Core&) = delete;
@@ -152,20 +154,36 @@ class Core {
   }
 
  private:
-  // Free slot for r: the one that last ran the same system and class if it
-  // is free (its captured step can be replayed), else the least recently
-  // used free slot; -1 when none is free.  Under mu_.
+  // Free slot for r: a free slot among whose affinity_depth most recent
+  // requests the same system and class ran (its captured step can be
+  // replayed), else the least recently used free slot; -1 when none is
+  // free.  Under mu_.
   int pick_slot(const Req& r) {
     int best = -1;
     for (int i = 0; i < (int)slot_req_.size(); ++i) {
       if (slot_req_[i]) continue;
-      if (r.system != 0 && slot_system_[i] == r.system && slot_class_[i] == r.cls) {
-        ++affinity_hits_;
-        return i;
-      }
+      if (r.system != 0)
+        for (const auto& h : slot_hist_[i])
+          if (h.first == r.system && h.second == r.cls) {
+            ++affinity_hits_;
+            return i;
+          }
       if (best < 0 || slot_used_[i] < slot_used_[best]) best = i;
     }
     return best;
+  }
+
+  // Records that slot s runs (system, class), most recent first.  Under mu_.
+  void remember(int s, uint64_t system, int cls) {
+    if (system == 0) return;
+    auto& h = slot_hist_[s];
+    for (size_t k = 0; k < h.size(); ++k)
+      if (h[k].first == system && h[k].second == cls) {
+        h.erase(h.begin() + (long)k);
+        break;
+      }
+    h.emplace_front(system, cls);
+    if ((int)h.size() > affinity_depth_) h.pop_back();
   }
 
   void loop() {
@@ -186,8 +204,7 @@ class Core {
             const int s = pick_slot(*pending_.front());
             if (s < 0) break;
             slot_req_[s] = pending_.front();
-            slot_system_[s] = pending_.front()->system;
-            slot_class_[s] = pending_.front()->cls;
+            remember(s, pending_.front()->system, pending_.front()->cls);
             slot_used_[s] = ++use_clock_;
             admit.emplace_back(s, pending_.front());
             pending_.pop_front();
@@ -231,13 +248,15 @@ class Core {
 
   Backend& be_;
   const int queue_capacity_;
+  const int affinity_depth_;
   mutable std::mutex mu_;
   std::condition_variable cv_, cv_done_, cv_idle_;
   std::deque<std::shared_ptr<Req>> pending_;
   std::unordered_map<uint64_t, std::shared_ptr<Req>> tickets_;
   std::vector<std::shared_ptr<Req>> slot_req_;
-  std::vector<int> slot_done_, slot_class_;
-  std::vector<uint64_t> slot_system_, slot_used_;
+  std::vector<int> slot_done_;
+  std::vector<std::deque<std::pair<uint64_t, int>>> slot_hist_;  // (system, class), most recent first
+  std::vector<uint64_t> slot_used_;
   uint64_t next_id_ = 1, use_clock_ = 0;
   int64_t completed_ = 0, affinity_hits_ = 0;
   int waiters_ = 0;

@@ -171,7 +171,7 @@ void many_threads() {
 }
 
 void full_queue_and_shutdown() {
-  FakeBackend be(2, 20000);  // slow: 20-60 ms per request
+  FakeBackend be(2, 300000);  // slow: 0.3-0.9 s per request (queued ones stay queued under load)
   CoreT core(be, 4);
   be.core = &core;
   core.start();
@@ -202,7 +202,9 @@ void full_queue_and_shutdown() {
         done.fetch_add(1);
       }
     });
-  std::this_thread::sleep_for(std::chrono::milliseconds(5));
+  // shut down once a request runs (the others, 0.3 s or more behind it,
+  // are still queued)
+  for (int k = 0; k < 5000 && be.launched.load() == 0; ++k) std::this_thread::sleep_for(std::chrono::milliseconds(1));
   core.shutdown();
   for (auto& th : ths) th.join();
   CHECK(cancelled.load() + done.load() == (int)tickets.size());

@@ -294,6 +294,43 @@ def test_device_resident_replicas_replay_graphs():
     assert st["graph_replays"] >= 8 and st["affinity_hits"] >= 8
 
 
+def test_more_replicas_than_slots_replay():
+    """Twelve device-resident replicas on four slots, all submitted at once
+    each round: a slot keeps the steps of its last eight systems, and a
+    replica goes preferably to a free slot that recently ran it, so from
+    the third round on most steps are replays; every result stays equal to
+    the same replica served by a server of its own (bitwise)."""
+    import torch
+    dev = torch.device("cuda:0")
+    _, systems = mix(count=12, seed0=2700, n_lo=300, n_hi=1500)
+    nmax = max(len(q) for _, _, q, _, _ in systems)
+    reps = [dict(x=torch.tensor(pos, device=dev), q=torch.tensor(q, device=dev), lo=lo, L=L,
+                 f=torch.zeros((len(q), 3), dtype=torch.float64, device=dev),
+                 e=torch.zeros(1, dtype=torch.float64, device=dev)) for _, pos, q, lo, L in systems]
+    with hs.Server(params(1), UNIT, max_n=nmax, max_slots=4) as sv:
+        replayed = []
+        for rnd in range(5):
+            torch.cuda.synchronize()
+            tickets = [sv.submit_device(r["x"], r["q"], r["lo"], r["L"], force=r["f"], energy=r["e"],
+                                        system_id=i + 1) for i, r in enumerate(reps)]
+            res = [sv.wait(t) for t in tickets]
+            assert all(o["status"] == 0 for o in res)
+            replayed.append(sum(o["replayed"] for o in res))
+            note(f"   round {rnd}: slots {[o['slot'] for o in res]} replayed {[o['replayed'] for o in res]}")
+        st = sv.stats()
+        energies = [r["e"].item() for r in reps]
+        forces = [r["f"].cpu().numpy() for r in reps]
+    note(f"   stats {st}")
+    with hs.Server(params(1), UNIT, max_n=nmax, max_slots=1) as ref:
+        for r, e, f in zip(reps, energies, forces):
+            out = ref.wait(ref.submit(r["x"].cpu().numpy(), r["q"].cpu().numpy(), r["lo"], r["L"], potential=False))
+            assert out["energy"] == e and np.array_equal(out["force"], f)
+    # (arrival order and sizes repeat each round, so the slots' histories
+    # mostly hold their replicas; at least a quarter of the steps must hit)
+    assert st["affinity_hits"] >= 12
+    assert sum(replayed[2:]) >= 9
+
+
 @pytest.mark.parametrize("case", ["3d_p6", "3d_p10", "3d_p12_K800", "noncubic_p8", "slab_p10"])
 def test_device_lsq_matches_host_qr(case):
     """The fit's pseudo-inverse from the device CholeskyQR2 (FP64 Gram
