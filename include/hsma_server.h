@@ -26,8 +26,8 @@
  * and class ran (as many as a slot keeps captured steps for); a slot
  * that sees the same system again (same size, same buffers) replays the
  * step it captured in a HIP graph instead of launching it kernel by kernel.
- * Completion is signalled by a host callback enqueued after the step (no
- * polling).  A request's kernels and their order do not depend on what else
+ * Completion: each slot has a thread blocked on the slot's end-of-step
+ * event, which reports the slot done (no polling, no host callbacks).  A request's kernels and their order do not depend on what else
  * runs, so its result is bitwise the same alone and in a mix.
  *
  * Device-resident systems: with HSMA_REQ_DEVICE the request's pointers are

@@ -6,10 +6,12 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hsma_server.h"
@@ -65,14 +67,29 @@ struct Slot {
   int64_t cap = 0;
   int last_class = -1;  // class of the slot's previous request
   bool replayed = false;
+  hipEvent_t done_ev = nullptr;  // recorded after each step's outputs
+  bool device_error = false;     // the wait for done_ev failed (set by the slot's waiter)
 };
 
 struct GpuBackend;
 typedef hsma::serve::Core<GpuBackend, Payload> CoreT;
 
-struct CallbackCtx {
-  CoreT* core = nullptr;
-  int slot = 0;
+// Completion: one thread per slot blocks on the slot's end-of-step event
+// and tells the core; `launched` counts steps enqueued, `handled` those
+// reported.
+struct SlotWaiter {
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  uint64_t launched = 0, handled = 0;
+  bool stop = false;
+  void post() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      ++launched;
+    }
+    cv.notify_one();
+  }
 };
 
 }  // namespace
@@ -82,7 +99,7 @@ struct hsma_server {
   int device = 0;
   int64_t bytes_per_slot = 0;
   std::vector<Slot> slots;
-  std::vector<CallbackCtx> cb;
+  std::vector<std::unique_ptr<SlotWaiter>> waiters;  // by slot, started after the core
   std::mutex class_mu;  // guards classes (submit threads add, the scheduler reads)
   std::vector<std::unique_ptr<PlanClass>> classes;
   std::unique_ptr<GpuBackend> backend;
@@ -136,9 +153,25 @@ hsma_status slot_plan(hsma_server* sv, Slot& s, int c, hsma::DevicePlan** out, s
   return HSMA_OK;
 }
 
-void on_done(void* data) {
-  CallbackCtx* c = static_cast<CallbackCtx*>(data);
-  c->core->notify_complete(c->slot);
+// The slot waiter's loop: for each step enqueued on the slot, wait for its
+// end-of-step event (a blocking wait, no polling), then report the slot
+// done.  Exits once stopped with nothing pending.
+void slot_waiter(hsma_server* sv, int si) {
+  SlotWaiter& w = *sv->waiters[(size_t)si];
+  Slot& s = sv->slots[(size_t)si];
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(w.mu);
+      w.cv.wait(lk, [&] { return w.stop || w.launched > w.handled; });
+      if (w.launched == w.handled) return;
+    }
+    if (hipEventSynchronize(s.done_ev) != hipSuccess) s.device_error = true;
+    {
+      std::lock_guard<std::mutex> lk(w.mu);
+      ++w.handled;
+    }
+    sv->core->notify_complete(si);
+  }
 }
 
 struct GpuBackend {
@@ -198,7 +231,8 @@ struct GpuBackend {
     } else if (p.energy) {
       SVCHK(hipMemcpyAsync(p.energy, d_e, sizeof(double), hipMemcpyDeviceToDevice, s.stream), "copy out");
     }
-    SVCHK(hipLaunchHostFunc(s.stream, on_done, &sv->cb[si]), "completion callback");
+    SVCHK(hipEventRecord(s.done_ev, s.stream), "completion event");
+    sv->waiters[(size_t)si]->post();
 #undef SVCHK
     return HSMA_OK;
   }
@@ -215,7 +249,8 @@ struct GpuBackend {
     int status = 0;
     std::memcpy(&status, h + 8 * cap + 1, sizeof(int));
     r.res.energy = h[8 * cap];
-    r.res.status = (hsma_status)status;
+    r.res.status = s.device_error ? HSMA_ERR_DEVICE : (hsma_status)status;
+    s.device_error = false;
     r.res.replayed = s.replayed ? 1 : 0;
     r.res.plan_class = r.cls;
     if (s.replayed) ++sv->graph_replays;
@@ -388,11 +423,11 @@ hsma_status hsma_server_create(const hsma_server_cfg* cfg, hsma_server** out) {
   const int nslots = (int)std::min<int64_t>(cfg->max_slots, budget / std::max<int64_t>(1, sv->bytes_per_slot));
   if (nslots < 1) return hsma::set_last_error(HSMA_ERR_OOM, "HBM budget smaller than one slot");
   sv->slots.resize(nslots);
-  sv->cb.resize(nslots);
   for (int i = 0; i < nslots; ++i) {
     Slot& s = sv->slots[i];
     s.cap = cfg->max_n;
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming | hipEventBlockingSync) != hipSuccess ||
         hipMalloc((void**)&s.d_io, sizeof(double) * (8 * s.cap + 2)) != hipSuccess ||
         hipHostMalloc((void**)&s.h_io, sizeof(double) * (8 * s.cap + 2)) != hipSuccess ||
         hipMalloc(&s.arena, arena) != hipSuccess) {
@@ -414,7 +449,8 @@ hsma_status hsma_server_create(const hsma_server_cfg* cfg, hsma_server** out) {
   // affinity over as many recent systems per slot as a slot plan keeps
   // captured steps
   sv->core.reset(new CoreT(*sv->backend, cfg->queue_capacity, hsma::DevicePlan::kGraphCache));
-  for (int i = 0; i < nslots; ++i) sv->cb[i] = CallbackCtx{sv->core.get(), i};
+  for (int i = 0; i < nslots; ++i) sv->waiters.emplace_back(new SlotWaiter());
+  for (int i = 0; i < nslots; ++i) sv->waiters[(size_t)i]->th = std::thread(slot_waiter, sv.get(), i);
   sv->core->start();
   *out = sv.release();
   return HSMA_OK;
@@ -505,9 +541,18 @@ void hsma_server_shutdown(hsma_server* s) {
 void hsma_server_destroy(hsma_server* s) {
   if (!s) return;
   if (s->core) {
-    s->core->shutdown();
+    s->core->shutdown();   // running steps finish (their waiters report them)
     s->core->wait_idle();  // threads blocked in hsma_server_wait leave first
   }
+  for (auto& w : s->waiters) {
+    {
+      std::lock_guard<std::mutex> lk(w->mu);
+      w->stop = true;
+    }
+    w->cv.notify_one();
+    if (w->th.joinable()) w->th.join();
+  }
+  s->waiters.clear();
   for (Slot& sl : s->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     std::string err;
@@ -517,6 +562,7 @@ void hsma_server_destroy(hsma_server* s) {
     if (sl.arena) (void)hipFree(sl.arena);
     if (sl.d_io) (void)hipFree(sl.d_io);
     if (sl.h_io) (void)hipHostFree(sl.h_io);
+    if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   s->core.reset();

@@ -3,9 +3,8 @@
 // AddressSanitizer without a GPU (tests/test_host_sanitizers.py).  "Device"
 // memory is host memory; a stream is a worker thread that runs its queued
 // operations in order (copies, event records and waits, host functions,
-// and the work a fake plan enqueues); a host function runs on the stream's
-// thread after everything queued before it, and the stream continues only
-// when it returns, as the real runtime orders it.
+// and the work a fake plan enqueues); hipEventSynchronize blocks until the
+// event's last record has run on its stream.
 #pragma once
 
 #include <condition_variable>
@@ -22,7 +21,7 @@
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
-enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2 };
+enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipEventBlockingSync = 1 };
 typedef void (*hipHostFn_t)(void* user);
 
 namespace fakehip {

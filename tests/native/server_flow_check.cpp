@@ -1,5 +1,5 @@
 // The request server's host code (server.cpp: slots, plan classes, shared
-// slot arenas, host and device requests, completion by host functions,
+// slot arenas, host and device requests, completion by per-slot waiters,
 // creation and destruction) run end to end on the CPU against the fake HIP
 // runtime and the fake plan of fake_device.h, under ThreadSanitizer or
 // AddressSanitizer + UBSan, with request patterns of the serving benchmark
