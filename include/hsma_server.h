@@ -27,7 +27,8 @@
  * that sees the same system again (same size, same buffers) replays the
  * step it captured in a HIP graph instead of launching it kernel by kernel.
  * Completion: each slot has a thread blocked on the slot's end-of-step
- * event, which reports the slot done (no polling, no host callbacks).  A request's kernels and their order do not depend on what else
+ * event, which reports the slot done (no polling, no host callbacks).
+ * A request's kernels and their order do not depend on what else
  * runs, so its result is bitwise the same alone and in a mix.
  *
  * Device-resident systems: with HSMA_REQ_DEVICE the request's pointers are
