@@ -374,6 +374,54 @@ def replica_bench(hs, workloads, n_rep=64, rounds=6, slots=8, loads=(0.5, 0.8, 0
     return out
 
 
+def single_system_latency(hs, workloads, sizes=(500, 2000, 10000, 20000), steps=60, warmup=5):
+    """Latency of one request of the serving shape on an otherwise idle GPU,
+    through a plan of its own (no server): systems of the serving mix's
+    recipe (L = (N/0.05)^(1/3), +-1, p 8, K 162, F 512, FP32C), inputs in
+    HBM, the step replayed from its captured graph.  Per step: the device
+    time between HIP events around it, and the host round trip (enqueue to
+    results available: launch plus a stream synchronisation); p50 and p99
+    over `steps` steps."""
+    import numpy as np
+    import torch
+    from workloads import Workload
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()  # a stream of its own (steps on it are captured and replayed)
+    out = []
+    for n in sizes:
+        Lb = (n / 0.05) ** (1.0 / 3.0)
+        w = Workload(f"latency_{n}", 0, (Lb, Lb, Lb), n, 4000 + n, p=8, F=512, K=162, lam=1.5)
+        pos, q, lo, L = workloads.make_system(w)
+        x = torch.tensor(pos, device=dev)
+        qq = torch.tensor(q, device=dev)
+        en = torch.zeros(1, dtype=torch.float64, device=dev)
+        f = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        with hs.Plan(hs.Params(precision=hs.FP32C, p=8, K=162, F=512, lam=1.5), lo, L) as plan:
+            plan.set_graph(True)
+            torch.cuda.synchronize()
+            for _ in range(warmup):
+                plan.compute_device(x, qq, en, None, f, stream=stream.cuda_stream)
+            stream.synchronize()
+            dev_ms, wall_ms = [], []
+            for _ in range(steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                e0.record(stream)
+                plan.compute_device(x, qq, en, None, f, stream=stream.cuda_stream)
+                e1.record(stream)
+                stream.synchronize()
+                wall_ms.append((time.perf_counter() - t0) * 1e3)
+                dev_ms.append(e0.elapsed_time(e1))
+        out.append({"n": n, "device_p50_ms": float(np.percentile(dev_ms, 50)),
+                    "device_p99_ms": float(np.percentile(dev_ms, 99)),
+                    "round_trip_p50_ms": float(np.percentile(wall_ms, 50)),
+                    "round_trip_p99_ms": float(np.percentile(wall_ms, 99))})
+        torch.cuda.synchronize()
+        del x, qq, en, f
+    return {"note": "one request on an idle GPU through its own plan (no server, graph replay), p50/p99 over "
+                    f"{steps} steps", "sizes": out}
+
+
 def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells, f64_cells, steps=10):
     """The same system with the sphere near set (images inside the sphere
     only, Sec. 2.2) at parameters that reach the same 1e-5 force bar:
@@ -656,6 +704,8 @@ def main():
     if not args.no_secondary:
         progress("50,000-ion system (27 cells)")
         out["c2_50000"] = c2_bench(hs, workloads, args)
+        progress("single-request latency at serving sizes")
+        out["single_system_latency"] = single_system_latency(hs, workloads)
     if args.serving:
         progress("serving mix")
         out["serving"] = serving_bench(hs, workloads)
