@@ -10,6 +10,11 @@
  *   v += dt/2 F/m;  x += dt v (wrapped along the periodic axes);
  *   F = F_Coulomb (the plan's step, F_i = q_i E_i) + F_LJ (pairs, walls);
  *   v += dt/2 F/m;  thermo row.
+ * With the Nose-Hoover thermostat (the paper's runs are NVT), half a
+ * thermostat step before and after, in the time-reversible splitting:
+ *   xi += dt/4 G;  v *= exp(-xi dt/2);  eta += dt/2 xi;  xi += dt/4 G,
+ *   G = (2 E_kin - nf kT) / Q,
+ * and the thermo row's E_kin and pressure are those after it.
  * Everything runs on the device on the caller's buffers; the plan's step is
  * replayed from a captured HIP graph after the first steps.
  *
@@ -50,6 +55,10 @@ typedef struct hsma_md_params {
   double wall_epsilon;  /* slab: the same form in the distance to each wall      */
   double wall_sigma;    /*   (wall_epsilon 0: no walls)                          */
   double wall_rcut;     /*   (0: 2^(1/6) wall_sigma)                             */
+  double nh_kT;         /* Nose-Hoover thermostat (NVT, as the paper's runs of
+                             Sec. 4.1 and 4.3): target kT, with               */
+  double nh_damping;    /*   damping time tau (thermostat mass nf kT tau^2, nf =
+                             3n - 3, slab 3n - 2); both 0: constant energy (NVE) */
 } hsma_md_params;
 
 typedef struct hsma_md hsma_md;
@@ -78,15 +87,26 @@ hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const d
 hsma_status hsma_md_create_for_box(const hsma_md_params* params, int geometry, const double box_lo[3],
                                    const double box_len[3], int64_t n, hsma_md** out);
 
-/* First half of a step: v += dt/2 F/m, x += dt v (wrapped).              */
+/* First half of a step: the thermostat's first half if one is set, then
+ * v += dt/2 F/m, x += dt v (wrapped).                                    */
 hsma_status hsma_md_drift(hsma_md* md, void* stream, double* d_x, double* d_v, const double* d_f,
                           const double* d_m);
 
 /* Second half, once d_f holds the Coulomb forces at the new d_x and
- * d_e_coulomb their energy (device scalar): F += F_LJ, v += dt/2 F/m, and
- * one thermo row (device, 4 doubles, or NULL).                          */
+ * d_e_coulomb their energy (device scalar): F += F_LJ, v += dt/2 F/m, one
+ * thermo row (device, 4 doubles, or NULL), then the thermostat's closing
+ * half if one is set.                                                   */
 hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double* d_v, double* d_f,
                            const double* d_m, const double* d_e_coulomb, double* d_thermo_row);
+
+/* Thermostat state after the driver's last enqueued call, copied on
+ * `stream` (which first waits for that call) into d_state (3 device
+ * doubles): xi (thermostat velocity), eta (its position) and its energy
+ * Q xi^2 / 2 + nf kT eta, so that E_Coulomb + E_LJ + E_kin + that energy
+ * is conserved by the integration (all 0 without a thermostat).  A later
+ * call of the driver on another stream must be ordered after this copy by
+ * the caller, as for any two calls of one driver.                       */
+hsma_status hsma_md_thermostat(hsma_md* md, void* stream, double* d_state);
 
 void hsma_md_destroy(hsma_md* md);
 

@@ -27,15 +27,24 @@ struct MdLJ {
   double weps, wsig, wrc, wshift;   // walls, same form in the distance d to a wall
 };
 
-// v += dt/2 F/m; x += dt v; wrapped into [lo, lo + L) along periodic axes.
+// Nose-Hoover thermostat: target kT, degrees of freedom, thermostat mass
+// Q = nf kT tau^2, box volume (pressure's kinetic part).
+struct MdNH {
+  double dt, kT, nf, Q, vol;
+};
+
+// v = s v + dt/2 F/m (s: the thermostat's velocity scale, 1 without one);
+// x += dt v; wrapped into [lo, lo + L) along periodic axes.
 __global__ __launch_bounds__(kMdBlock) void k_md_kick_drift(int n, double dt, double* __restrict__ x,
                                                             double* __restrict__ v, const double* __restrict__ f,
-                                                            const double* __restrict__ m, MdBox box) {
+                                                            const double* __restrict__ m, MdBox box,
+                                                            const double* __restrict__ scale) {
   const int i = blockIdx.x * kMdBlock + threadIdx.x;
   if (i >= n) return;
   const double h = 0.5 * dt / m[i];
+  const double sv = scale ? *scale : 1.0;
   for (int k = 0; k < 3; ++k) {
-    const double vk = v[3 * i + k] + h * f[3 * i + k];
+    const double vk = sv * v[3 * i + k] + h * f[3 * i + k];
     v[3 * i + k] = vk;
     double xk = x[3 * i + k] + dt * vk;
     if (k < 2 || !box.slab) xk -= box.L[k] * floor((xk - box.lo[k]) / box.L[k]);
@@ -149,6 +158,47 @@ __global__ __launch_bounds__(kMdBlock) void k_md_kick(int n, double dt, double* 
   if (threadIdx.x == 0) part[blockIdx.x] = rk[0];
 }
 
+// Half a step of the Nose-Hoover thermostat (time-reversible splitting):
+// xi += dt/4 G(K); s = exp(-dt/2 xi); K -> s^2 K; eta += dt/2 xi;
+// xi += dt/4 G(K), with G(K) = (2K - nf kT) / Q.  K: the sum of the
+// kinetic-energy block partials (start of a step) or the thermo row's
+// (end of a step, whose E_kin and pressure are then updated to the scaled
+// velocities).  nh = {xi, eta, E_thermostat = Q xi^2 / 2 + nf kT eta, s};
+// the velocities are scaled by s by the next kernel that reads them.
+__global__ __launch_bounds__(64) void k_md_nh(int nblk, const double* __restrict__ ke_part, double* __restrict__ row,
+                                              double* __restrict__ nh, MdNH p) {
+  if (threadIdx.x != 0) return;
+  double K = 0.0;
+  if (row) {
+    K = row[2];
+  } else {
+    for (int b = 0; b < nblk; ++b) K += ke_part[b];
+  }
+  const double g = p.nf * p.kT;
+  double xi = nh[0], eta = nh[1];
+  xi += 0.25 * p.dt * (2.0 * K - g) / p.Q;
+  const double sc = exp(-0.5 * p.dt * xi);
+  const double K2 = K * sc * sc;
+  eta += 0.5 * p.dt * xi;
+  xi += 0.25 * p.dt * (2.0 * K2 - g) / p.Q;
+  nh[0] = xi;
+  nh[1] = eta;
+  nh[2] = 0.5 * p.Q * xi * xi + g * eta;
+  nh[3] = sc;
+  if (row) {
+    row[3] += 2.0 * (K2 - K) / (3.0 * p.vol);
+    row[2] = K2;
+  }
+}
+
+// v *= s (the end-of-step thermostat scale).
+__global__ __launch_bounds__(kMdBlock) void k_md_scale(int n, double* __restrict__ v, const double* __restrict__ nh) {
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  if (i >= n) return;
+  const double sc = nh[3];
+  for (int k = 0; k < 3; ++k) v[3 * i + k] *= sc;
+}
+
 // Thermo row: E_C, E_LJ, E_kin, P (fixed-order sums of the block partials).
 __global__ __launch_bounds__(64) void k_md_thermo(int nblk, const double* __restrict__ lj_part,
                                                   const double* __restrict__ ke_part,
@@ -182,11 +232,47 @@ struct hsma_md {
   double* d_ke_part = nullptr;  // nblk
   double* d_ecoul = nullptr;
   double* d_row = nullptr;      // 4: thermo row when the caller passes none
+  double* d_nh = nullptr;       // 4: thermostat state {xi, eta, E_thermostat, scale}
+  bool nh_on = false;
+  hsma::MdNH nh{};
   hipEvent_t ev = nullptr;      // end of the driver's last call (its kernels follow the plan's)
   bool recorded = false;
 };
 
 namespace {
+
+// Start of a step: the thermostat's first half at the current velocities
+// (whose scale the kick-drift applies), then v = s v + dt/2 F/m, x += dt v.
+void md_begin_step(hsma_md* md, hipStream_t st, double* x, double* v, const double* f, const double* m) {
+  const int n = (int)md->n;
+  if (md->nh_on) {
+    hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, 0.0, v, f, m,
+                       md->d_ke_part);
+    hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_ke_part,
+                       (double*)nullptr, md->d_nh, md->nh);
+  }
+  hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, x, v, f, m,
+                     md->box, md->nh_on ? (const double*)(md->d_nh + 3) : (const double*)nullptr);
+}
+
+// End of a step, once f holds the Coulomb forces at x and d_e_coulomb their
+// energy: F += F_LJ, v += dt/2 F/m, the thermo row, then the thermostat's
+// second half (row updated, v scaled).
+void md_end_step(hsma_md* md, hipStream_t st, const double* x, double* v, double* f, const double* m,
+                 const double* e_coul, double* row) {
+  const int n = (int)md->n;
+  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, x, md->box, md->lj, f,
+                     md->d_lj_part);
+  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, v,
+                     (const double*)f, m, md->d_ke_part);
+  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
+  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
+                     (const double*)md->d_ke_part, e_coul, vol, md->box.slab, row);
+  if (md->nh_on) {
+    hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, 0, (const double*)nullptr, row, md->d_nh, md->nh);
+    hipLaunchKernelGGL(hsma::k_md_scale, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, v, (const double*)md->d_nh);
+  }
+}
 
 // F = F_Coulomb (the plan's step) + F_LJ at x; one thermo row (E_kin from v).
 hsma_status md_forces(hsma_md* md, hipStream_t st, const double* x, const double* v, double* f, const double* q,
@@ -247,7 +333,9 @@ namespace {
 hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, const double lo[3],
                       const double L[3], int64_t n, hsma_md** out) {
   if (!(p->dt > 0) || !std::isfinite(p->dt) || !(p->lj_epsilon >= 0) || !(p->lj_sigma > 0) || !(p->lj_rcut >= 0) ||
-      !(p->wall_epsilon >= 0) || !(p->wall_rcut >= 0) || (p->wall_epsilon > 0 && !(p->wall_sigma > 0)))
+      !(p->wall_epsilon >= 0) || !(p->wall_rcut >= 0) || (p->wall_epsilon > 0 && !(p->wall_sigma > 0)) ||
+      !(p->nh_kT >= 0) || !(p->nh_damping >= 0) || !std::isfinite(p->nh_kT) || !std::isfinite(p->nh_damping) ||
+      ((p->nh_kT > 0) != (p->nh_damping > 0)))
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "invalid MD parameter");
   std::unique_ptr<hsma_md> md(new (std::nothrow) hsma_md());
   if (!md) return hsma::set_last_error(HSMA_ERR_OOM, "host allocation failed");
@@ -276,7 +364,17 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
     md->lj.wshift = -4.0 * p->wall_epsilon * (w6 * w6 - w6);
   }
   md->nblk = (int)((n + hsma::kMdBlock - 1) / hsma::kMdBlock);
-  if (hipMalloc((void**)&md->d_lj_part, sizeof(double) * 2 * md->nblk) != hipSuccess ||
+  // Nose-Hoover: degrees of freedom without the conserved momentum (3D:
+  // 3; slab: x and y), thermostat mass nf kT tau^2
+  md->nh_on = p->nh_kT > 0;
+  md->nh.dt = p->dt;
+  md->nh.kT = p->nh_kT;
+  md->nh.nf = 3.0 * (double)n - (md->box.slab ? 2.0 : 3.0);
+  md->nh.Q = md->nh.nf * p->nh_kT * p->nh_damping * p->nh_damping;
+  md->nh.vol = L[0] * L[1] * L[2];
+  if (hipMalloc((void**)&md->d_nh, sizeof(double) * 4) != hipSuccess ||
+      hipMemset(md->d_nh, 0, sizeof(double) * 4) != hipSuccess ||
+      hipMalloc((void**)&md->d_lj_part, sizeof(double) * 2 * md->nblk) != hipSuccess ||
       hipMalloc((void**)&md->d_ke_part, sizeof(double) * md->nblk) != hipSuccess ||
       hipMalloc((void**)&md->d_ecoul, sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&md->d_row, sizeof(double) * 4) != hipSuccess ||
@@ -292,10 +390,13 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
 hsma_status hsma_md_drift(hsma_md* md, void* stream, double* d_x, double* d_v, const double* d_f,
                           const double* d_m) {
   if (!md || !d_x || !d_v || !d_f || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
-  hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, (hipStream_t)stream,
-                     (int)md->n, md->prm.dt, d_x, d_v, d_f, d_m, md->box);
+  md_begin_step(md, (hipStream_t)stream, d_x, d_v, d_f, d_m);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
+  // the thermostat's half uses the driver's buffers: destroy waits for it
+  if (hipEventRecord(md->ev, (hipStream_t)stream) != hipSuccess)
+    return hsma::set_last_error(HSMA_ERR_DEVICE, "hipEventRecord failed");
+  md->recorded = true;
   return HSMA_OK;
 }
 
@@ -304,15 +405,7 @@ hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double*
   if (!md || !d_x || !d_v || !d_f || !d_m || !d_e_coulomb)
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  const int n = (int)md->n;
-  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, d_x, md->box, md->lj, d_f,
-                     md->d_lj_part);
-  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, d_v,
-                     (const double*)d_f, d_m, md->d_ke_part);
-  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
-  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
-                     (const double*)md->d_ke_part, d_e_coulomb, vol, md->box.slab,
-                     d_thermo_row ? d_thermo_row : md->d_row);
+  md_end_step(md, st, d_x, d_v, d_f, d_m, d_e_coulomb, d_thermo_row ? d_thermo_row : md->d_row);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
   if (hipEventRecord(md->ev, st) != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, "hipEventRecord failed");
@@ -345,18 +438,10 @@ hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, doub
     return hsma::set_last_error(s, err);
   const int n = (int)md->n;
   for (int step = 0; step < nsteps; ++step) {
-    hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, d_x, d_v,
-                       (const double*)d_f, d_m, md->box);
+    md_begin_step(md, st, d_x, d_v, d_f, d_m);
     s = md->plan->dev.run(st, n, d_x, d_q, md->d_ecoul, nullptr, d_f, err);
     if (s != HSMA_OK) return hsma::set_last_error(s, err);
-    hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, (const double*)d_x, md->box,
-                       md->lj, d_f, md->d_lj_part);
-    hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, d_v,
-                       (const double*)d_f, d_m, md->d_ke_part);
-    const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
-    hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
-                       (const double*)md->d_ke_part, (const double*)md->d_ecoul, vol, md->box.slab,
-                       d_thermo ? d_thermo + 4 * (size_t)step : md->d_row);
+    md_end_step(md, st, d_x, d_v, d_f, d_m, md->d_ecoul, d_thermo ? d_thermo + 4 * (size_t)step : md->d_row);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
@@ -365,10 +450,20 @@ hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, doub
   return HSMA_OK;
 }
 
+hsma_status hsma_md_thermostat(hsma_md* md, void* stream, double* d_state) {
+  if (!md || !d_state) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (md->recorded && hipStreamWaitEvent((hipStream_t)stream, md->ev, 0) != hipSuccess)
+    return hsma::set_last_error(HSMA_ERR_DEVICE, "hipStreamWaitEvent failed");
+  if (hipMemcpyAsync(d_state, md->d_nh, sizeof(double) * 3, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
+      hipSuccess)
+    return hsma::set_last_error(HSMA_ERR_DEVICE, "hipMemcpyAsync failed");
+  return HSMA_OK;
+}
+
 void hsma_md_destroy(hsma_md* md) {
   if (!md) return;
   if (md->recorded) (void)hipEventSynchronize(md->ev);  // after the plan's work on the same stream
-  void* ps[] = {md->d_lj_part, md->d_ke_part, md->d_ecoul, md->d_row};
+  void* ps[] = {md->d_lj_part, md->d_ke_part, md->d_ecoul, md->d_row, md->d_nh};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (md->ev) (void)hipEventDestroy(md->ev);

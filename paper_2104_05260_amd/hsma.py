@@ -86,7 +86,7 @@ class _CResult(ctypes.Structure):
 class _CMDParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("lj_epsilon", ctypes.c_double), ("lj_sigma", ctypes.c_double),
                 ("lj_rcut", ctypes.c_double), ("wall_epsilon", ctypes.c_double), ("wall_sigma", ctypes.c_double),
-                ("wall_rcut", ctypes.c_double)]
+                ("wall_rcut", ctypes.c_double), ("nh_kT", ctypes.c_double), ("nh_damping", ctypes.c_double)]
 
 
 class _CServerStats(ctypes.Structure):
@@ -192,8 +192,9 @@ def load_library():
     lib.hsma_md_create_for_box.argtypes = [ctypes.POINTER(_CMDParams), ctypes.c_int, d, d, i64, ctypes.POINTER(vp)]
     lib.hsma_md_drift.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.hsma_md_finish.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hsma_md_thermostat.argtypes = [vp, vp, vp]
     for name in ("hsma_md_create", "hsma_md_run", "hsma_md_forces", "hsma_md_create_for_box", "hsma_md_drift",
-                 "hsma_md_finish"):
+                 "hsma_md_finish", "hsma_md_thermostat"):
         getattr(lib, name).restype = ctypes.c_int
     lib.hsma_server_get_stats.restype = ctypes.c_int
     lib.hsma_server_destroy.argtypes = [vp]
@@ -494,7 +495,7 @@ class MD:
 
     def __init__(self, plan: Optional["Plan"], n: int, dt: float, lj_epsilon: float = 1.0, lj_sigma: float = 1.0,
                  lj_rcut: float = 0.0, wall_epsilon: float = 0.0, wall_sigma: float = 1.0, wall_rcut: float = 0.0,
-                 geometry: int = GEOM_3D, box_lo=None, box_len=None):
+                 geometry: int = GEOM_3D, box_lo=None, box_len=None, nh_kT: float = 0.0, nh_damping: float = 0.0):
         """With a plan: hsma_md_create.  With plan None: a driver for the
         box (hsma_md_create_for_box) whose Coulomb forces come from
         elsewhere (drift / finish around a server request)."""
@@ -502,7 +503,7 @@ class MD:
         self._lib = lib
         self._plan = plan  # kept alive: the driver uses it
         self._m = ctypes.c_void_p()
-        p = _CMDParams(dt, lj_epsilon, lj_sigma, lj_rcut, wall_epsilon, wall_sigma, wall_rcut)
+        p = _CMDParams(dt, lj_epsilon, lj_sigma, lj_rcut, wall_epsilon, wall_sigma, wall_rcut, nh_kT, nh_damping)
         if plan is not None:
             _check(lib.hsma_md_create(plan._p, ctypes.byref(p), int(n), ctypes.byref(self._m)))
         else:
@@ -547,6 +548,14 @@ class MD:
             stream = torch.cuda.current_stream().cuda_stream
         _check(self._lib.hsma_md_finish(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v), self._ptr(f),
                                         self._ptr(m), self._ptr(e_coulomb), self._ptr(thermo_row)))
+
+    def thermostat(self, state, stream=None):
+        """Copies the thermostat's (xi, eta, energy) into `state`, a float64
+        GPU tensor of 3 entries (hsma_md_thermostat)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self._lib.hsma_md_thermostat(self._m, ctypes.c_void_p(stream), self._ptr(state)))
 
     def close(self):
         if self._m:

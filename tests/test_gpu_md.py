@@ -83,6 +83,51 @@ def cpu_verlet(x, v, q, m, box, coulomb, dt, nsteps, slab=False, weps=0.0):
     return x, v, np.array(rows)
 
 
+def nh_half(xi, eta, K, nf, kT, Q, dt):
+    """Half a step of the Nose-Hoover chain of length one in the symmetric
+    (Trotter) splitting: quarter kick of the thermostat momentum, velocity
+    scale exp(-dt/2 xi), thermostat position, quarter kick.  Returns the new
+    (xi, eta) and the scale."""
+    xi += 0.25 * dt * (2 * K - nf * kT) / Q
+    s = np.exp(-0.5 * dt * xi)
+    eta += 0.5 * dt * xi
+    xi += 0.25 * dt * (2 * K * s * s - nf * kT) / Q
+    return xi, eta, s
+
+
+def cpu_nose_hoover(x, v, q, m, box, coulomb, dt, nsteps, kT, tau, slab=False, weps=0.0):
+    """NVT on the CPU: thermostat half, velocity Verlet, thermostat half,
+    with the oracle's Coulomb forces.  nf = 3n - 3 (3n - 2 in the slab),
+    Q = nf kT tau^2.  Rows: E_C, E_LJ, E_kin, P after the closing half;
+    also the thermostat's (xi, eta, Q xi^2 / 2 + nf kT eta) per step."""
+    x, v = x.copy(), v.copy()
+    n = len(x)
+    nf = 3 * n - (2 if slab else 3)
+    Q = nf * kT * tau * tau
+    xi = eta = 0.0
+    fc, ec = coulomb(x)
+    fl, el, wl = lj_numpy(x, box, slab, weps=weps)
+    f = fc + fl
+    rows, nh = [], []
+    for _ in range(nsteps):
+        xi, eta, s = nh_half(xi, eta, 0.5 * (m[:, None] * v * v).sum(), nf, kT, Q, dt)
+        v = s * v + 0.5 * dt * f / m[:, None]
+        x = x + dt * v
+        for k in range(2 if slab else 3):
+            x[:, k] -= box[k] * np.floor(x[:, k] / box[k])
+        fc, ec = coulomb(x)
+        fl, el, wl = lj_numpy(x, box, slab, weps=weps)
+        f = fc + fl
+        v = v + 0.5 * dt * f / m[:, None]
+        xi, eta, s = nh_half(xi, eta, 0.5 * (m[:, None] * v * v).sum(), nf, kT, Q, dt)
+        v = s * v
+        ke = 0.5 * (m[:, None] * v * v).sum()
+        pres = (2 * ke + wl + (0.0 if slab else ec)) / (3 * box.prod())
+        rows.append((ec, el, ke, pres))
+        nh.append((xi, eta, 0.5 * Q * xi * xi + nf * kT * eta))
+    return x, v, np.array(rows), np.array(nh)
+
+
 def min_image_diff(a, b, box, axes=3):
     d = a - b
     for k in range(axes):
@@ -133,6 +178,45 @@ def test_md_trajectory_matches_cpu_3d(prec):
     assert de <= (1e-10 if prec == 0 else 1e-6) and dk <= tol and dl <= tol and dp <= tol
 
 
+def test_nose_hoover_trajectory_matches_cpu():
+    """NVT (Nose-Hoover, target kT = 1.5 from a start at kT = 1, tau = 0.05):
+    216 ions, FP64 path, 25 steps: positions, velocities, the per step rows
+    (E_kin and pressure after the thermostat's closing half) and the
+    thermostat's state against the same splitting on the CPU with the
+    oracle's forces (1e-9)."""
+    import torch
+    box = np.array([7.0, 7.0, 7.0])
+    pos, q, v0, m = lattice_system((6, 6, 6), box, 11, jitter=0.05)
+    kc, kT, tau = 2.0, 1.5, 0.05
+    params = hs.Params(precision=0, p=8, K=162, F=512, lam=1.5, coulomb_k=kc)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+    nsteps, dt = 25, 0.002
+    th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+    st = torch.zeros(3, dtype=torch.float64, device=dev)
+    with hs.Plan(params, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt, nh_kT=kT, nh_damping=tau) as md:
+        md.run(x, v, f, qq, mm, nsteps, thermo=th)
+        md.thermostat(st)
+        torch.cuda.synchronize()
+    xg, vg, tg, sg = x.cpu().numpy(), v.cpu().numpy(), th.cpu().numpy(), st.cpu().numpy()
+
+    def coulomb(xx):
+        r = ohsma.hsma3d(xx, q, np.zeros(3), box, 8, 162, 512, 1.5)
+        return kc * r.force, kc * r.energy
+
+    xc, vc, rc, nc = cpu_nose_hoover(pos, v0, q, m, box, coulomb, dt, nsteps, kT, tau)
+    dx = min_image_diff(xg, xc, box) / box[0]
+    dv = np.abs(vg - vc).max() / np.abs(vc).max()
+    dr = (np.abs(tg - rc) / np.abs(rc).max(0)).max()
+    dn = np.abs(sg - nc[-1]).max() / np.abs(nc[-1]).max()
+    note(f"   positions {dx:.2e} velocities {dv:.2e} rows {dr:.2e} thermostat {dn:.2e}; "
+         f"E_kin {rc[0, 2]:.3f} -> {rc[-1, 2]:.3f}, xi {nc[-1, 0]:.4f}")
+    assert dx <= 1e-9 and dv <= 1e-9 and dr <= 1e-9 and dn <= 1e-9
+    assert nc[-1, 0] < 0.0  # colder than the target: the thermostat heats (xi < 0)
+
+
 def test_md_energy_conservation_dt2():
     """NVE: the total energy's fluctuation about its start falls like dt^2
     (velocity Verlet), and stays small, over the same time with dt and
@@ -167,6 +251,75 @@ def test_md_energy_conservation_dt2():
     note(f"   fluctuation ratio dt / (dt/2): {ratio:.2f}")
     assert 2.5 <= ratio <= 6.5
     assert fluct[1] <= 1e-3 * abs(r0[2])
+
+
+def test_nose_hoover_extended_energy_dt2():
+    """NVT conserves the extended energy E_C + E_LJ + E_kin + Q xi^2 / 2 +
+    nf kT eta: its fluctuation about the start falls like dt^2 (the splitting
+    is second order) over the same time with dt and dt / 2, while the
+    thermostat exchanges energy with the system (FP64 path, p = 10, target
+    kT = 1.6, tau = 0.1)."""
+    import torch
+    box = np.array([11.0, 11.0, 11.0])
+    pos, q, v0, m = lattice_system((4, 4, 6), box, 21)
+    params = hs.Params(precision=0, p=10, K=242, F=800, lam=1.5, coulomb_k=1.0)
+    dev = torch.device("cuda:0")
+    T = 0.8
+    fluct, moved = [], []
+    for dt in (0.004, 0.002):
+        nsteps = int(round(T / dt))
+        x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+        f = torch.zeros_like(x)
+        qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+        th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+        st = torch.zeros((nsteps, 3), dtype=torch.float64, device=dev)
+        row0 = torch.zeros(4, dtype=torch.float64, device=dev)
+        with hs.Plan(params, (0, 0, 0), box) as plan, \
+                hs.MD(plan, len(q), dt, nh_kT=1.6, nh_damping=0.1) as md:
+            md.forces(x, v, f, qq, mm, thermo_row=row0)
+            for i in range(nsteps):
+                md.run(x, v, f, qq, mm, 1, forces_valid=True, thermo=th[i])
+                md.thermostat(st[i])
+            torch.cuda.synchronize()
+        t, sn, r0 = th.cpu().numpy(), st.cpu().numpy(), row0.cpu().numpy()
+        H0 = r0[0] + r0[1] + r0[2]
+        H = t[:, 0] + t[:, 1] + t[:, 2] + sn[:, 2]
+        fl = np.sqrt(np.mean((H - H0) ** 2))
+        fluct.append(fl)
+        moved.append(np.abs(sn[:, 2]).max())
+        note(f"   dt {dt}: {nsteps} steps, H0 {H0:.8f}, rms(H - H0) {fl:.3e}, max |E_thermostat| {moved[-1]:.3e}, "
+             f"E_kin {t[0, 2]:.3f} -> {t[-1, 2]:.3f}")
+    ratio = fluct[0] / fluct[1]
+    note(f"   fluctuation ratio dt / (dt/2): {ratio:.2f}")
+    assert 2.5 <= ratio <= 6.5
+    assert fluct[1] <= 1e-3 * moved[1]
+
+
+def test_nose_hoover_mean_temperature_is_the_target():
+    """Over a Nose-Hoover run the thermostat's momentum obeys
+    Q dxi/dt = 2 E_kin - nf kT, so the time average of 2 E_kin / nf equals
+    kT up to Q (xi_end - xi_start) / (nf time) whatever the dynamics: 96 ions
+    from kT = 1 thermostatted to kT = 1.5 (tau = 0.1, 1000 steps of 0.004),
+    the average over the last 750 steps within 3 percent of the target."""
+    import torch
+    box = np.array([11.0, 11.0, 11.0])
+    pos, q, v0, m = lattice_system((4, 4, 6), box, 23)
+    params = hs.Params(precision=0, p=8, K=162, F=512, lam=1.5, coulomb_k=1.0)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+    nsteps, dt, kT = 1000, 0.004, 1.5
+    th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+    with hs.Plan(params, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt, nh_kT=kT, nh_damping=0.1) as md:
+        md.run(x, v, f, qq, mm, nsteps, thermo=th)
+        torch.cuda.synchronize()
+    t = th.cpu().numpy()
+    nf = 3 * len(q) - 3
+    temp = 2 * t[:, 2] / nf
+    mean = temp[250:].mean()
+    note(f"   kinetic temperature: first step {temp[0]:.3f}, mean over the last 750 steps {mean:.4f} (target {kT})")
+    assert abs(mean - kT) <= 0.03 * kT
 
 
 def test_md_slab_with_walls_matches_cpu():

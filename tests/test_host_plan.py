@@ -72,6 +72,24 @@ def test_plan_parameter_errors(bad, err):
     assert e.value.name == err
 
 
+@pytest.mark.parametrize("bad", [
+    dict(nh_kT=1.0),                    # a target temperature needs a damping time
+    dict(nh_damping=0.1),               # and a damping time a target
+    dict(nh_kT=-1.0, nh_damping=0.1),
+    dict(nh_kT=float("nan"), nh_damping=0.1),
+    dict(dt=0.0),
+])
+def test_md_parameter_errors(bad):
+    """hsma_md_create_for_box rejects inconsistent MD parameters before it
+    touches a device."""
+    lib_or_skip()
+    kw = dict(dt=0.001)
+    kw.update(bad)
+    with pytest.raises(hs.HSMAError) as e:
+        hs.MD(None, 10, box_lo=[0, 0, 0], box_len=[5, 5, 5], **kw)
+    assert e.value.name == "HSMA_ERR_INVALID_ARG"
+
+
 def test_solid_harmonics_harmonic_orthonormal_and_same_span_as_oracle():
     lib_or_skip()
     p = 8
