@@ -422,6 +422,64 @@ def single_system_latency(hs, workloads, sizes=(500, 2000, 10000, 20000), steps=
                     f"{steps} steps", "sizes": out}
 
 
+def md_bench(hs, steps=200, warmup=20, seed=91):
+    """The MD driver on the 3D electrolyte of the paper's accuracy study
+    (Sec. 4.1, monovalent case): 1,500 cations and 1,500 anions, WCA soft
+    spheres (sigma 1, epsilon kT) in a periodic box of 25 sigma, Bjerrum
+    length 3.5 sigma (Coulomb prefactor 3.5 kT sigma / e^2), time step
+    0.01 tau, Nose-Hoover thermostat at kT = 1 (damping time 0.1 tau: the
+    paper's 0.01 tau equals the time step, a thermostat period of about
+    four steps; the rate does not depend on it); HSMA FP32C with p 8,
+    K 162, F 512.  Ions on 3,000 random sites of a
+    15^3 lattice (no contacts at the start), Maxwell velocities.  `warmup`
+    steps (the Coulomb step is captured into a graph), then `steps` steps
+    in one hsma_md_run, timed with HIP events on the driver's stream.
+    Reported beside the rate: the mean kinetic temperature of the timed
+    steps and the drift of the extended energy (E_C + E_LJ + E_kin + the
+    thermostat's) over them."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    L, m_side, n = 25.0, 15, 3000
+    g = (np.stack(np.meshgrid(*(np.arange(m_side),) * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5) * (L / m_side)
+    pos = g[rng.choice(len(g), n, replace=False)]
+    q = np.where(rng.permutation(n) % 2 == 0, 1.0, -1.0)
+    v0 = rng.normal(0.0, 1.0, (n, 3))
+    v0 -= v0.mean(0)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.ones(n, dtype=torch.float64, device=dev)
+    th = torch.zeros((steps, 4), dtype=torch.float64, device=dev)
+    th0 = torch.zeros((warmup, 4), dtype=torch.float64, device=dev)
+    s0, s1 = (torch.zeros(3, dtype=torch.float64, device=dev) for _ in range(2))
+    stream = torch.cuda.Stream()
+    prm = hs.Params(precision=hs.FP32C, p=8, K=162, F=512, lam=1.5, coulomb_k=3.5)
+    dt = 0.01
+    with hs.Plan(prm, (0.0, 0.0, 0.0), (L, L, L)) as plan, \
+            hs.MD(plan, n, dt, nh_kT=1.0, nh_damping=0.1) as md:
+        torch.cuda.synchronize()
+        md.run(x, v, f, qq, mm, warmup, forces_valid=False, thermo=th0, stream=stream.cuda_stream)
+        md.thermostat(s0, stream=stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        md.run(x, v, f, qq, mm, steps, forces_valid=True, thermo=th, stream=stream.cuda_stream)
+        e1.record(stream)
+        md.thermostat(s1, stream=stream.cuda_stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    t, t0, a, b = th.cpu().numpy(), th0.cpu().numpy(), s0.cpu().numpy(), s1.cpu().numpy()
+    nf = 3 * n - 3
+    h0 = t0[-1, :3].sum() + a[2]
+    h1 = t[-1, :3].sum() + b[2]
+    return {"system": "3D electrolyte, 3,000 ions (+-1), L 25 sigma, Bjerrum length 3.5 sigma, WCA; "
+                      "NVT (Nose-Hoover kT 1, damping 0.1 tau), dt 0.01 tau; FP32C p 8",
+            "n": n, "steps": steps, "ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
+            "mean_kT": float(np.mean(2 * t[:, 2] / nf)),
+            "extended_energy_drift_per_step": float((h1 - h0) / steps),
+            "extended_energy": float(h0)}
+
+
 def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells, f64_cells, steps=10):
     """The same system with the sphere near set (images inside the sphere
     only, Sec. 2.2) at parameters that reach the same 1e-5 force bar:
@@ -706,6 +764,8 @@ def main():
         out["c2_50000"] = c2_bench(hs, workloads, args)
         progress("single-request latency at serving sizes")
         out["single_system_latency"] = single_system_latency(hs, workloads)
+        progress("MD driver: 3,000-ion electrolyte, NVT")
+        out["md"] = md_bench(hs)
     if args.serving:
         progress("serving mix")
         out["serving"] = serving_bench(hs, workloads)

@@ -27,8 +27,10 @@
  * fourth value is the LJ part (2 E_kin + W_LJ) / (3 V) only.
  *
  * The LJ pairs are found by testing all N^2 minimum-image distances (LDS
- * tiles of 256 sources): meant for the ensembles served here (up to about
- * 10^4 - 10^5 ions per replica), not for large single systems.
+ * tiles of 256 sources; small systems split the sources into chunks over
+ * more blocks and sum the chunks' forces in a fixed order): meant for the
+ * ensembles served here (up to about 10^4 - 10^5 ions per replica), not
+ * for large single systems.
  *
  * Layouts as in hsma.h: positions, velocities, forces n x 3 row-major FP64;
  * charges and masses n FP64.  Positions must lie in the plan's box (slab: z

@@ -18,7 +18,7 @@ namespace {
 constexpr int kMdBlock = 256;
 
 struct MdBox {
-  double lo[3], L[3];
+  double lo[3], L[3], iL[3];  // iL = 1 / L
   int slab;  // z not periodic (walls at lo[2] and lo[2] + L[2])
 };
 
@@ -52,15 +52,23 @@ __global__ __launch_bounds__(kMdBlock) void k_md_kick_drift(int n, double dt, do
   }
 }
 
-// Lennard-Jones forces added to f (pairs by the minimum image, every pair
-// in a fixed order per particle; walls in the slab), and per-block sums of
-// the energy (1/2 per pair side, walls in full) and of the pair virial
-// r . F (1/2 per side).  Sources staged through LDS in tiles of kMdBlock.
+// Lennard-Jones forces (pairs by the minimum image; walls in the slab):
+// block (b, c) takes targets b * kMdBlock ... and the sources of chunk c
+// (`chunk` sources, a multiple of kMdBlock, staged through LDS in tiles),
+// so that small systems still spread over many blocks.  It writes its
+// targets' partial forces to fpart[c] (summed in chunk order by the next
+// kick) and its sums of the energy (1/2 per pair side, walls in full, by
+// the last chunk) and of the pair virial r . F (1/2 per side) to part.
+// The image of a source is the nearest one, rint(d / L) taken as
+// rint(d * (1 / L)): the two differ only near |d| = L / 2, and the cut-off
+// is below half a box edge, so no pair inside it is affected.
 __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restrict__ x, MdBox box, MdLJ lj,
-                                                    double* __restrict__ f, double* __restrict__ part) {
+                                                    int chunk, double* __restrict__ fpart,
+                                                    double* __restrict__ part) {
   __shared__ double sx[kMdBlock], sy[kMdBlock], sz[kMdBlock];
   __shared__ double re[kMdBlock], rw[kMdBlock];
   const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  const int c = blockIdx.y;
   const bool ok = i < n;
   double xi = 0, yi = 0, zi = 0;
   if (ok) {
@@ -69,23 +77,24 @@ __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restr
     zi = x[3 * i + 2];
   }
   double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
-  for (int j0 = 0; j0 < n; j0 += kMdBlock) {
+  const int jb = c * chunk, je = min(n, jb + chunk);
+  for (int j0 = jb; j0 < je; j0 += kMdBlock) {
     const int j = j0 + threadIdx.x;
     __syncthreads();
-    if (j < n) {
+    if (j < je) {
       sx[threadIdx.x] = x[3 * j];
       sy[threadIdx.x] = x[3 * j + 1];
       sz[threadIdx.x] = x[3 * j + 2];
     }
     __syncthreads();
-    const int jn = min(kMdBlock, n - j0);
+    const int jn = min(kMdBlock, je - j0);
     if (!ok) continue;
     for (int jj = 0; jj < jn; ++jj) {
       if (j0 + jj == i) continue;
       double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
-      dx -= box.L[0] * rint(dx / box.L[0]);
-      dy -= box.L[1] * rint(dy / box.L[1]);
-      if (!box.slab) dz -= box.L[2] * rint(dz / box.L[2]);
+      dx -= box.L[0] * rint(dx * box.iL[0]);
+      dy -= box.L[1] * rint(dy * box.iL[1]);
+      if (!box.slab) dz -= box.L[2] * rint(dz * box.iL[2]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 >= lj.rc2) continue;
       const double s2 = lj.sig2 / r2, s6 = s2 * s2 * s2;
@@ -96,24 +105,25 @@ __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restr
       e += 0.5 * (4.0 * lj.eps * (s6 * s6 - s6) + lj.shift);
       w += 0.5 * fr * r2;
     }
-    if (box.slab && lj.weps > 0.0 && j0 + kMdBlock >= n) {
-      // walls at z = lo and z = lo + L, once per particle (last tile)
-      const double dlo = zi - box.lo[2], dhi = box.lo[2] + box.L[2] - zi;
-      const double ds[2] = {dlo, dhi};
-      for (int s = 0; s < 2; ++s) {
-        const double d = ds[s];
-        if (d >= lj.wrc) continue;
-        const double sd = lj.wsig / d, s6 = sd * sd * sd * sd * sd * sd;
-        const double fd = 24.0 * lj.weps * (2.0 * s6 * s6 - s6) / d;  // away from the wall
-        fz += s == 0 ? fd : -fd;
-        e += 4.0 * lj.weps * (s6 * s6 - s6) + lj.wshift;
-      }
+  }
+  if (ok && box.slab && lj.weps > 0.0 && c == (int)gridDim.y - 1) {
+    // walls at z = lo and z = lo + L, once per particle (last chunk)
+    const double dlo = zi - box.lo[2], dhi = box.lo[2] + box.L[2] - zi;
+    const double ds[2] = {dlo, dhi};
+    for (int s = 0; s < 2; ++s) {
+      const double d = ds[s];
+      if (d >= lj.wrc) continue;
+      const double sd = lj.wsig / d, s6 = sd * sd * sd * sd * sd * sd;
+      const double fd = 24.0 * lj.weps * (2.0 * s6 * s6 - s6) / d;  // away from the wall
+      fz += s == 0 ? fd : -fd;
+      e += 4.0 * lj.weps * (s6 * s6 - s6) + lj.wshift;
     }
   }
   if (ok) {
-    f[3 * i] += fx;
-    f[3 * i + 1] += fy;
-    f[3 * i + 2] += fz;
+    double* o = fpart + ((long)c * n + i) * 3;
+    o[0] = fx;
+    o[1] = fy;
+    o[2] = fz;
   }
   re[threadIdx.x] = ok ? e : 0.0;
   rw[threadIdx.x] = ok ? w : 0.0;
@@ -126,19 +136,29 @@ __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = re[0];
-    part[2 * blockIdx.x + 1] = rw[0];
+    const int b = c * gridDim.x + blockIdx.x;
+    part[2 * b] = re[0];
+    part[2 * b + 1] = rw[0];
   }
 }
 
-// v += dt/2 F/m (dt = 0: velocities unchanged), and per-block sums of the
-// kinetic energy 1/2 m v^2.
+// F += the LJ partial forces of the nch chunks in chunk order (fpart not
+// NULL), then v += dt/2 F/m (dt = 0: velocities unchanged), and per-block
+// sums of the kinetic energy 1/2 m v^2 (v NULL: 0).
 __global__ __launch_bounds__(kMdBlock) void k_md_kick(int n, double dt, double* __restrict__ v,
-                                                      const double* __restrict__ f, const double* __restrict__ m,
+                                                      double* __restrict__ f, const double* __restrict__ m,
+                                                      const double* __restrict__ fpart, int nch,
                                                       double* __restrict__ part) {
   __shared__ double rk[kMdBlock];
   const int i = blockIdx.x * kMdBlock + threadIdx.x;
   double ke = 0.0;
+  if (i < n && fpart) {
+    for (int k = 0; k < 3; ++k) {
+      double fk = f[3 * i + k];
+      for (int c = 0; c < nch; ++c) fk += fpart[((long)c * n + i) * 3 + k];
+      f[3 * i + k] = fk;
+    }
+  }
   if (i < n && v) {
     const double h = 0.5 * dt / m[i];
     double s = 0.0;
@@ -200,17 +220,17 @@ __global__ __launch_bounds__(kMdBlock) void k_md_scale(int n, double* __restrict
 }
 
 // Thermo row: E_C, E_LJ, E_kin, P (fixed-order sums of the block partials).
-__global__ __launch_bounds__(64) void k_md_thermo(int nblk, const double* __restrict__ lj_part,
+__global__ __launch_bounds__(64) void k_md_thermo(int nblk, int nlj, const double* __restrict__ lj_part,
                                                   const double* __restrict__ ke_part,
                                                   const double* __restrict__ e_coul, double volume, int slab,
                                                   double* __restrict__ row) {
   if (threadIdx.x != 0) return;
   double elj = 0, wlj = 0, ke = 0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = 0; b < nlj; ++b) {
     elj += lj_part[2 * b];
     wlj += lj_part[2 * b + 1];
-    ke += ke_part[b];
   }
+  for (int b = 0; b < nblk; ++b) ke += ke_part[b];
   const double ec = *e_coul;
   row[0] = ec;
   row[1] = elj;
@@ -228,7 +248,9 @@ struct hsma_md {
   hsma::MdBox box{};
   hsma::MdLJ lj{};
   int nblk = 0;
-  double* d_lj_part = nullptr;  // 2 x nblk
+  int ljch = 1, ljchunk = 0;    // LJ source chunks and their size (a multiple of kMdBlock)
+  double* d_lj_part = nullptr;  // 2 x nblk x ljch
+  double* d_ljf = nullptr;      // ljch x n x 3: LJ partial forces by chunk
   double* d_ke_part = nullptr;  // nblk
   double* d_ecoul = nullptr;
   double* d_row = nullptr;      // 4: thermo row when the caller passes none
@@ -246,13 +268,27 @@ namespace {
 void md_begin_step(hsma_md* md, hipStream_t st, double* x, double* v, const double* f, const double* m) {
   const int n = (int)md->n;
   if (md->nh_on) {
-    hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, 0.0, v, f, m,
-                       md->d_ke_part);
+    hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, 0.0, v,
+                       const_cast<double*>(f), m, (const double*)nullptr, 0, md->d_ke_part);
     hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_ke_part,
                        (double*)nullptr, md->d_nh, md->nh);
   }
   hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, x, v, f, m,
                      md->box, md->nh_on ? (const double*)(md->d_nh + 3) : (const double*)nullptr);
+}
+
+// F += F_LJ at x (pairs by source chunks, summed into f by the kick),
+// v += dt/2 F/m (dt = 0: v unchanged, may be NULL), one thermo row.
+void md_lj_kick_thermo(hsma_md* md, hipStream_t st, const double* x, double* v, double* f, const double* m,
+                       double dt, const double* e_coul, double* row) {
+  const int n = (int)md->n;
+  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk, md->ljch), dim3(hsma::kMdBlock), 0, st, n, x, md->box, md->lj,
+                     md->ljchunk, md->d_ljf, md->d_lj_part);
+  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, dt, v, f, m,
+                     (const double*)md->d_ljf, md->ljch, md->d_ke_part);
+  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
+  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, md->nblk * md->ljch,
+                     (const double*)md->d_lj_part, (const double*)md->d_ke_part, e_coul, vol, md->box.slab, row);
 }
 
 // End of a step, once f holds the Coulomb forces at x and d_e_coulomb their
@@ -261,13 +297,7 @@ void md_begin_step(hsma_md* md, hipStream_t st, double* x, double* v, const doub
 void md_end_step(hsma_md* md, hipStream_t st, const double* x, double* v, double* f, const double* m,
                  const double* e_coul, double* row) {
   const int n = (int)md->n;
-  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, x, md->box, md->lj, f,
-                     md->d_lj_part);
-  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, v,
-                     (const double*)f, m, md->d_ke_part);
-  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
-  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
-                     (const double*)md->d_ke_part, e_coul, vol, md->box.slab, row);
+  md_lj_kick_thermo(md, st, x, v, f, m, md->prm.dt, e_coul, row);
   if (md->nh_on) {
     hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, 0, (const double*)nullptr, row, md->d_nh, md->nh);
     hipLaunchKernelGGL(hsma::k_md_scale, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, v, (const double*)md->d_nh);
@@ -280,14 +310,7 @@ hsma_status md_forces(hsma_md* md, hipStream_t st, const double* x, const double
   const int n = (int)md->n;
   hsma_status s = md->plan->dev.run(st, n, x, q, md->d_ecoul, nullptr, f, err);
   if (s != HSMA_OK) return s;
-  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, x, md->box, md->lj, f,
-                     md->d_lj_part);
-  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, 0.0, const_cast<double*>(v),
-                     (const double*)f, m, md->d_ke_part);
-  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
-  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_lj_part,
-                     (const double*)md->d_ke_part, (const double*)md->d_ecoul, vol, md->box.slab,
-                     row ? row : md->d_row);
+  md_lj_kick_thermo(md, st, x, const_cast<double*>(v), f, m, 0.0, md->d_ecoul, row ? row : md->d_row);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     err = std::string("md kernels: ") + hipGetErrorString(e);
@@ -364,6 +387,15 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
     md->lj.wshift = -4.0 * p->wall_epsilon * (w6 * w6 - w6);
   }
   md->nblk = (int)((n + hsma::kMdBlock - 1) / hsma::kMdBlock);
+  for (int k = 0; k < 3; ++k) md->box.iL[k] = 1.0 / L[k];
+  // LJ work: about 1024 blocks of (targets, source chunk) where the system
+  // is small enough, chunks of whole LDS tiles
+  {
+    const int want = std::max(1, std::min(md->nblk, (1024 + md->nblk - 1) / md->nblk));
+    const int per = (int)((n + want - 1) / want);
+    md->ljchunk = (per + hsma::kMdBlock - 1) / hsma::kMdBlock * hsma::kMdBlock;
+    md->ljch = (int)((n + md->ljchunk - 1) / md->ljchunk);
+  }
   // Nose-Hoover: degrees of freedom without the conserved momentum (3D:
   // 3; slab: x and y), thermostat mass nf kT tau^2
   md->nh_on = p->nh_kT > 0;
@@ -374,7 +406,8 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
   md->nh.vol = L[0] * L[1] * L[2];
   if (hipMalloc((void**)&md->d_nh, sizeof(double) * 4) != hipSuccess ||
       hipMemset(md->d_nh, 0, sizeof(double) * 4) != hipSuccess ||
-      hipMalloc((void**)&md->d_lj_part, sizeof(double) * 2 * md->nblk) != hipSuccess ||
+      hipMalloc((void**)&md->d_lj_part, sizeof(double) * 2 * md->nblk * md->ljch) != hipSuccess ||
+      hipMalloc((void**)&md->d_ljf, sizeof(double) * 3 * (size_t)n * md->ljch) != hipSuccess ||
       hipMalloc((void**)&md->d_ke_part, sizeof(double) * md->nblk) != hipSuccess ||
       hipMalloc((void**)&md->d_ecoul, sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&md->d_row, sizeof(double) * 4) != hipSuccess ||
@@ -463,7 +496,7 @@ hsma_status hsma_md_thermostat(hsma_md* md, void* stream, double* d_state) {
 void hsma_md_destroy(hsma_md* md) {
   if (!md) return;
   if (md->recorded) (void)hipEventSynchronize(md->ev);  // after the plan's work on the same stream
-  void* ps[] = {md->d_lj_part, md->d_ke_part, md->d_ecoul, md->d_row, md->d_nh};
+  void* ps[] = {md->d_lj_part, md->d_ljf, md->d_ke_part, md->d_ecoul, md->d_row, md->d_nh};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (md->ev) (void)hipEventDestroy(md->ev);

@@ -356,6 +356,44 @@ def test_md_slab_with_walls_matches_cpu():
     assert dx <= 1e-9 and de <= 1e-10 and dl <= 1e-9
 
 
+def test_nose_hoover_slab_with_walls_matches_cpu():
+    """NVT between the dielectric interfaces (the slab test's 100 ions and
+    walls; Nose-Hoover at kT = 1.5, tau = 0.05, nf = 3n - 2 since the walls
+    take up momentum along z), 15 steps: positions, rows and thermostat
+    state against the numpy integrator with the oracle's slab forces
+    (FP64)."""
+    import torch
+    box = np.array([10.0, 10.0, 8.0])
+    pos, q, v0, m = lattice_system((5, 5, 4), box, 31, z_lo=1.2, z_hi=6.8)
+    kc, kT, tau = 1.5, 1.5, 0.05
+    params = hs.Params(geometry=1, precision=0, p=8, K=200, F=512, lam=1.6, M=6, gamma_up=-0.5, gamma_low=0.3,
+                       nz=40, coulomb_k=kc)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+    nsteps, dt = 15, 0.002
+    th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+    st = torch.zeros(3, dtype=torch.float64, device=dev)
+    with hs.Plan(params, (0, 0, 0), box) as plan, \
+            hs.MD(plan, len(q), dt, wall_epsilon=1.0, wall_sigma=1.0, nh_kT=kT, nh_damping=tau) as md:
+        md.run(x, v, f, qq, mm, nsteps, thermo=th)
+        md.thermostat(st)
+        torch.cuda.synchronize()
+    xg, tg, sg = x.cpu().numpy(), th.cpu().numpy(), st.cpu().numpy()
+
+    def coulomb(xx):
+        r = ohsma.hsma2d(xx, q, np.zeros(3), box, 8, 200, 512, 1.6, 6, -0.5, 0.3, 40)
+        return kc * r.force, kc * r.energy
+
+    xc, vc, rc, nc = cpu_nose_hoover(pos, v0, q, m, box, coulomb, dt, nsteps, kT, tau, slab=True, weps=1.0)
+    dx = min_image_diff(xg, xc, box, axes=2) / box[0]
+    dr = (np.abs(tg - rc) / np.maximum(np.abs(rc).max(0), 1e-12)).max()
+    dn = np.abs(sg - nc[-1]).max() / np.abs(nc[-1]).max()
+    note(f"   slab NVT: positions {dx:.2e} rows {dr:.2e} thermostat {dn:.2e}; xi {nc[-1, 0]:.4f}")
+    assert dx <= 1e-9 and dr <= 1e-9 and dn <= 1e-9
+
+
 def test_coulomb_virial_is_the_energy():
     """The pressure's Coulomb virial W_C = -dE/ds at s = 1 under scaling of
     positions and box together equals E_C (the HSMA energy is homogeneous of
