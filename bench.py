@@ -435,8 +435,9 @@ def md_bench(hs, steps=200, warmup=20, seed=91):
     steps (the Coulomb step is captured into a graph), then `steps` steps
     in one hsma_md_run, timed with HIP events on the driver's stream.
     Reported beside the rate: the mean kinetic temperature of the timed
-    steps and the drift of the extended energy (E_C + E_LJ + E_kin + the
-    thermostat's) over them."""
+    steps, the drift of the extended energy (E_C + E_LJ + E_kin + the
+    thermostat's) over them, and the peaks of the radial distribution
+    functions g_++, g_+- and g_-- over a further 1,000 steps."""
     import numpy as np
     import torch
     rng = np.random.default_rng(seed)
@@ -468,16 +469,36 @@ def md_bench(hs, steps=200, warmup=20, seed=91):
         md.thermostat(s1, stream=stream.cuda_stream)
         stream.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        # radial distribution functions over a further 10 tau, sampled every
+        # 0.2 tau (hsma_md_rdf), as in the paper's accuracy study
+        nbins, rmax, samples = 120, 6.0, 50
+        hist = torch.zeros((3, nbins), dtype=torch.int64, device=dev)
+        for _ in range(samples):
+            md.run(x, v, f, qq, mm, 20, forces_valid=True, stream=stream.cuda_stream)
+            md.rdf(x, qq, rmax, hist, stream=stream.cuda_stream)
+        stream.synchronize()
     t, t0, a, b = th.cpu().numpy(), th0.cpu().numpy(), s0.cpu().numpy(), s1.cpu().numpy()
     nf = 3 * n - 3
     h0 = t0[-1, :3].sum() + a[2]
     h1 = t[-1, :3].sum() + b[2]
+    hc = hist.cpu().numpy().astype(np.float64)
+    dr = rmax / nbins
+    edges = np.arange(nbins + 1) * dr
+    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    npos, nneg = int((q > 0).sum()), int((q < 0).sum())
+    pairs = np.array([npos * (npos - 1) / 2, npos * nneg, nneg * (nneg - 1) / 2])
+    g = hc / (samples * pairs[:, None] * shell[None, :] / L ** 3)
+    centre = edges[:-1] + 0.5 * dr
+    peaks = {name: {"g_max": float(g[c].max()), "r_at_max": float(centre[int(g[c].argmax())])}
+             for c, name in enumerate(("++", "+-", "--"))}
     return {"system": "3D electrolyte, 3,000 ions (+-1), L 25 sigma, Bjerrum length 3.5 sigma, WCA; "
                       "NVT (Nose-Hoover kT 1, damping 0.1 tau), dt 0.01 tau; FP32C p 8",
             "n": n, "steps": steps, "ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
             "mean_kT": float(np.mean(2 * t[:, 2] / nf)),
             "extended_energy_drift_per_step": float((h1 - h0) / steps),
-            "extended_energy": float(h0)}
+            "extended_energy": float(h0),
+            "rdf": {"samples": samples, "every_steps": 20, "r_max": rmax, "bins": nbins, "peaks": peaks,
+                    "g_at_large_r": float(g[1][centre > 5.0].mean())}}
 
 
 def sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms_cells, f64_cells, steps=10):

@@ -110,6 +110,31 @@ hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double*
  * the caller, as for any two calls of one driver.                       */
 hsma_status hsma_md_thermostat(hsma_md* md, void* stream, double* d_state);
 
+/* Structure of a configuration: the observables of the paper's MD runs
+ * (Sec. 4: radial distribution functions of the 3D electrolytes, ion
+ * density profiles between the dielectric interfaces).  Both add counts to
+ * the caller's device histogram (uint64, not cleared: accumulate over
+ * snapshots) with integer atomics, so the counts do not depend on the
+ * order of the work; asynchronous on `stream`.  Errors: INVALID_ARG.
+ *
+ * Pair distances: every pair i < j with both charges nonzero at
+ * minimum-image distance r < r_max goes to bin floor(r / dr), dr = r_max /
+ * nbins, of class 0 (both q > 0), 1 (opposite signs) or 2 (both q < 0);
+ * d_hist holds 3 x nbins counts.  Per periodic axis (x and y; z too in 3D)
+ * d = (x_i - x_j) - L rint((x_i - x_j) * (1 / L)), then r =
+ * sqrt((dx^2 + dy^2) + dz^2), each FP64 operation rounded on its own (no
+ * fused multiply-add), so that a CPU recomputation in this order finds the
+ * same bins.  1 <= nbins <= 4096; 0 < r_max <= half the smallest periodic
+ * box edge.  O(n^2) pair tests, as for the LJ pairs.                    */
+hsma_status hsma_md_rdf(hsma_md* md, void* stream, const double* d_x, const double* d_q, int nbins, double r_max,
+                        unsigned long long* d_hist);
+
+/* Density profile along z: particle i with q_i != 0 goes to bin
+ * floor((z_i - lo_z) / (L_z / nbins)) (clamped to [0, nbins - 1]) of class
+ * 0 (q > 0) or 1 (q < 0); d_hist holds 2 x nbins counts; 1 <= nbins <= 4096. */
+hsma_status hsma_md_zprofile(hsma_md* md, void* stream, const double* d_x, const double* d_q, int nbins,
+                             unsigned long long* d_hist);
+
 void hsma_md_destroy(hsma_md* md);
 
 #ifdef __cplusplus

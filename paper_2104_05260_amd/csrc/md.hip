@@ -219,6 +219,72 @@ __global__ __launch_bounds__(kMdBlock) void k_md_scale(int n, double* __restrict
   for (int k = 0; k < 3; ++k) v[3 * i + k] *= sc;
 }
 
+// Structure of a configuration (the observables of the paper's MD runs).
+// Pair-distance histogram: block (b, c) takes targets b * kMdBlock ... and
+// the sources of chunk c, counts each pair i < j once, into LDS bins, then
+// adds its nonzero bins to the caller's histogram.  Integer atomics: the
+// counts do not depend on the order.  Every FP64 operation that decides a
+// bin is rounded on its own (no contraction), so a CPU recomputation in the
+// same order finds the same bin.
+constexpr int kRdfMaxBins = 4096;
+__global__ __launch_bounds__(kMdBlock) void k_md_rdf(int n, const double* __restrict__ x,
+                                                     const double* __restrict__ q, MdBox box, int chunk,
+                                                     int nbins, double rmax2, double dr,
+                                                     unsigned long long* __restrict__ hist) {
+  extern __shared__ unsigned int bins[];  // 3 x nbins
+  for (int k = threadIdx.x; k < 3 * nbins; k += kMdBlock) bins[k] = 0u;
+  __shared__ double sx[kMdBlock], sy[kMdBlock], sz[kMdBlock], sq[kMdBlock];
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  const bool ok = i < n;
+  double xi = 0, yi = 0, zi = 0, qi = 0;
+  if (ok) {
+    xi = x[3 * i];
+    yi = x[3 * i + 1];
+    zi = x[3 * i + 2];
+    qi = q[i];
+  }
+  const int jb = blockIdx.y * chunk, je = min(n, jb + chunk);
+  for (int j0 = jb; j0 < je; j0 += kMdBlock) {
+    const int j = j0 + threadIdx.x;
+    __syncthreads();
+    if (j < je) {
+      sx[threadIdx.x] = x[3 * j];
+      sy[threadIdx.x] = x[3 * j + 1];
+      sz[threadIdx.x] = x[3 * j + 2];
+      sq[threadIdx.x] = q[j];
+    }
+    __syncthreads();
+    const int jn = min(kMdBlock, je - j0);
+    if (!ok || qi == 0.0) continue;
+    for (int jj = 0; jj < jn; ++jj) {
+      if (j0 + jj <= i || sq[jj] == 0.0) continue;
+      double dx = __dsub_rn(xi, sx[jj]), dy = __dsub_rn(yi, sy[jj]), dz = __dsub_rn(zi, sz[jj]);
+      dx = __dsub_rn(dx, __dmul_rn(box.L[0], rint(__dmul_rn(dx, box.iL[0]))));
+      dy = __dsub_rn(dy, __dmul_rn(box.L[1], rint(__dmul_rn(dy, box.iL[1]))));
+      if (!box.slab) dz = __dsub_rn(dz, __dmul_rn(box.L[2], rint(__dmul_rn(dz, box.iL[2]))));
+      const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+      if (!(r2 < rmax2)) continue;
+      const int b = min(nbins - 1, (int)__ddiv_rn(__dsqrt_rn(r2), dr));
+      const int cls = (qi > 0.0) == (sq[jj] > 0.0) ? (qi > 0.0 ? 0 : 2) : 1;
+      atomicAdd(&bins[cls * nbins + b], 1u);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 3 * nbins; k += kMdBlock)
+    if (bins[k]) atomicAdd(&hist[k], (unsigned long long)bins[k]);
+}
+
+// Density profile along z: bin floor((z - lo_z) / dz), clamped to the
+// range; class 0 (q > 0) or 1 (q < 0).
+__global__ __launch_bounds__(kMdBlock) void k_md_zprofile(int n, const double* __restrict__ x,
+                                                          const double* __restrict__ q, double lo, double dz,
+                                                          int nbins, unsigned long long* __restrict__ hist) {
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  if (i >= n || q[i] == 0.0) return;
+  const int b = max(0, min(nbins - 1, (int)floor(__ddiv_rn(__dsub_rn(x[3 * i + 2], lo), dz))));
+  atomicAdd(&hist[(q[i] > 0.0 ? 0 : 1) * nbins + b], 1ull);
+}
+
 // Thermo row: E_C, E_LJ, E_kin, P (fixed-order sums of the block partials).
 __global__ __launch_bounds__(64) void k_md_thermo(int nblk, int nlj, const double* __restrict__ lj_part,
                                                   const double* __restrict__ ke_part,
@@ -490,6 +556,37 @@ hsma_status hsma_md_thermostat(hsma_md* md, void* stream, double* d_state) {
   if (hipMemcpyAsync(d_state, md->d_nh, sizeof(double) * 3, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
       hipSuccess)
     return hsma::set_last_error(HSMA_ERR_DEVICE, "hipMemcpyAsync failed");
+  return HSMA_OK;
+}
+
+hsma_status hsma_md_rdf(hsma_md* md, void* stream, const double* d_x, const double* d_q, int nbins, double r_max,
+                        unsigned long long* d_hist) {
+  if (!md || !d_x || !d_q || !d_hist) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (nbins < 1 || nbins > hsma::kRdfMaxBins)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "nbins must be in [1, 4096]");
+  const double half = 0.5 * std::min(md->box.L[0], std::min(md->box.L[1], md->box.slab ? INFINITY : md->box.L[2]));
+  if (!(r_max > 0) || !(r_max <= half))
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "r_max must be in (0, half the smallest periodic box edge]");
+  const int n = (int)md->n;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(hsma::k_md_rdf, dim3(md->nblk, md->ljch), dim3(hsma::kMdBlock),
+                     sizeof(unsigned int) * 3 * (size_t)nbins, st, n, d_x, d_q, md->box, md->ljchunk, nbins,
+                     r_max * r_max, r_max / nbins, d_hist);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
+  return HSMA_OK;
+}
+
+hsma_status hsma_md_zprofile(hsma_md* md, void* stream, const double* d_x, const double* d_q, int nbins,
+                             unsigned long long* d_hist) {
+  if (!md || !d_x || !d_q || !d_hist) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (nbins < 1 || nbins > hsma::kRdfMaxBins)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "nbins must be in [1, 4096]");
+  const int n = (int)md->n;
+  hipLaunchKernelGGL(hsma::k_md_zprofile, dim3(md->nblk), dim3(hsma::kMdBlock), 0, (hipStream_t)stream, n, d_x, d_q,
+                     md->box.lo[2], md->box.L[2] / nbins, nbins, d_hist);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
   return HSMA_OK;
 }
 

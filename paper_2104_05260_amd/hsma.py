@@ -193,8 +193,10 @@ def load_library():
     lib.hsma_md_drift.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.hsma_md_finish.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hsma_md_thermostat.argtypes = [vp, vp, vp]
+    lib.hsma_md_rdf.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp]
+    lib.hsma_md_zprofile.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
     for name in ("hsma_md_create", "hsma_md_run", "hsma_md_forces", "hsma_md_create_for_box", "hsma_md_drift",
-                 "hsma_md_finish", "hsma_md_thermostat"):
+                 "hsma_md_finish", "hsma_md_thermostat", "hsma_md_rdf", "hsma_md_zprofile"):
         getattr(lib, name).restype = ctypes.c_int
     lib.hsma_server_get_stats.restype = ctypes.c_int
     lib.hsma_server_destroy.argtypes = [vp]
@@ -556,6 +558,36 @@ class MD:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         _check(self._lib.hsma_md_thermostat(self._m, ctypes.c_void_p(stream), self._ptr(state)))
+
+    @staticmethod
+    def _hist_ptr(t):
+        import torch
+        if t.dtype != torch.int64 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("histograms must be contiguous int64 GPU tensors")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def rdf(self, x, q, r_max: float, hist, stream=None):
+        """Adds the pair-distance counts of configuration x to `hist`, an
+        int64 GPU tensor of shape (3, nbins): classes (+,+), (+,-), (-,-)
+        (hsma_md_rdf)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        if hist.dim() != 2 or hist.shape[0] != 3:
+            raise ValueError("hist must have shape (3, nbins)")
+        _check(self._lib.hsma_md_rdf(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(q),
+                                     int(hist.shape[1]), float(r_max), self._hist_ptr(hist)))
+
+    def zprofile(self, x, q, hist, stream=None):
+        """Adds the z-density counts of configuration x to `hist`, an int64
+        GPU tensor of shape (2, nbins): q > 0 and q < 0 (hsma_md_zprofile)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        if hist.dim() != 2 or hist.shape[0] != 2:
+            raise ValueError("hist must have shape (2, nbins)")
+        _check(self._lib.hsma_md_zprofile(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(q),
+                                          int(hist.shape[1]), self._hist_ptr(hist)))
 
     def close(self):
         if self._m:

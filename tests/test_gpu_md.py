@@ -394,6 +394,100 @@ def test_nose_hoover_slab_with_walls_matches_cpu():
     assert dx <= 1e-9 and dr <= 1e-9 and dn <= 1e-9
 
 
+def rdf_numpy(x, q, box, nbins, rmax, slab):
+    """Pair-distance counts by the definition: every pair i < j with both
+    charges nonzero, minimum image along the periodic axes, bin floor(r /
+    dr); each FP64 operation rounded on its own in the order the library
+    states (numpy evaluates one operation at a time)."""
+    n = len(x)
+    i, j = np.triu_indices(n, 1)
+    keep = (q[i] != 0) & (q[j] != 0)
+    i, j = i[keep], j[keep]
+    d = []
+    for k in range(3):
+        dk = x[i, k] - x[j, k]
+        if k < 2 or not slab:
+            dk = dk - box[k] * np.rint(dk * (1.0 / box[k]))
+        d.append(dk)
+    r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+    m = r2 < rmax * rmax
+    b = np.minimum(nbins - 1, (np.sqrt(r2[m]) / (rmax / nbins)).astype(np.int64))
+    qi, qj = q[i][m], q[j][m]
+    cls = np.where((qi > 0) == (qj > 0), np.where(qi > 0, 0, 2), 1)
+    h = np.zeros((3, nbins), np.int64)
+    np.add.at(h, (cls, b), 1)
+    return h
+
+
+@pytest.mark.parametrize("slab", [False, True])
+def test_rdf_and_zprofile_counts_exact(slab):
+    """Pair-distance and z-density counts on 700 ions (three target blocks,
+    three source chunks, a ragged end; charges +-1, +2 and some zero) with
+    r_max at half the box edge: equal, count for count, to the definition
+    evaluated in numpy; and accumulated over two calls."""
+    import torch
+    rng = np.random.default_rng(5)
+    box = np.array([9.0, 11.0, 8.0])
+    n = 700
+    x = rng.uniform(0, 1, (n, 3)) * box
+    if slab:
+        x[:, 2] = 0.5 + rng.uniform(0, 1, n) * (box[2] - 1.0)
+    q = rng.choice([1.0, -1.0, 2.0, 0.0], n, p=[0.45, 0.4, 0.1, 0.05])
+    dev = torch.device("cuda:0")
+    xt, qt = torch.tensor(x, device=dev), torch.tensor(q, device=dev)
+    nbins, rmax = 300, 4.0  # half the smallest periodic edge in 3D (L_z = 8)
+    h = torch.zeros((3, nbins), dtype=torch.int64, device=dev)
+    zh = torch.zeros((2, 64), dtype=torch.int64, device=dev)
+    with hs.MD(None, n, 0.001, geometry=hs.GEOM_2D if slab else hs.GEOM_3D, box_lo=(0, 0, 0), box_len=box) as md:
+        md.rdf(xt, qt, rmax, h)
+        md.rdf(xt, qt, rmax, h)
+        md.zprofile(xt, qt, zh)
+        with pytest.raises(hs.HSMAError):
+            md.rdf(xt, qt, 4.6, h)  # beyond half the smallest periodic edge (3D: 4; slab: 4.5)
+        torch.cuda.synchronize()
+    ref = rdf_numpy(x, q, box, nbins, rmax, slab)
+    hg = h.cpu().numpy()
+    zref = np.zeros((2, 64), np.int64)
+    zb = np.clip(np.floor((x[:, 2] - 0.0) / (box[2] / 64)).astype(np.int64), 0, 63)
+    for c, sel in enumerate((q > 0, q < 0)):
+        np.add.at(zref[c], zb[sel], 1)
+    note(f"   slab={slab}: {ref.sum()} pairs within r_max; classes {ref.sum(1).tolist()}")
+    assert np.array_equal(hg, 2 * ref)
+    assert np.array_equal(zh.cpu().numpy(), zref)
+
+
+def test_electrolyte_rdf_contacts():
+    """The 216-ion melt of the trajectory test (Bjerrum length 2), thermostatted
+    at kT = 1 for 1,000 steps and sampled every 50: unlike charges are in
+    contact more often than like ones (pair-normalised counts below 1.3
+    sigma; measured 1.65 times as often in this dense melt, asserted with a
+    margin of 1.25 over the sampling noise of about 3 percent), and every
+    count stays within its pair total."""
+    import torch
+    box = np.array([7.0, 7.0, 7.0])
+    pos, q, v0, m = lattice_system((6, 6, 6), box, 11, jitter=0.05)
+    params = hs.Params(precision=1, p=8, K=162, F=512, lam=1.5, coulomb_k=2.0)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+    nbins, rmax = 70, 3.5
+    h = torch.zeros((3, nbins), dtype=torch.int64, device=dev)
+    with hs.Plan(params, (0, 0, 0), box) as plan, hs.MD(plan, len(q), 0.005, nh_kT=1.0, nh_damping=0.1) as md:
+        md.run(x, v, f, qq, mm, 200, forces_valid=False)
+        for _ in range(16):
+            md.run(x, v, f, qq, mm, 50, forces_valid=True)
+            md.rdf(x, qq, rmax, h)
+        torch.cuda.synchronize()
+    hc = h.cpu().numpy()
+    npos, nneg = int((q > 0).sum()), int((q < 0).sum())
+    pairs = np.array([npos * (npos - 1) / 2, npos * nneg, nneg * (nneg - 1) / 2]) * 16
+    close = hc[:, : int(1.3 / (rmax / nbins))].sum(1) / pairs
+    note(f"   contacts per pair below 1.3 sigma: ++ {close[0]:.4f}, +- {close[1]:.4f}, -- {close[2]:.4f}")
+    assert close[1] > 1.25 * max(close[0], close[2])
+    assert (hc.sum(1) <= pairs).all()
+
+
 def test_coulomb_virial_is_the_energy():
     """The pressure's Coulomb virial W_C = -dE/ds at s = 1 under scaling of
     positions and box together equals E_C (the HSMA energy is homogeneous of
