@@ -488,6 +488,39 @@ def test_electrolyte_rdf_contacts():
     assert (hc.sum(1) <= pairs).all()
 
 
+def test_slab_dielectric_depletion():
+    """The paper's slab experiment in miniature (Sec. 4.3: ions between two
+    interfaces with gamma = 0.939 on both sides, WCA walls of sigma 0.5 at
+    the interfaces, Bjerrum length 3.5, NVT): repulsive polarisation
+    depletes the ions near the interfaces.  100 ions in 10 x 10 x 8, 1,000
+    steps of equilibration then 60 z profiles 50 steps apart
+    (hsma_md_zprofile), with gamma = 0.939 and with gamma = 0: fewer ions
+    within 1 sigma of an interface with the images (FP32C, p = 8)."""
+    import torch
+    box = np.array([10.0, 10.0, 8.0])
+    pos, q, v0, m = lattice_system((5, 5, 4), box, 31, z_lo=1.2, z_hi=6.8)
+    dev = torch.device("cuda:0")
+    near = {}
+    for g in (0.939, 0.0):
+        params = hs.Params(geometry=1, precision=1, p=8, K=200, F=512, lam=1.6, M=6, gamma_up=g, gamma_low=g,
+                           nz=40, coulomb_k=3.5)
+        x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+        f = torch.zeros_like(x)
+        qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+        zh = torch.zeros((2, 16), dtype=torch.int64, device=dev)  # bins of 0.5 sigma
+        with hs.Plan(params, (0, 0, 0), box) as plan, \
+                hs.MD(plan, len(q), 0.005, wall_epsilon=1.0, wall_sigma=0.5, nh_kT=1.0, nh_damping=0.05) as md:
+            md.run(x, v, f, qq, mm, 1000, forces_valid=False)
+            for _ in range(60):
+                md.run(x, v, f, qq, mm, 50, forces_valid=True)
+                md.zprofile(x, qq, zh)
+            torch.cuda.synchronize()
+        h = zh.cpu().numpy().sum(0)
+        near[g] = (h[:2].sum() + h[-2:].sum()) / h.sum()
+        note(f"   gamma {g}: profile {h.tolist()}; fraction within 1 sigma of an interface {near[g]:.4f}")
+    assert near[0.939] < 0.8 * near[0.0]
+
+
 def test_coulomb_virial_is_the_energy():
     """The pressure's Coulomb virial W_C = -dE/ds at s = 1 under scaling of
     positions and box together equals E_C (the HSMA energy is homogeneous of
