@@ -101,6 +101,13 @@ hsma_status hsma_md_drift(hsma_md* md, void* stream, double* d_x, double* d_v, c
 hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double* d_v, double* d_f,
                            const double* d_m, const double* d_e_coulomb, double* d_thermo_row);
 
+/* Forces at the start of a run for a driver without a plan: once d_f
+ * holds the Coulomb forces at d_x and d_e_coulomb their energy, F += F_LJ
+ * and one thermo row (E_kin from d_v, which may be NULL: 0), with no kick
+ * and no thermostat (what hsma_md_forces does after the plan's step).   */
+hsma_status hsma_md_short_range(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
+                                const double* d_m, const double* d_e_coulomb, double* d_thermo_row);
+
 /* Thermostat state after the driver's last enqueued call, copied on
  * `stream` (which first waits for that call) into d_state (3 device
  * doubles): xi (thermostat velocity), eta (its position) and its energy

@@ -512,6 +512,19 @@ hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double*
   return HSMA_OK;
 }
 
+hsma_status hsma_md_short_range(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
+                                const double* d_m, const double* d_e_coulomb, double* d_thermo_row) {
+  if (!md || !d_x || !d_f || !d_m || !d_e_coulomb) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  md_lj_kick_thermo(md, st, d_x, const_cast<double*>(d_v), d_f, d_m, 0.0, d_e_coulomb,
+                    d_thermo_row ? d_thermo_row : md->d_row);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
+  if (hipEventRecord(md->ev, st) != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, "hipEventRecord failed");
+  md->recorded = true;
+  return HSMA_OK;
+}
+
 hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const double* d_v, double* d_f,
                            const double* d_q, const double* d_m, double* d_thermo_row) {
   if (!md || !d_x || !d_f || !d_q || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");

@@ -193,10 +193,11 @@ def load_library():
     lib.hsma_md_drift.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.hsma_md_finish.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hsma_md_thermostat.argtypes = [vp, vp, vp]
+    lib.hsma_md_short_range.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hsma_md_rdf.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp]
     lib.hsma_md_zprofile.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
     for name in ("hsma_md_create", "hsma_md_run", "hsma_md_forces", "hsma_md_create_for_box", "hsma_md_drift",
-                 "hsma_md_finish", "hsma_md_thermostat", "hsma_md_rdf", "hsma_md_zprofile"):
+                 "hsma_md_finish", "hsma_md_thermostat", "hsma_md_rdf", "hsma_md_zprofile", "hsma_md_short_range"):
         getattr(lib, name).restype = ctypes.c_int
     lib.hsma_server_get_stats.restype = ctypes.c_int
     lib.hsma_server_destroy.argtypes = [vp]
@@ -551,6 +552,17 @@ class MD:
         _check(self._lib.hsma_md_finish(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v), self._ptr(f),
                                         self._ptr(m), self._ptr(e_coulomb), self._ptr(thermo_row)))
 
+    def short_range(self, x, v, f, m, e_coulomb, thermo_row=None, stream=None):
+        """F += F_LJ at x and one thermo row, no kick, no thermostat: the
+        start of a run whose Coulomb forces came from elsewhere
+        (hsma_md_short_range)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(self._lib.hsma_md_short_range(self._m, ctypes.c_void_p(stream), self._ptr(x), self._ptr(v),
+                                             self._ptr(f), self._ptr(m), self._ptr(e_coulomb),
+                                             self._ptr(thermo_row)))
+
     def thermostat(self, state, stream=None):
         """Copies the thermostat's (xi, eta, energy) into `state`, a float64
         GPU tensor of 3 entries (hsma_md_thermostat)."""
@@ -645,7 +657,7 @@ class ReplicaEnsemble:
         if self.first:
             res = self._coulomb()  # forces at the starting positions
             for r in self.reps:
-                r["md"].finish(r["x"], torch_zero_v(r), r["f"], r["m"], r["e"])
+                r["md"].short_range(r["x"], r["v"], r["f"], r["m"], r["e"])
             self.first = False
         for r in self.reps:
             r["md"].drift(r["x"], r["v"], r["f"], r["m"])
@@ -657,13 +669,3 @@ class ReplicaEnsemble:
     def close(self):
         for r in self.reps:
             r["md"].close()
-
-
-def torch_zero_v(r):
-    """Zero velocities of a replica's shape (the first force evaluation adds
-    the LJ forces without a kick: dt/2 F/m on zero velocities is discarded)."""
-    import torch
-    if "_z" not in r:
-        r["_z"] = torch.zeros_like(r["v"])
-    r["_z"].zero_()
-    return r["_z"]

@@ -551,13 +551,16 @@ def test_coulomb_virial_is_the_energy():
     assert abs(r[0] - e1) <= 1e-10 * abs(e1) and abs(r[3] - p_ref) <= 1e-10 * abs(p_ref)
 
 
-def test_replica_ensemble_on_the_server():
+@pytest.mark.parametrize("nh", [False, True])
+def test_replica_ensemble_on_the_server(nh):
     """Four MD replicas on the serving loop (device-resident state, Coulomb
     forces by device requests with system ids, drift and finish on the
-    device): trajectories and thermo rows equal each replica integrated by
-    its own plan to 1e-9 (FP64; the server re-targets a unit-box plan), and
-    the replicas' steps are replayed from captured graphs."""
+    device; NVE, or NVT with a Nose-Hoover thermostat per replica):
+    trajectories and thermo rows equal each replica integrated by its own
+    plan to 1e-9 (FP64; the server re-targets a unit-box plan), and the
+    replicas' steps are replayed from captured graphs."""
     import torch
+    th_kw = dict(nh_kT=1.5, nh_damping=0.05) if nh else {}
     dev = torch.device("cuda:0")
     prm = hs.Params(precision=0, p=8, K=162, F=512, lam=1.5)
     reps, refs = [], []
@@ -572,12 +575,12 @@ def test_replica_ensemble_on_the_server():
         x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
         f = torch.zeros_like(x)
         th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
-        with hs.Plan(prm, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt) as md:
+        with hs.Plan(prm, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt, **th_kw) as md:
             md.run(x, v, f, torch.tensor(q, device=dev), torch.tensor(m, device=dev), nsteps, thermo=th)
             torch.cuda.synchronize()
         refs.append((x.cpu().numpy(), th.cpu().numpy(), box))
     with hs.Server(prm, (1.0, 1.0, 1.0), max_n=216, max_slots=4) as sv:
-        ens = hs.ReplicaEnsemble(sv, reps, dt)
+        ens = hs.ReplicaEnsemble(sv, reps, dt, **th_kw)
         rows = [[torch.zeros(4, dtype=torch.float64, device=dev) for _ in reps] for _ in range(nsteps)]
         for s in range(nsteps):
             res = ens.step(rows[s])
