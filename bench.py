@@ -771,13 +771,19 @@ def main():
     progress(f"timed: {ms:.3f} ms per step")
     if not args.no_fp64:
         progress("FP64 path on the same system")
-        out["fp64_gpu"], _, _ = fp64_leg(hs, w, lo, L, x, qq, en, pot, f, e32, f32, ms, stream)
+        out["fp64_gpu"], e64_large, f64_large = fp64_leg(hs, w, lo, L, x, qq, en, pot, f, e32, f32, ms, stream)
         progress(f"fp64: rel energy err {out['fp64_gpu']['rel_energy_err']:.2e}")
     if not args.no_tree:
         progress("treecode on the same system")
         params = hs.Params.from_workload(w, precision=hs.FP32C)
         params.near_rule = 2
-        out["tree_near_set_large"] = tree_entry(hs, params, w, lo, L, x, qq, en, pot, f, stream, ms, 5)
+        out["tree_near_set_large"] = tree_entry(hs, params, w, lo, L, x, qq, en, pot, f, stream, ms, 5,
+                                                None if args.no_fp64 else e64_large,
+                                                None if args.no_fp64 else f64_large)
+    if not args.no_sphere_rule:
+        progress("sphere near set on the same system")
+        out["sphere_near_set_large"] = sphere_rule_bench(hs, w, pos, q, lo, L, x, qq, en, pot, f, stream, ms,
+                                                         None if args.no_fp64 else f64_large, steps=2)
     del x, qq, pot, f
     torch.cuda.empty_cache()
     if not args.no_secondary:
