@@ -63,6 +63,7 @@ struct Work {
 // order, round-robin to nnear waves per group, which write slots
 // nch .. nch + nnear - 1.
 constexpr int kMaxNearSplit = 64;
+constexpr int kMaxFarChunks = 256;  // far chunks per group at most (partial slots per target)
 constexpr int kNearWaves = 8192;  // near-pass waves per launch (about, when there are enough candidates)
 struct PartSched {
   int n, ngroups, ndesc, F, nch, chunk, nnear;

@@ -2220,7 +2220,15 @@ static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree, int 
   const int ntiles = (int)((n + kTile - 1) / kTile);
   ps.ndesc = ndesc;
   ps.F = ndesc * ntiles;
+  // many short chunks: the blocks in flight then read the same few source
+  // tiles at about the same time (cache reuse) and the last round of blocks
+  // is a small share of the launch.  Measured against a target of 32,768
+  // waves (50,000 ions: 42 chunks per group; 999,999 ions: 3): 50,000 ions
+  // 21.9 -> 20.4 ms (saturated from about 170 chunks on), the slab 39.0 ->
+  // 37.7 ms, 999,999 ions 8.24 -> 7.87 s (34 chunks).  At most
+  // kMaxFarChunks per group bounds the partial slots each target writes.
   long long want = std::max<long long>(1, (target + (long long)ps.ngroups - 1) / ps.ngroups);
+  want = std::min<long long>(want, kMaxFarChunks);
   // at least 4 tiles per chunk while that leaves 4096 far waves, else at
   // least 2 (fewer partial slots to write and to sum)
   const long long cap4 = std::max<long long>(1, ps.F / 4);
@@ -2278,11 +2286,11 @@ void DevicePlan::capacity_bounds(int64_t n, size_t& part_bytes, size_t& cpart_by
   // every size (see sphere_chunk)
   const size_t sph = 1024 + (size_t)ngroups * ((size_t)host.prm.F / kSphereChunkMax + 2);
   const size_t ncg = host.check_groups.size();
-  // far slots <= part_target + ngroups; near slots <= min(kMaxNearSplit
-  // ngroups, near_target + ngroups)
+  // far slots <= min(part_target + ngroups, kMaxFarChunks ngroups); near
+  // slots <= min(kMaxNearSplit ngroups, near_target + ngroups)
   const size_t nearb = std::min<size_t>((size_t)kMaxNearSplit * ngroups, (size_t)near_target + ngroups);
   // far slots: treecode one per image entry and group
-  const size_t farb = std::max<size_t>((size_t)part_target + ngroups,
+  const size_t farb = std::max<size_t>(std::min<size_t>((size_t)part_target + ngroups, (size_t)kMaxFarChunks * ngroups),
                                        host.prm.near_rule == 2 ? tree_target + host.desc_particles.size() * ngroups : 0);
   part_bytes = rb * 5 * (size_t)kGroup * (farb + nearb + sph + 1);
   const size_t rbc = cpart_elem();
