@@ -10,6 +10,11 @@
  *   v += dt/2 F/m;  x += dt v (wrapped along the periodic axes);
  *   F = F_Coulomb (the plan's step, F_i = q_i E_i) + F_LJ (pairs, walls);
  *   v += dt/2 F/m;  thermo row.
+ * With respa_inner = k >= 2 a step of dt is: v += dt/2 F_C/m; k times
+ * { v += dt/(2k) F_LJ/m; x += dt/k v; F_LJ at x; v += dt/(2k) F_LJ/m };
+ * F_C at x; v += dt/2 F_C/m; thermo row (F_C: the plan's Coulomb forces,
+ * F_LJ: pairs and walls).  The driver keeps the two force parts between
+ * its calls (forces_valid = 1 reuses them after its own last run).
  * With the Nose-Hoover thermostat (the paper's runs are NVT), half a
  * thermostat step before and after, in the time-reversible splitting:
  *   xi += dt/4 G;  v *= exp(-xi dt/2);  eta += dt/2 xi;  xi += dt/4 G,
@@ -61,6 +66,11 @@ typedef struct hsma_md_params {
                              Sec. 4.1 and 4.3): target kT, with               */
   double nh_damping;    /*   damping time tau (thermostat mass nf kT tau^2, nf =
                              3n - 3, slab 3n - 2); both 0: constant energy (NVE) */
+  int respa_inner;      /* 0 or 1: velocity Verlet.  k >= 2 (at most 1000):
+                             multiple time steps (reversible RESPA, as the
+                             paper's slab runs of Sec. 4.3): the Coulomb forces
+                             act every dt, the short-range forces every dt / k
+                             (hsma_md_run with a plan only)                    */
 } hsma_md_params;
 
 typedef struct hsma_md hsma_md;

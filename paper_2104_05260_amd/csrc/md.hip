@@ -34,8 +34,9 @@ struct MdNH {
 };
 
 // v = s v + dt/2 F/m (s: the thermostat's velocity scale, 1 without one);
-// x += dt v; wrapped into [lo, lo + L) along periodic axes.
-__global__ __launch_bounds__(kMdBlock) void k_md_kick_drift(int n, double dt, double* __restrict__ x,
+// then, when dtx != 0, x += dtx v, wrapped into [lo, lo + L) along
+// periodic axes.
+__global__ __launch_bounds__(kMdBlock) void k_md_kick_drift(int n, double dt, double dtx, double* __restrict__ x,
                                                             double* __restrict__ v, const double* __restrict__ f,
                                                             const double* __restrict__ m, MdBox box,
                                                             const double* __restrict__ scale) {
@@ -46,9 +47,11 @@ __global__ __launch_bounds__(kMdBlock) void k_md_kick_drift(int n, double dt, do
   for (int k = 0; k < 3; ++k) {
     const double vk = sv * v[3 * i + k] + h * f[3 * i + k];
     v[3 * i + k] = vk;
-    double xk = x[3 * i + k] + dt * vk;
-    if (k < 2 || !box.slab) xk -= box.L[k] * floor((xk - box.lo[k]) / box.L[k]);
-    x[3 * i + k] = xk;
+    if (dtx != 0.0) {
+      double xk = x[3 * i + k] + dtx * vk;
+      if (k < 2 || !box.slab) xk -= box.L[k] * floor((xk - box.lo[k]) / box.L[k]);
+      x[3 * i + k] = xk;
+    }
   }
 }
 
@@ -211,6 +214,27 @@ __global__ __launch_bounds__(64) void k_md_nh(int nblk, const double* __restrict
   }
 }
 
+// out = the LJ partial forces of the nch chunks summed in chunk order
+// (multiple time steps keep the short-range forces on their own).
+__global__ __launch_bounds__(kMdBlock) void k_md_lj_sum(int n, int nch, const double* __restrict__ fpart,
+                                                        double* __restrict__ out) {
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) {
+    double fk = 0.0;
+    for (int c = 0; c < nch; ++c) fk += fpart[((long)c * n + i) * 3 + k];
+    out[3 * i + k] = fk;
+  }
+}
+
+// f = a + b (the caller's total force after a multiple-time-step run).
+__global__ __launch_bounds__(kMdBlock) void k_md_add(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                     double* __restrict__ f) {
+  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) f[3 * i + k] = a[3 * i + k] + b[3 * i + k];
+}
+
 // v *= s (the end-of-step thermostat scale).
 __global__ __launch_bounds__(kMdBlock) void k_md_scale(int n, double* __restrict__ v, const double* __restrict__ nh) {
   const int i = blockIdx.x * kMdBlock + threadIdx.x;
@@ -321,6 +345,9 @@ struct hsma_md {
   double* d_ecoul = nullptr;
   double* d_row = nullptr;      // 4: thermo row when the caller passes none
   double* d_nh = nullptr;       // 4: thermostat state {xi, eta, E_thermostat, scale}
+  double* d_fc = nullptr;       // multiple time steps: Coulomb forces, n x 3
+  double* d_flj = nullptr;      //   and short-range forces, n x 3, at the current positions
+  bool split_valid = false;     //   (left by this driver's last run or forces call)
   bool nh_on = false;
   hsma::MdNH nh{};
   hipEvent_t ev = nullptr;      // end of the driver's last call (its kernels follow the plan's)
@@ -339,7 +366,8 @@ void md_begin_step(hsma_md* md, hipStream_t st, double* x, double* v, const doub
     hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_ke_part,
                        (double*)nullptr, md->d_nh, md->nh);
   }
-  hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, x, v, f, m,
+  hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->prm.dt, md->prm.dt, x,
+                     v, f, m,
                      md->box, md->nh_on ? (const double*)(md->d_nh + 3) : (const double*)nullptr);
 }
 
@@ -370,10 +398,88 @@ void md_end_step(hsma_md* md, hipStream_t st, const double* x, double* v, double
   }
 }
 
+// F_LJ at x into d_flj (pairs by source chunks, the chunks summed in order).
+void md_short_range_split(hsma_md* md, hipStream_t st, const double* x) {
+  const int n = (int)md->n;
+  hipLaunchKernelGGL(hsma::k_md_lj, dim3(md->nblk, md->ljch), dim3(hsma::kMdBlock), 0, st, n, x, md->box, md->lj,
+                     md->ljchunk, md->d_ljf, md->d_lj_part);
+  hipLaunchKernelGGL(hsma::k_md_lj_sum, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, md->ljch,
+                     (const double*)md->d_ljf, md->d_flj);
+}
+
+// v += dt/2 F/m (dt = 0: v unchanged, may be NULL) with the per-block kinetic
+// energies, then the thermo row from the last LJ evaluation and E_C.
+void md_kick_thermo(hsma_md* md, hipStream_t st, double* v, const double* f, const double* m, double dt,
+                    const double* e_coul, double* row) {
+  const int n = (int)md->n;
+  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, dt, v, const_cast<double*>(f), m,
+                     (const double*)nullptr, 0, md->d_ke_part);
+  const double vol = md->box.L[0] * md->box.L[1] * md->box.L[2];
+  hipLaunchKernelGGL(hsma::k_md_thermo, dim3(1), dim3(64), 0, st, md->nblk, md->nblk * md->ljch,
+                     (const double*)md->d_lj_part, (const double*)md->d_ke_part, e_coul, vol, md->box.slab, row);
+}
+
+// One outer step of the multiple-time-step (reversible RESPA) integrator:
+// the Coulomb forces kick for dt/2 at both ends of the outer step, and in
+// between respa_inner velocity-Verlet steps of dt / respa_inner move the
+// particles under the short-range forces alone; the thermostat's halves
+// wrap the outer step.  d_fc and d_flj hold the forces at x on entry and
+// on exit.
+hsma_status md_respa_step(hsma_md* md, hipStream_t st, double* x, double* v, const double* q, const double* m,
+                          double* row, std::string& err) {
+  const int n = (int)md->n;
+  const int k = md->prm.respa_inner;
+  const double dt = md->prm.dt, dti = dt / k;
+  if (md->nh_on) {
+    hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, 0.0, v, md->d_fc, m,
+                       (const double*)nullptr, 0, md->d_ke_part);
+    hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, md->nblk, (const double*)md->d_ke_part,
+                       (double*)nullptr, md->d_nh, md->nh);
+  }
+  // v = s v + dt/2 F_C/m
+  hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, dt, 0.0, x, v,
+                     (const double*)md->d_fc, m, md->box, md->nh_on ? (const double*)(md->d_nh + 3) : (const double*)nullptr);
+  for (int j = 0; j < k; ++j) {
+    hipLaunchKernelGGL(hsma::k_md_kick_drift, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, dti, dti, x, v,
+                       (const double*)md->d_flj, m, md->box, (const double*)nullptr);
+    md_short_range_split(md, st, x);
+    if (j + 1 < k)
+      hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, dti, v, md->d_flj, m,
+                         (const double*)nullptr, 0, md->d_ke_part);
+  }
+  // the last inner closing kick, then the Coulomb forces at the new x
+  hipLaunchKernelGGL(hsma::k_md_kick, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, dti, v, md->d_flj, m,
+                     (const double*)nullptr, 0, md->d_ke_part);
+  hsma_status s = md->plan->dev.run(st, n, x, q, md->d_ecoul, nullptr, md->d_fc, err);
+  if (s != HSMA_OK) return s;
+  md_kick_thermo(md, st, v, md->d_fc, m, dt, md->d_ecoul, row);
+  if (md->nh_on) {
+    hipLaunchKernelGGL(hsma::k_md_nh, dim3(1), dim3(64), 0, st, 0, (const double*)nullptr, row, md->d_nh, md->nh);
+    hipLaunchKernelGGL(hsma::k_md_scale, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, v, (const double*)md->d_nh);
+  }
+  return HSMA_OK;
+}
+
 // F = F_Coulomb (the plan's step) + F_LJ at x; one thermo row (E_kin from v).
+// With multiple time steps the two parts are also kept apart (d_fc, d_flj).
 hsma_status md_forces(hsma_md* md, hipStream_t st, const double* x, const double* v, double* f, const double* q,
                       const double* m, double* row, std::string& err) {
   const int n = (int)md->n;
+  if (md->prm.respa_inner >= 2) {
+    hsma_status s = md->plan->dev.run(st, n, x, q, md->d_ecoul, nullptr, md->d_fc, err);
+    if (s != HSMA_OK) return s;
+    md_short_range_split(md, st, x);
+    md_kick_thermo(md, st, const_cast<double*>(v), md->d_flj, m, 0.0, md->d_ecoul, row ? row : md->d_row);
+    hipLaunchKernelGGL(hsma::k_md_add, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, (const double*)md->d_fc,
+                       (const double*)md->d_flj, f);
+    md->split_valid = true;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      err = std::string("md kernels: ") + hipGetErrorString(e);
+      return HSMA_ERR_DEVICE;
+    }
+    return HSMA_OK;
+  }
   hsma_status s = md->plan->dev.run(st, n, x, q, md->d_ecoul, nullptr, f, err);
   if (s != HSMA_OK) return s;
   md_lj_kick_thermo(md, st, x, const_cast<double*>(v), f, m, 0.0, md->d_ecoul, row ? row : md->d_row);
@@ -424,8 +530,10 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
   if (!(p->dt > 0) || !std::isfinite(p->dt) || !(p->lj_epsilon >= 0) || !(p->lj_sigma > 0) || !(p->lj_rcut >= 0) ||
       !(p->wall_epsilon >= 0) || !(p->wall_rcut >= 0) || (p->wall_epsilon > 0 && !(p->wall_sigma > 0)) ||
       !(p->nh_kT >= 0) || !(p->nh_damping >= 0) || !std::isfinite(p->nh_kT) || !std::isfinite(p->nh_damping) ||
-      ((p->nh_kT > 0) != (p->nh_damping > 0)))
+      ((p->nh_kT > 0) != (p->nh_damping > 0)) || p->respa_inner < 0 || p->respa_inner > 1000)
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "invalid MD parameter");
+  if (!plan && p->respa_inner >= 2)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "multiple time steps need a plan (hsma_md_run)");
   std::unique_ptr<hsma_md> md(new (std::nothrow) hsma_md());
   if (!md) return hsma::set_last_error(HSMA_ERR_OOM, "host allocation failed");
   md->plan = plan;
@@ -477,6 +585,8 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
       hipMalloc((void**)&md->d_ke_part, sizeof(double) * md->nblk) != hipSuccess ||
       hipMalloc((void**)&md->d_ecoul, sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&md->d_row, sizeof(double) * 4) != hipSuccess ||
+      (p->respa_inner >= 2 && (hipMalloc((void**)&md->d_fc, sizeof(double) * 3 * (size_t)n) != hipSuccess ||
+                               hipMalloc((void**)&md->d_flj, sizeof(double) * 3 * (size_t)n) != hipSuccess)) ||
       hipEventCreateWithFlags(&md->ev, hipEventDisableTiming) != hipSuccess) {
     hsma_md_destroy(md.release());
     return hsma::set_last_error(HSMA_ERR_OOM, "device allocation failed");
@@ -489,6 +599,8 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
 hsma_status hsma_md_drift(hsma_md* md, void* stream, double* d_x, double* d_v, const double* d_f,
                           const double* d_m) {
   if (!md || !d_x || !d_v || !d_f || !d_m) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (md->prm.respa_inner >= 2)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "multiple time steps run through hsma_md_run only");
   md_begin_step(md, (hipStream_t)stream, d_x, d_v, d_f, d_m);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hsma::set_last_error(HSMA_ERR_DEVICE, std::string("md kernels: ") + hipGetErrorString(e));
@@ -503,6 +615,8 @@ hsma_status hsma_md_finish(hsma_md* md, void* stream, const double* d_x, double*
                            const double* d_m, const double* d_e_coulomb, double* d_thermo_row) {
   if (!md || !d_x || !d_v || !d_f || !d_m || !d_e_coulomb)
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
+  if (md->prm.respa_inner >= 2)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "multiple time steps run through hsma_md_run only");
   hipStream_t st = (hipStream_t)stream;
   md_end_step(md, st, d_x, d_v, d_f, d_m, d_e_coulomb, d_thermo_row ? d_thermo_row : md->d_row);
   const hipError_t e = hipGetLastError();
@@ -546,9 +660,22 @@ hsma_status hsma_md_run(hsma_md* md, void* stream, int nsteps, double* d_x, doub
   hipStream_t st = (hipStream_t)stream;
   std::string err;
   hsma_status s;
-  if (!forces_valid && (s = md_forces(md, st, d_x, d_v, d_f, d_q, d_m, nullptr, err)) != HSMA_OK)
+  const bool respa = md->prm.respa_inner >= 2;
+  // multiple time steps need the two force parts, which only this driver's
+  // own last run or forces call leaves
+  if ((!forces_valid || (respa && !md->split_valid)) &&
+      (s = md_forces(md, st, d_x, d_v, d_f, d_q, d_m, nullptr, err)) != HSMA_OK)
     return hsma::set_last_error(s, err);
   const int n = (int)md->n;
+  if (respa) {
+    for (int step = 0; step < nsteps; ++step) {
+      s = md_respa_step(md, st, d_x, d_v, d_q, d_m, d_thermo ? d_thermo + 4 * (size_t)step : md->d_row, err);
+      if (s != HSMA_OK) return hsma::set_last_error(s, err);
+    }
+    hipLaunchKernelGGL(hsma::k_md_add, dim3(md->nblk), dim3(hsma::kMdBlock), 0, st, n, (const double*)md->d_fc,
+                       (const double*)md->d_flj, d_f);
+    nsteps = 0;
+  }
   for (int step = 0; step < nsteps; ++step) {
     md_begin_step(md, st, d_x, d_v, d_f, d_m);
     s = md->plan->dev.run(st, n, d_x, d_q, md->d_ecoul, nullptr, d_f, err);
@@ -606,7 +733,7 @@ hsma_status hsma_md_zprofile(hsma_md* md, void* stream, const double* d_x, const
 void hsma_md_destroy(hsma_md* md) {
   if (!md) return;
   if (md->recorded) (void)hipEventSynchronize(md->ev);  // after the plan's work on the same stream
-  void* ps[] = {md->d_lj_part, md->d_ljf, md->d_ke_part, md->d_ecoul, md->d_row, md->d_nh};
+  void* ps[] = {md->d_lj_part, md->d_ljf, md->d_ke_part, md->d_ecoul, md->d_row, md->d_nh, md->d_fc, md->d_flj};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (md->ev) (void)hipEventDestroy(md->ev);

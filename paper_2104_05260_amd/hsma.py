@@ -86,7 +86,8 @@ class _CResult(ctypes.Structure):
 class _CMDParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("lj_epsilon", ctypes.c_double), ("lj_sigma", ctypes.c_double),
                 ("lj_rcut", ctypes.c_double), ("wall_epsilon", ctypes.c_double), ("wall_sigma", ctypes.c_double),
-                ("wall_rcut", ctypes.c_double), ("nh_kT", ctypes.c_double), ("nh_damping", ctypes.c_double)]
+                ("wall_rcut", ctypes.c_double), ("nh_kT", ctypes.c_double), ("nh_damping", ctypes.c_double),
+                ("respa_inner", ctypes.c_int)]
 
 
 class _CServerStats(ctypes.Structure):
@@ -498,7 +499,8 @@ class MD:
 
     def __init__(self, plan: Optional["Plan"], n: int, dt: float, lj_epsilon: float = 1.0, lj_sigma: float = 1.0,
                  lj_rcut: float = 0.0, wall_epsilon: float = 0.0, wall_sigma: float = 1.0, wall_rcut: float = 0.0,
-                 geometry: int = GEOM_3D, box_lo=None, box_len=None, nh_kT: float = 0.0, nh_damping: float = 0.0):
+                 geometry: int = GEOM_3D, box_lo=None, box_len=None, nh_kT: float = 0.0, nh_damping: float = 0.0,
+                 respa_inner: int = 0):
         """With a plan: hsma_md_create.  With plan None: a driver for the
         box (hsma_md_create_for_box) whose Coulomb forces come from
         elsewhere (drift / finish around a server request)."""
@@ -506,7 +508,8 @@ class MD:
         self._lib = lib
         self._plan = plan  # kept alive: the driver uses it
         self._m = ctypes.c_void_p()
-        p = _CMDParams(dt, lj_epsilon, lj_sigma, lj_rcut, wall_epsilon, wall_sigma, wall_rcut, nh_kT, nh_damping)
+        p = _CMDParams(dt, lj_epsilon, lj_sigma, lj_rcut, wall_epsilon, wall_sigma, wall_rcut, nh_kT, nh_damping,
+                       int(respa_inner))
         if plan is not None:
             _check(lib.hsma_md_create(plan._p, ctypes.byref(p), int(n), ctypes.byref(self._m)))
         else:

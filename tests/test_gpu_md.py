@@ -128,6 +128,41 @@ def cpu_nose_hoover(x, v, q, m, box, coulomb, dt, nsteps, kT, tau, slab=False, w
     return x, v, np.array(rows), np.array(nh)
 
 
+def cpu_respa(x, v, q, m, box, coulomb, dt, k, nsteps, kT=0.0, tau=0.0):
+    """Reversible RESPA on the CPU with the oracle's Coulomb forces: per
+    outer step, Coulomb half kicks of dt/2 around k velocity-Verlet steps of
+    dt/k under the short-range forces, optionally wrapped in the
+    Nose-Hoover halves.  Rows as cpu_nose_hoover's."""
+    x, v = x.copy(), v.copy()
+    n = len(x)
+    nf = 3 * n - 3
+    Q = nf * kT * tau * tau
+    xi = eta = 0.0
+    fc, ec = coulomb(x)
+    fl, el, wl = lj_numpy(x, box, False)
+    rows = []
+    dti = dt / k
+    for _ in range(nsteps):
+        s = 1.0
+        if kT > 0:
+            xi, eta, s = nh_half(xi, eta, 0.5 * (m[:, None] * v * v).sum(), nf, kT, Q, dt)
+        v = s * v + 0.5 * dt * fc / m[:, None]
+        for _ in range(k):
+            v = v + 0.5 * dti * fl / m[:, None]
+            x = x + dti * v
+            x -= box * np.floor(x / box)
+            fl, el, wl = lj_numpy(x, box, False)
+            v = v + 0.5 * dti * fl / m[:, None]
+        fc, ec = coulomb(x)
+        v = v + 0.5 * dt * fc / m[:, None]
+        if kT > 0:
+            xi, eta, s = nh_half(xi, eta, 0.5 * (m[:, None] * v * v).sum(), nf, kT, Q, dt)
+            v = s * v
+        ke = 0.5 * (m[:, None] * v * v).sum()
+        rows.append((ec, el, ke, (2 * ke + wl + ec) / (3 * box.prod())))
+    return x, v, np.array(rows)
+
+
 def min_image_diff(a, b, box, axes=3):
     d = a - b
     for k in range(axes):
@@ -215,6 +250,75 @@ def test_nose_hoover_trajectory_matches_cpu():
          f"E_kin {rc[0, 2]:.3f} -> {rc[-1, 2]:.3f}, xi {nc[-1, 0]:.4f}")
     assert dx <= 1e-9 and dv <= 1e-9 and dr <= 1e-9 and dn <= 1e-9
     assert nc[-1, 0] < 0.0  # colder than the target: the thermostat heats (xi < 0)
+
+
+@pytest.mark.parametrize("nh", [False, True])
+def test_respa_trajectory_matches_cpu(nh):
+    """Multiple time steps (respa_inner = 3: Coulomb forces every 0.006,
+    short-range forces every 0.002), 216 ions, FP64, 10 outer steps, NVE
+    and NVT: positions, velocities and rows against the same integrator on
+    the CPU with the oracle's forces (1e-9); forces_valid = 1 continues
+    from the driver's own force parts."""
+    import torch
+    box = np.array([7.0, 7.0, 7.0])
+    pos, q, v0, m = lattice_system((6, 6, 6), box, 11, jitter=0.05)
+    kc = 2.0
+    params = hs.Params(precision=0, p=8, K=162, F=512, lam=1.5, coulomb_k=kc)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+    nsteps, dt, k = 10, 0.006, 3
+    th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+    kw = dict(nh_kT=1.5, nh_damping=0.05) if nh else {}
+    with hs.Plan(params, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt, respa_inner=k, **kw) as md:
+        md.run(x, v, f, qq, mm, 4, thermo=th[:4])
+        md.run(x, v, f, qq, mm, nsteps - 4, forces_valid=True, thermo=th[4:])
+        torch.cuda.synchronize()
+    xg, vg, tg = x.cpu().numpy(), v.cpu().numpy(), th.cpu().numpy()
+
+    def coulomb(xx):
+        r = ohsma.hsma3d(xx, q, np.zeros(3), box, 8, 162, 512, 1.5)
+        return kc * r.force, kc * r.energy
+
+    xc, vc, rc = cpu_respa(pos, v0, q, m, box, coulomb, dt, k, nsteps, *( (1.5, 0.05) if nh else ()))
+    dx = min_image_diff(xg, xc, box) / box[0]
+    dv = np.abs(vg - vc).max() / np.abs(vc).max()
+    dr = (np.abs(tg - rc) / np.abs(rc).max(0)).max()
+    note(f"   nh={nh}: positions {dx:.2e} velocities {dv:.2e} rows {dr:.2e}")
+    assert dx <= 1e-9 and dv <= 1e-9 and dr <= 1e-9
+
+
+def test_respa_energy_conservation_dt2():
+    """NVE with multiple time steps (3 short-range steps per Coulomb step):
+    the total energy's fluctuation falls like dt^2 when both steps are
+    halved together (FP64, p = 10, the system of the velocity-Verlet test)."""
+    import torch
+    box = np.array([11.0, 11.0, 11.0])
+    pos, q, v0, m = lattice_system((4, 4, 6), box, 21)
+    params = hs.Params(precision=0, p=10, K=242, F=800, lam=1.5, coulomb_k=1.0)
+    dev = torch.device("cuda:0")
+    T, fluct = 0.96, []
+    for dt in (0.012, 0.006):
+        nsteps = int(round(T / dt))
+        x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+        f = torch.zeros_like(x)
+        qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+        th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+        row0 = torch.zeros(4, dtype=torch.float64, device=dev)
+        with hs.Plan(params, (0, 0, 0), box) as plan, hs.MD(plan, len(q), dt, respa_inner=3) as md:
+            md.forces(x, v, f, qq, mm, thermo_row=row0)
+            md.run(x, v, f, qq, mm, nsteps, forces_valid=True, thermo=th)
+            torch.cuda.synchronize()
+        t, r0 = th.cpu().numpy(), row0.cpu().numpy()
+        H0 = r0[0] + r0[1] + r0[2]
+        H = t[:, 0] + t[:, 1] + t[:, 2]
+        fluct.append(np.sqrt(np.mean((H - H0) ** 2)))
+        note(f"   outer dt {dt}: {nsteps} steps, rms(H - H0) {fluct[-1]:.3e} ({fluct[-1] / abs(r0[2]):.2e} of E_kin)")
+    ratio = fluct[0] / fluct[1]
+    note(f"   fluctuation ratio dt / (dt/2): {ratio:.2f}")
+    assert 2.5 <= ratio <= 6.5
+    assert fluct[1] <= 1e-3 * abs(r0[2])
 
 
 def test_md_energy_conservation_dt2():

@@ -78,6 +78,8 @@ def test_plan_parameter_errors(bad, err):
     dict(nh_kT=-1.0, nh_damping=0.1),
     dict(nh_kT=float("nan"), nh_damping=0.1),
     dict(dt=0.0),
+    dict(respa_inner=-1),
+    dict(respa_inner=3),                # multiple time steps need a plan (hsma_md_run)
 ])
 def test_md_parameter_errors(bad):
     """hsma_md_create_for_box rejects inconsistent MD parameters before it
