@@ -1451,6 +1451,135 @@ __device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, fl
   fz = dz0 + 2.f * dz1;  // -d/dz phi
 }
 
+// The same evaluation in FP64 from the FP64 moments (the slab: its 189
+// image entries per target each add the FP32 evaluation's rounding, which
+// on the 20,000-ion slab was about a third of the energy error).
+__device__ __forceinline__ void tree_eval64(const double* __restrict__ M, int P, double X, double Y, double Z, double& phi,
+                                          float& fx, float& fy, float& fz) {
+  const double r2 = X * X + Y * Y + Z * Z;
+  const double ri = 1.0 / sqrt(r2);
+  const double ri2 = ri * ri;
+  const double wr = X * ri2, wi = Y * ri2;
+  const double zr = Z * ri2;
+  // the potential's terms are summed in FP64 (on the 50,000-ion system the
+  // energy error at order 12 went from 1.2e-6 to 4.5e-7 for 1 % of the time)
+  double phi0 = 0.0, phi1 = 0.0;
+  double dz0 = 0.0, dz1 = 0.0, Wr = 0.0, Wi = 0.0;
+  // column m = 0: T_n^0 is real.  Step n: recursion (n >= 1), potential
+  // (n <= P), d/dz (n >= 1), and + M_{n-1}^1 conj(T_n^0) (n >= 2).  The
+  // factors 2n - 1 and (n - 1)^2 and the place in M are carried from step
+  // to step: pv points at M_{n-1}^0, and M_n^0 is 2n reals further.
+  {
+    double p = 0.0, t = ri;
+    auto step0 = [&](const double af, const double bf, const double* __restrict__ row, const double* __restrict__ pv,
+                     auto pot, auto wplus) {
+      const double a = af * zr;
+      const double b = bf * ri2;
+      const double nt = a * t - b * p;
+      p = t;
+      t = nt;
+      if constexpr (decltype(pot)::value) phi0 = fma((double)row[0], (double)t, phi0);  // M_n^0
+      dz0 = fma(pv[0], t, dz0);
+      if constexpr (decltype(wplus)::value) {
+        Wr = fma(pv[2], t, Wr);
+        Wi = fma(pv[3], t, Wi);
+      }
+    };
+    phi0 = fma((double)M[0], (double)t, phi0);  // n = 0
+    step0(1.0, 0.0, M + 2, M, std::true_type{}, std::false_type{});
+    double af = 3.0, bf = 1.0;
+    const double* __restrict__ pv = M + 2;  // M_1^0
+#pragma unroll 1
+    for (int n = 2; n <= P; ++n) {
+      const double* __restrict__ nx = pv + 2 * n;  // M_n^0
+      step0(af, bf, nx, pv, std::true_type{}, std::true_type{});
+      pv = nx;
+      bf += af;
+      af += 2.0;
+    }
+    step0(af, bf, pv, pv, std::false_type{}, std::true_type{});  // n = P + 1
+  }
+  // columns m >= 1.  Step n of column m: recursion (n > m), potential
+  // (n <= P), d/dz (n - 1 >= m), - conj(M_{n-1}^{m-1}) T_n^m (always) and
+  // + M_{n-1}^{m+1} conj(T_n^m) (n - 1 >= m + 1).  The step's factors
+  // 2n - 1 and (n - 1)^2 - m^2 (small integers, exact in FP32) and its
+  // place in M are carried from step to step: pv points at M_{n-1}^{m-1}
+  // (then M_{n-1}^m, M_{n-1}^{m+1}), and M_n^{m-1} is 2n reals further.
+  double sr = ri, si = 0.0;
+  double pr = 0.0, pi = 0.0, tr = 0.0, ti = 0.0;
+  auto stepm = [&](const double af, const double bf, const double* __restrict__ row, const double* __restrict__ pv,
+                   auto rec, auto pot, auto dz, auto wplus) {
+    if constexpr (decltype(rec)::value) {
+      const double a = af * zr;
+      const double b = bf * ri2;
+      const double nr = a * tr - b * pr, ni = a * ti - b * pi;
+      pr = tr;
+      pi = ti;
+      tr = nr;
+      ti = ni;
+    }
+    if constexpr (decltype(pot)::value) {  // row: M_n^m
+      phi1 = fma((double)row[0], (double)tr, phi1);
+      phi1 = fma((double)row[1], (double)ti, phi1);
+    }
+    if constexpr (decltype(dz)::value) {
+      dz1 = fma(pv[2], tr, dz1);
+      dz1 = fma(pv[3], ti, dz1);
+    }
+    Wr = fma(-pv[0], tr, Wr);
+    Wr = fma(-pv[1], ti, Wr);
+    Wi = fma(-pv[0], ti, Wi);
+    Wi = fma(pv[1], tr, Wi);
+    if constexpr (decltype(wplus)::value) {
+      Wr = fma(pv[4], tr, Wr);
+      Wr = fma(pv[5], ti, Wr);
+      Wi = fma(pv[5], tr, Wi);
+      Wi = fma(-pv[4], ti, Wi);
+    }
+  };
+  auto seed = [&](const int m) {
+    const double c = (double)(2 * m - 1);
+    const double nr = c * (wr * sr - wi * si), ni = c * (wr * si + wi * sr);
+    sr = nr;
+    si = ni;
+    pr = 0.0;
+    pi = 0.0;
+    tr = sr;
+    ti = si;
+  };
+  // M_n^m
+  auto at = [&](const int n, const int m) { return M + (n * (n + 1) + 2 * m); };
+  const std::false_type no{};
+  const std::true_type yes{};
+#pragma unroll 1
+  for (int m = 1; m < P; ++m) {
+    seed(m);
+    stepm(0.0, 0.0, at(m, m), at(m - 1, m - 1), no, yes, no, no);
+    stepm((double)(2 * m + 1), 0.0, at(m + 1, m), at(m, m - 1), yes, yes, yes, no);
+    double af = (double)(2 * m + 3), bf = (double)((m + 1) * (m + 1) - m * m);
+    const double* __restrict__ pv = at(m + 1, m - 1);
+#pragma unroll 1
+    for (int n = m + 2; n <= P; ++n) {
+      const double* __restrict__ nx = pv + 2 * n;  // M_n^{m-1}
+      stepm(af, bf, nx + 2, pv, yes, yes, yes, yes);
+      pv = nx;
+      bf += af;
+      af += 2.0;
+    }
+    stepm(af, bf, pv, pv, yes, no, yes, yes);  // n = P + 1
+  }
+  // m = P: steps P and P + 1; m = P + 1: step P + 1 only
+  seed(P);
+  stepm(0.0, 0.0, at(P, P), at(P - 1, P - 1), no, yes, no, no);
+  stepm((double)(2 * P + 1), 0.0, at(P + 1, P), at(P, P - 1), yes, no, yes, no);
+  seed(P + 1);
+  stepm(0.0, 0.0, at(P, P), at(P, P), no, no, no, no);
+  phi = phi0 + 2.0 * phi1;
+  fx = (float)-Wr;
+  fy = (float)-Wi;
+  fz = (float)(dz0 + 2.0 * dz1);  // -d/dz phi
+}
+
 // Near-set sums of the particles by the treecode: wave b takes target
 // group (= tile) b % ngroups and c = b / ngroups, that is image entry
 // c / ps.split and share c % ps.split.  Every wave walks the image's tree
@@ -1467,7 +1596,7 @@ __device__ __forceinline__ void tree_eval(const float* __restrict__ M, int P, fl
 #ifndef HSMA_TREE_WAVES
 #define HSMA_TREE_WAVES 8
 #endif
-template <int P, bool CHECKS>
+template <int P, bool CHECKS, bool E64>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WAVES))) void k_tree_far(
     const double4* __restrict__ tgt, PartSched ps, const Group* __restrict__ cgroups,
     const CheckSched* __restrict__ csched, int cg0, int ncg, int cbase, int csplit, const Desc* __restrict__ desc,
@@ -1475,8 +1604,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
     const double4* __restrict__ tile_c, const float4* __restrict__ tile_h, const float4* __restrict__ src,
     const double4* __restrict__ pos64, const StepParams* __restrict__ sp, TreeLevels tl,
     const double4* __restrict__ node_c,
-    const double4* __restrict__ node_box, const float* __restrict__ mom, double theta, float* __restrict__ part,
+    const double4* __restrict__ node_box, const void* __restrict__ momv, double theta, float* __restrict__ part,
     long comp_stride, long slot_stride) {
+  // moments: FP32, or FP64 for the FP64 evaluation (E64)
+  const float* __restrict__ mom = (const float*)momv;
+  const double* __restrict__ mom64 = (const double*)momv;
   // the wave's target group, image entry, share and output slot
   int gi, split, img, tskip, first, count;
   long obase;
@@ -1676,8 +1808,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HSMA_TREE_WA
     // point (x, y, sigma (z - sz)): evaluate there, scale, mirror E_z
     double p;
     float gx, gy, gz;
-    tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, sg * (oz - (float)dlz), p, gx,
-              gy, gz);
+    if constexpr (E64)
+      tree_eval64(mom64 + (long)g * kTreeMomStride, pe, ptx - dlx, pty - dly, ds.sigma * (ptz - dlz), p, gx, gy,
+                  gz);
+    else
+      tree_eval(mom + (long)g * kTreeMomStride, pe, ox - (float)dlx, oy - (float)dly, sg * (oz - (float)dlz), p, gx,
+                gy, gz);
     double pd = ds.scale * p;
     gx *= sc;
     gy *= sc;
@@ -2490,16 +2626,24 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, long comp, long slot, std::s
   const TreeLevels tl = tree_;
   const int grid = CHECKS ? tree_cwaves_ : psched_.nch * psched_.ngroups;
   if (grid <= 0) return HSMA_OK;
-#define HSMA_TREE_FAR(PP)                                                                                          \
-  hipLaunchKernelGGL((k_tree_far<PP, CHECKS>), dim3(grid), dim3(64), 0, st,                                        \
+  // the slab evaluates the multipoles in FP64 (from the FP64 moments)
+  const bool e64 = host.prm.geometry == HSMA_GEOM_2D;
+  const void* momp = e64 ? (const void*)d_tmom64 : (const void*)d_tmom32;
+#define HSMA_TREE_FAR1(PP, EE)                                                                                     \
+  hipLaunchKernelGGL((k_tree_far<PP, CHECKS, EE>), dim3(grid), dim3(64), 0, st,                                    \
                      CHECKS ? (const double4*)d_check_pos : (const double4*)d_pos64, psched_,                     \
                      (const Group*)d_check_groups, (const CheckSched*)d_csched, tree_cgroup0_,                   \
                      (int)host.check_groups.size(), tree_cbase_,                                                 \
                      tree_csplit_, CHECKS ? (const Desc*)d_desc_check : (const Desc*)d_desc_part, ntiles_,         \
                      (const double4*)d_tile_c, (const float4*)d_tile_h, (const float4*)d_src32,                   \
                      (const double4*)d_pos64, (const StepParams*)d_sp, tl, (const double4*)d_tnode,               \
-                     (const double4*)d_tbox, (const float*)d_tmom32, host.prm.tree_theta,                         \
+                     (const double4*)d_tbox, momp, host.prm.tree_theta,                                           \
                      CHECKS ? (float*)d_cpart : (float*)d_part, comp, slot)
+#define HSMA_TREE_FAR(PP)                                                                                          \
+  do {                                                                                                             \
+    if (e64) HSMA_TREE_FAR1(PP, true);                                                                             \
+    else HSMA_TREE_FAR1(PP, false);                                                                                \
+  } while (0)
   switch (P) {
     case 4: HSMA_TREE_FAR(4); break;
     case 6: HSMA_TREE_FAR(6); break;
@@ -2511,6 +2655,7 @@ hsma_status DevicePlan::launch_tree(hipStream_t st, long comp, long slot, std::s
       return HSMA_ERR_INVALID_ARG;
   }
 #undef HSMA_TREE_FAR
+#undef HSMA_TREE_FAR1
   HIPCHK(hipGetLastError());
   return HSMA_OK;
 }
