@@ -97,7 +97,7 @@ def tree_roofline(workload: str, launch_ms: float):
     the share of the VALU peak: FP32 flop at 157.3 TFLOP/s plus FP64 flop
     at 78.6 TFLOP/s."""
     c = measured_valu("k_tree_far_particles", workload)
-    out = {"kernel": "k_tree_far<P,false> (treecode sums at the particles)", "bound": "alu",
+    out = {"kernel": "k_tree_far<P,false,false> (treecode sums at the particles)", "bound": "alu",
            "launch_ms": launch_ms, "peak": PEAK_FP32_TFLOPS, "fp64_peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
            "traffic": None}
     if c is None or not launch_ms:
