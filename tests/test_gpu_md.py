@@ -128,20 +128,21 @@ def cpu_nose_hoover(x, v, q, m, box, coulomb, dt, nsteps, kT, tau, slab=False, w
     return x, v, np.array(rows), np.array(nh)
 
 
-def cpu_respa(x, v, q, m, box, coulomb, dt, k, nsteps, kT=0.0, tau=0.0):
+def cpu_respa(x, v, q, m, box, coulomb, dt, k, nsteps, kT=0.0, tau=0.0, slab=False, weps=0.0, wsig=1.0):
     """Reversible RESPA on the CPU with the oracle's Coulomb forces: per
     outer step, Coulomb half kicks of dt/2 around k velocity-Verlet steps of
     dt/k under the short-range forces, optionally wrapped in the
     Nose-Hoover halves.  Rows as cpu_nose_hoover's."""
     x, v = x.copy(), v.copy()
     n = len(x)
-    nf = 3 * n - 3
+    nf = 3 * n - (2 if slab else 3)
     Q = nf * kT * tau * tau
     xi = eta = 0.0
     fc, ec = coulomb(x)
-    fl, el, wl = lj_numpy(x, box, False)
+    fl, el, wl = lj_numpy(x, box, slab, weps=weps, wsig=wsig)
     rows = []
     dti = dt / k
+    axes = 2 if slab else 3
     for _ in range(nsteps):
         s = 1.0
         if kT > 0:
@@ -150,8 +151,8 @@ def cpu_respa(x, v, q, m, box, coulomb, dt, k, nsteps, kT=0.0, tau=0.0):
         for _ in range(k):
             v = v + 0.5 * dti * fl / m[:, None]
             x = x + dti * v
-            x -= box * np.floor(x / box)
-            fl, el, wl = lj_numpy(x, box, False)
+            x[:, :axes] -= box[:axes] * np.floor(x[:, :axes] / box[:axes])
+            fl, el, wl = lj_numpy(x, box, slab, weps=weps, wsig=wsig)
             v = v + 0.5 * dti * fl / m[:, None]
         fc, ec = coulomb(x)
         v = v + 0.5 * dt * fc / m[:, None]
@@ -159,7 +160,7 @@ def cpu_respa(x, v, q, m, box, coulomb, dt, k, nsteps, kT=0.0, tau=0.0):
             xi, eta, s = nh_half(xi, eta, 0.5 * (m[:, None] * v * v).sum(), nf, kT, Q, dt)
             v = s * v
         ke = 0.5 * (m[:, None] * v * v).sum()
-        rows.append((ec, el, ke, (2 * ke + wl + ec) / (3 * box.prod())))
+        rows.append((ec, el, ke, (2 * ke + wl + (0.0 if slab else ec)) / (3 * box.prod())))
     return x, v, np.array(rows)
 
 
@@ -287,6 +288,41 @@ def test_respa_trajectory_matches_cpu(nh):
     dr = (np.abs(tg - rc) / np.abs(rc).max(0)).max()
     note(f"   nh={nh}: positions {dx:.2e} velocities {dv:.2e} rows {dr:.2e}")
     assert dx <= 1e-9 and dv <= 1e-9 and dr <= 1e-9
+
+
+def test_respa_slab_with_walls_matches_cpu():
+    """Multiple time steps between the dielectric interfaces (the slab
+    test's 100 ions, walls of sigma 0.5 among the short-range forces,
+    respa_inner = 4, NVT): 8 outer steps against the numpy integrator with
+    the oracle's slab forces (FP64, 1e-9)."""
+    import torch
+    box = np.array([10.0, 10.0, 8.0])
+    pos, q, v0, m = lattice_system((5, 5, 4), box, 31, z_lo=1.2, z_hi=6.8)
+    kc = 1.5
+    params = hs.Params(geometry=1, precision=0, p=8, K=200, F=512, lam=1.6, M=6, gamma_up=-0.5, gamma_low=0.3,
+                       nz=40, coulomb_k=kc)
+    dev = torch.device("cuda:0")
+    x, v = torch.tensor(pos, device=dev), torch.tensor(v0, device=dev)
+    f = torch.zeros_like(x)
+    qq, mm = torch.tensor(q, device=dev), torch.tensor(m, device=dev)
+    nsteps, dt, k = 8, 0.008, 4
+    th = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+    with hs.Plan(params, (0, 0, 0), box) as plan, \
+            hs.MD(plan, len(q), dt, wall_epsilon=1.0, wall_sigma=0.5, nh_kT=1.5, nh_damping=0.05,
+                  respa_inner=k) as md:
+        md.run(x, v, f, qq, mm, nsteps, thermo=th)
+        torch.cuda.synchronize()
+    xg, tg = x.cpu().numpy(), th.cpu().numpy()
+
+    def coulomb(xx):
+        r = ohsma.hsma2d(xx, q, np.zeros(3), box, 8, 200, 512, 1.6, 6, -0.5, 0.3, 40)
+        return kc * r.force, kc * r.energy
+
+    xc, vc, rc = cpu_respa(pos, v0, q, m, box, coulomb, dt, k, nsteps, 1.5, 0.05, slab=True, weps=1.0, wsig=0.5)
+    dx = min_image_diff(xg, xc, box, axes=2) / box[0]
+    dr = (np.abs(tg - rc) / np.maximum(np.abs(rc).max(0), 1e-12)).max()
+    note(f"   slab RESPA: positions {dx:.2e} rows {dr:.2e}")
+    assert dx <= 1e-9 and dr <= 1e-9
 
 
 def test_respa_energy_conservation_dt2():
