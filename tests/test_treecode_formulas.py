@@ -147,3 +147,89 @@ def test_mirror_rule():
     E_m = g * (qs[:, None] * dm / rm[:, None] ** 3).sum(0) * np.array([1, 1, -1])
     assert abs(phi_img - phi_m) < 1e-13 * abs(phi_img) + 1e-15
     assert np.abs(E_img - E_m).max() < 1e-13 * np.abs(E_img).max()
+
+
+# ---- translation to a local expansion (the cell-cell step of an FMM) ----
+# Not used by the kernels yet: the formulas a level-1 cell-cell step of the
+# treecode would use, pinned here first.
+# With M_n^m = sum_j q_j U_n^m(y_j - c_S) and D = c_T - c_S, the potential
+# at c_T + w is sum_{a,b} L_a^b conj(U_a^b(w)) with
+#   L_a^b = (-1)^a sum_{n,m} conj(M_n^m) T_{n+a}^{m+b}(D),
+# from T_k^l(x - y) = sum_{a,b} conj(U_a^b(y)) T_{k+a}^{l+b}(x) (|y| < |x|)
+# and U_a^b(-w) = (-1)^a U_a^b(w).  L_a^{-b} = (-1)^b conj(L_a^b).
+
+def m2l(M, D, P):
+    """L_a^b for 0 <= b <= a <= P from moments M (orders <= P) at D."""
+    T = irregular(2 * P + 1, D)
+    L = np.zeros((P + 1, P + 1), complex)
+    for a in range(P + 1):
+        for b in range(a + 1):
+            L[a, b] = (-1) ** a * sum(np.conj(at(M, n, m)) * at(T, n + a, m + b)
+                                      for n in range(P + 1) for m in range(-n, n + 1))
+    return L
+
+
+def l2p(L, w, P):
+    """Potential and field (-grad) of the local expansion L at c_T + w, the
+    field from dU_n^m/dz = U_{n-1}^m, (d/dx + i d/dy) U_n^m = -U_{n-1}^{m+1},
+    (d/dx - i d/dy) U_n^m = U_{n-1}^{m-1}."""
+    U = regular(P, w)
+    phi = 0.0
+    g = np.zeros(3, complex)
+    for a in range(P + 1):
+        for b in range(-a, a + 1):
+            lab = at(L, a, b)
+            phi += lab * np.conj(at(U, a, b))
+            if a >= 1:
+                dz = at(U, a - 1, b)
+                dxp, dxm = -at(U, a - 1, b + 1), at(U, a - 1, b - 1)  # (dx + i dy) U, (dx - i dy) U
+                dxu, dyu = 0.5 * (dxp + dxm), (dxp - dxm) / 2j
+                g += lab * np.conj(np.array([dxu, dyu, dz]))
+    return phi, -g
+
+
+def _sources(seed, n=40):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-0.5, 0.5, (n, 3)), rng.choice([-1.0, 1.0], n)
+
+
+def test_regular_derivative_relations():
+    """dU_n^m/dz = U_{n-1}^m, (d/dx + i d/dy) U_n^m = -U_{n-1}^{m+1},
+    (d/dx - i d/dy) U_n^m = U_{n-1}^{m-1} (central differences)."""
+    h, P = 1e-6, 7
+    v = np.array([0.3, -0.2, 0.4])
+    U = regular(P, v)
+    d = [(regular(P, v + h * e) - regular(P, v - h * e)) / (2 * h) for e in np.eye(3)]
+    for n in range(1, P + 1):
+        for m in range(n + 1):
+            assert abs(d[2][n, m] - at(U, n - 1, m)) < 1e-9
+            assert abs(d[0][n, m] + 1j * d[1][n, m] + at(U, n - 1, m + 1)) < 1e-9
+            assert abs(d[0][n, m] - 1j * d[1][n, m] - at(U, n - 1, m - 1)) < 1e-9
+
+
+def test_m2l_l2p_converge_to_direct_sums():
+    """Moments about c_S translated to a local expansion about c_T (|c_T -
+    c_S| = 4.2, both clusters of radius 0.87): potential and field at
+    targets near c_T converge to the direct sums geometrically with the
+    order; the potential is real and L_a^{-b} = (-1)^b conj(L_a^b)."""
+    y, q = _sources(3)
+    cT = np.array([3.1, -1.7, 2.2])
+    x = np.random.default_rng(4).uniform(-0.5, 0.5, (8, 3)) + cT
+    errs = []
+    for P in (6, 10, 14):
+        M = sum(qq * regular(P, yy) for yy, qq in zip(y, q))
+        L = m2l(M, cT, P)
+        T = irregular(2 * P + 1, cT)
+        lm = (-1) ** 3 * sum(np.conj(at(M, n, m)) * at(T, n + 3, m - 2) for n in range(P + 1) for m in range(-n, n + 1))
+        assert abs(lm - (-1) ** 2 * np.conj(L[3, 2])) < 1e-14
+        e = 0.0
+        for xx in x:
+            phi, fld = l2p(L, xx - cT, P)
+            d = xx - y
+            r = np.linalg.norm(d, axis=1)
+            phi_d = (q / r).sum()
+            fld_d = (q[:, None] * d / r[:, None] ** 3).sum(0)
+            assert abs(phi.imag) < 1e-12 and np.abs(fld.imag).max() < 1e-12
+            e = max(e, abs(phi.real - phi_d) / abs(phi_d), np.abs(fld.real - fld_d).max() / np.abs(fld_d).max())
+        errs.append(e)
+    assert errs[0] < 1e-3 and errs[1] < errs[0] / 50 and errs[2] < errs[1] / 50, errs
