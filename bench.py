@@ -708,6 +708,8 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="for counter runs: one 512 MiB device copy (calibration of the byte counters) "
                          "then warmup + steps of the benchmarked step, nothing else")
+    ap.add_argument("--md-only", action="store_true",
+                    help="only the MD driver measurement (for kernel traces of the MD step); prints its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -725,6 +727,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.md_only:
+        print(json.dumps({"md": md_bench(hs)}), flush=True)
+        return
     import dataclasses
     w = workloads.CONFIGS[args.workload]
     over = {k: v for k, v in (("near_rule", args.near_rule), ("p", args.p), ("K", args.K), ("F", args.F))
