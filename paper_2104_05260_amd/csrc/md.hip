@@ -25,6 +25,7 @@ struct MdBox {
 struct MdLJ {
   double eps, sig2, rc2, shift;     // pairs: 4 eps [(s/r)^12 - (s/r)^6] + shift, r < rc
   double weps, wsig, wrc, wshift;   // walls, same form in the distance d to a wall
+  float rc2_screen;                 // FP32 pre-screen: (rc + the FP32 distance error bound)^2
 };
 
 // Nose-Hoover thermostat: target kT, degrees of freedom, thermostat mass
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restr
                                                     int chunk, double* __restrict__ fpart,
                                                     double* __restrict__ part) {
   __shared__ double sx[kMdBlock], sy[kMdBlock], sz[kMdBlock];
+  __shared__ float fsx[kMdBlock], fsy[kMdBlock], fsz[kMdBlock];
   __shared__ double re[kMdBlock], rw[kMdBlock];
   const int i = blockIdx.x * kMdBlock + threadIdx.x;
   const int c = blockIdx.y;
@@ -87,6 +89,9 @@ __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restr
     yi = x[3 * i + 1];
     zi = x[3 * i + 2];
   }
+  const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
+  const float Lf0 = (float)box.L[0], Lf1 = (float)box.L[1], Lf2 = (float)box.L[2];
+  const float iLf0 = (float)box.iL[0], iLf1 = (float)box.iL[1], iLf2 = (float)box.iL[2];
   double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
   const int jb = c * chunk, je = min(n, jb + chunk);
   for (int j0 = jb; j0 < je; j0 += kMdBlock) {
@@ -96,12 +101,23 @@ __global__ __launch_bounds__(kMdBlock) void k_md_lj(int n, const double* __restr
       sx[threadIdx.x] = x[3 * j];
       sy[threadIdx.x] = x[3 * j + 1];
       sz[threadIdx.x] = x[3 * j + 2];
+      fsx[threadIdx.x] = (float)sx[threadIdx.x];
+      fsy[threadIdx.x] = (float)sy[threadIdx.x];
+      fsz[threadIdx.x] = (float)sz[threadIdx.x];
     }
     __syncthreads();
     const int jn = min(kMdBlock, je - j0);
     if (!ok) continue;
     for (int jj = 0; jj < jn; ++jj) {
       if (j0 + jj == i) continue;
+      // FP32 pre-screen: most pairs lie far beyond the cut-off; the FP64
+      // test below decides for every pair the screen lets through, and the
+      // screen's radius exceeds rc by a bound on the FP32 distance error
+      float ux = xf - fsx[jj], uy = yf - fsy[jj], uz = zf - fsz[jj];
+      ux -= Lf0 * rintf(ux * iLf0);
+      uy -= Lf1 * rintf(uy * iLf1);
+      if (!box.slab) uz -= Lf2 * rintf(uz * iLf2);
+      if (ux * ux + uy * uy + uz * uz >= lj.rc2_screen) continue;
       double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
       dx -= box.L[0] * rint(dx * box.iL[0]);
       dy -= box.L[1] * rint(dy * box.iL[1]);
@@ -565,6 +581,16 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
   md->lj.eps = p->lj_epsilon;
   md->lj.sig2 = p->lj_sigma * p->lj_sigma;
   md->lj.rc2 = rc * rc;
+  {
+    // FP32 distance error bound: positions rounded to FP32 (relative
+    // 2^-24 each), their difference, the image shift and the products, at
+    // most a few units of 2^-24 times the largest coordinate; 64 units of
+    // margin over the box's largest extent plus its lower corner
+    const double ext = std::max(std::max(L[0], L[1]), L[2]) +
+                       std::max(std::max(std::fabs(lo[0]), std::fabs(lo[1])), std::fabs(lo[2]));
+    const double rs = (rc + 64.0 * std::ldexp(1.0, -24) * ext) * (1.0 + 1e-6);
+    md->lj.rc2_screen = (float)(rs * rs) * (1.0f + 1e-6f);
+  }
   md->lj.shift = -4.0 * p->lj_epsilon * (sr6 * sr6 - sr6);
   md->lj.weps = p->wall_epsilon;
   md->lj.wsig = p->wall_sigma;
