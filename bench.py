@@ -436,8 +436,10 @@ def md_bench(hs, steps=200, warmup=20, seed=91):
     in one hsma_md_run, timed with HIP events on the driver's stream.
     Reported beside the rate: the mean kinetic temperature of the timed
     steps, the drift of the extended energy (E_C + E_LJ + E_kin + the
-    thermostat's) over them, and the peaks of the radial distribution
-    functions g_++, g_+- and g_-- over a further 1,000 steps."""
+    thermostat's) over them, the peaks of the radial distribution
+    functions g_++, g_+- and g_-- over a further 1,000 steps, and the rate
+    of two-level RESPA (Coulomb forces every 0.02 tau, short-range forces
+    every 0.01 tau) from the state reached."""
     import numpy as np
     import torch
     rng = np.random.default_rng(seed)
