@@ -75,7 +75,8 @@ typedef struct hsma_md_params {
 
 typedef struct hsma_md hsma_md;
 
-/* A driver for n particles integrated with `plan` (which must outlive it).
+/* A driver for n particles integrated with `plan` (which must outlive it);
+ * 2 <= n <= 2^26 (and within the plan's own particle limit).
  * Errors: INVALID_ARG (n, parameters, a cut-off above half a box edge),
  * OOM, DEVICE.                                                           */
 hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* params, int64_t n, hsma_md** out);
@@ -94,7 +95,7 @@ hsma_status hsma_md_forces(hsma_md* md, void* stream, const double* d_x, const d
 
 /* A driver without a plan, for steps whose Coulomb forces come from
  * elsewhere (e.g. a device request to hsma_server): geometry and box as in
- * hsma_plan_create.  hsma_md_run and hsma_md_forces need a plan and refuse
+ * hsma_plan_create; 2 <= n <= 2^26.  hsma_md_run and hsma_md_forces need a plan and refuse
  * it (INVALID_ARG); the two halves of a step below work on any driver.   */
 hsma_status hsma_md_create_for_box(const hsma_md_params* params, int geometry, const double box_lo[3],
                                    const double box_len[3], int64_t n, hsma_md** out);

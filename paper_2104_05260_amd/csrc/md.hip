@@ -16,6 +16,10 @@ namespace hsma {
 namespace {
 
 constexpr int kMdBlock = 256;
+// Largest system of one driver: the kernels index the n x 3 coordinate
+// arrays with 32-bit offsets (3 n < 2^31), and the O(n^2) pair search is
+// far past practical long before this bound.
+constexpr int64_t kMdMaxParticles = (int64_t)1 << 26;
 
 struct MdBox {
   double lo[3], L[3], iL[3];  // iL = 1 / L
@@ -532,8 +536,8 @@ hsma_status md_create(hsma_plan* plan, const hsma_md_params* p, int geometry, co
 hsma_status hsma_md_create(hsma_plan* plan, const hsma_md_params* p, int64_t n, hsma_md** out) {
   if (!plan || !p || !out) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  if (n < 2 || n > hsma::max_particles(plan->dev.host.prm.near_rule))
-    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range");
+  if (n < 2 || n > std::min(hsma::max_particles(plan->dev.host.prm.near_rule), hsma::kMdMaxParticles))
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range (2 to 2^26 particles)");
   const hsma::HostPlan& hp = plan->dev.host;
   const hsma_status s = md_create(plan, p, hp.prm.geometry, hp.lo, hp.L, n, out);
   if (s == HSMA_OK) plan->dev.use_graph = true;  // the Coulomb step replays from a captured graph
@@ -544,7 +548,8 @@ hsma_status hsma_md_create_for_box(const hsma_md_params* p, int geometry, const 
                                    const double box_len[3], int64_t n, hsma_md** out) {
   if (!p || !out || !box_lo || !box_len) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  if (n < 2 || n > ((int64_t)1 << 30) - 1) return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range");
+  if (n < 2 || n > hsma::kMdMaxParticles)
+    return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "n out of range (2 to 2^26 particles)");
   if (geometry != HSMA_GEOM_3D && geometry != HSMA_GEOM_2D)
     return hsma::set_last_error(HSMA_ERR_INVALID_ARG, "geometry must be HSMA_GEOM_3D or HSMA_GEOM_2D");
   for (int k = 0; k < 3; ++k)

@@ -92,6 +92,17 @@ def test_md_parameter_errors(bad):
     assert e.value.name == "HSMA_ERR_INVALID_ARG"
 
 
+@pytest.mark.parametrize("n", [1, (1 << 26) + 1])
+def test_md_particle_count_limits(n):
+    """A driver holds 2 to 2^26 particles (its kernels index 3 n
+    coordinates with 32-bit offsets); other counts are refused before any
+    allocation."""
+    lib_or_skip()
+    with pytest.raises(hs.HSMAError) as e:
+        hs.MD(None, n, 0.001, box_lo=[0, 0, 0], box_len=[5, 5, 5])
+    assert e.value.name == "HSMA_ERR_INVALID_ARG" and "2^26" in str(e.value)
+
+
 def test_solid_harmonics_harmonic_orthonormal_and_same_span_as_oracle():
     lib_or_skip()
     p = 8
