@@ -33,7 +33,7 @@ struct DevicePlan {
 
   // tuning of the work decomposition (the no-allocation entry point runs
   // with smaller targets so that its partial sums fit the static scratch)
-  int part_target = 524288;    // waves per particle pair launch (about; at most kMaxFarChunks per group)
+  int part_target = 4194304;   // waves per particle pair launch (about; at most kMaxFarChunks per group)
   int check_target = 2048;     // minimum waves per check pair launch (about)
   int check_target_max = 65536;
   int near_target = kNearWaves;  // near-pass waves per launch (about)

@@ -2361,8 +2361,11 @@ static PartSched part_schedule(int64_t n, int ndesc, int target, bool tree, int 
   // is a small share of the launch.  Measured against a target of 32,768
   // waves (50,000 ions: 42 chunks per group; 999,999 ions: 3): 50,000 ions
   // 21.9 -> 20.4 ms (saturated from about 170 chunks on), the slab 39.0 ->
-  // 37.7 ms, 999,999 ions 8.24 -> 7.87 s (34 chunks).  At most
-  // kMaxFarChunks per group bounds the partial slots each target writes.
+  // 37.7 ms, 999,999 ions 8.24 -> 7.87 s (34 chunks).  With the cap of
+  // kMaxFarChunks reached up to about 10^6 ions as well (1.7 MB of sources
+  // per chunk on 999,999 ions instead of 12.7), the far kernel fetches 7.6x
+  // fewer bytes there for 0.4 % less time.  The cap bounds the partial
+  // slots each target writes.
   long long want = std::max<long long>(1, (target + (long long)ps.ngroups - 1) / ps.ngroups);
   want = std::min<long long>(want, kMaxFarChunks);
   // at least 4 tiles per chunk while that leaves 4096 far waves, else at
