@@ -91,15 +91,17 @@ def measured_valu(kernel: str, workload: str):
 def tree_roofline(workload: str, launch_ms: float):
     """Position of the treecode's particle kernel (k_tree_far, the dominant
     kernel of near rule 2): its VALU flop per launch from the committed
-    counters over its live HIP-event duration.  Its work is not a fixed
-    count of pair terms (accepted nodes and opened tiles depend on the
-    configuration), so the flop count is what the kernel issued.  frac is
+    counters over its live HIP-event duration, and its HBM bytes per
+    launch from the committed FETCH_SIZE / WRITE_SIZE counters.  Its work
+    is not a fixed count of pair terms (accepted nodes and opened tiles
+    depend on the configuration), so the flop count is what the kernel
+    issued.  frac is
     the share of the VALU peak: FP32 flop at 157.3 TFLOP/s plus FP64 flop
     at 78.6 TFLOP/s."""
     c = measured_valu("k_tree_far_particles", workload)
     out = {"kernel": "k_tree_far<P,false,false> (treecode sums at the particles)", "bound": "alu",
            "launch_ms": launch_ms, "peak": PEAK_FP32_TFLOPS, "fp64_peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-           "traffic": None}
+           "traffic": measured_traffic("k_tree_far_particles", workload)}
     if c is None or not launch_ms:
         out.update({"achieved": None, "frac": None, "flop_source": "no counters for this kernel source"})
         return out
